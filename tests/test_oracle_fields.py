@@ -1,0 +1,57 @@
+"""Pins of the oracle's effective-field terms and LLG right-hand side (Eq. (1))."""
+
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import fields
+
+MU0 = 4e-7 * math.pi
+
+
+def test_uniform_m_has_no_exchange_field():
+    M = workloads.uniform_m((6, 5, 3), 8e5, (1.0, 2.0, -0.5))
+    H = fields.exchange_field(M, (1e-9, 2e-9, 3e-9), 8e5, 1.3e-11)
+    assert np.max(np.abs(H)) == 0.0
+
+
+@pytest.mark.parametrize("axis,m", [(0, 1), (0, 3), (1, 2), (2, 1)])
+def test_neumann_laplacian_cosine_eigenvectors(axis, m):
+    """cos(pi m (i + 1/2)/n) has eigenvalue -(2 - 2cos(pi m/n))/d^2 for the
+    Neumann second difference."""
+    n = (8, 6, 5)
+    cell = (2e-9, 3e-9, 4e-9)
+    Ms, A = 8e5, 1.3e-11
+    L = n[axis]
+    idx = np.arange(L)
+    prof = np.cos(math.pi * m * (idx + 0.5) / L)
+    shape = [1, 1, 1]
+    shape[2 - axis] = L
+    M = np.zeros((3, n[2], n[1], n[0]))
+    M[1] = prof.reshape(shape) * Ms
+    H = fields.exchange_field(M, cell, Ms, A)
+    lam = -(2 - 2 * math.cos(math.pi * m / L)) / cell[axis] ** 2
+    ref = 2 * A / (MU0 * Ms * Ms) * lam * M
+    assert np.max(np.abs(H - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_anisotropy_along_axis():
+    u = np.array([0.0, 0.6, 0.8])
+    M = workloads.uniform_m((2, 2, 1), 1.1e6, u)
+    H = fields.anisotropy_field(M, 1.1e6, 5e5, u)
+    ref = 2 * 5e5 / (MU0 * 1.1e6) * u
+    assert np.allclose(H[:, 0, 0, 0], ref, rtol=1e-14)
+
+
+def test_rhs_is_orthogonal_to_m_and_satisfies_gilbert_form():
+    Ms, alpha, gamma = 8e5, 0.3, 2.211e5
+    M = workloads.random_m((5, 4, 3), Ms, 7)
+    H = workloads.random_m((5, 4, 3), 1e5, 8)
+    F = fields.llg_rhs(M, H, Ms, alpha, gamma)
+    dot = np.sum(M * F, axis=0)
+    assert np.max(np.abs(dot)) <= 1e-12 * Ms * np.max(np.abs(F))
+    # Eq. (1): dM/dt = -gamma M x H + (alpha/Ms) M x dM/dt
+    rhs = -gamma * fields.cross(M, H) + (alpha / Ms) * fields.cross(M, F)
+    assert np.max(np.abs(F - rhs)) <= 1e-12 * np.max(np.abs(F))
