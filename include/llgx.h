@@ -1,0 +1,183 @@
+/*
+ * llgx — explicit finite-difference LLG micromagnetics with polynomial
+ * extrapolation of the demagnetizing field, for AMD Instinct MI355X (gfx950).
+ *
+ * Method: S. Lepadatu, "Speeding up explicit numerical evaluation methods for
+ * micromagnetic simulations using demagnetizing field polynomial
+ * extrapolation", arXiv:2107.06729.  Section and equation numbers below refer
+ * to that paper.
+ *
+ * Conventions shared by every call
+ *   - Every call returns llgx_status: LLGX_OK (0) or a negative error code.
+ *     Nothing throws across the ABI.  llgx_last_error() gives a message.
+ *   - Units are SI: cell sizes in m, Ms and fields in A/m, A in J/m, K in
+ *     J/m^3, gamma in m/(A s), times in s.  M is in A/m as in Eq. (1).
+ *   - Vector fields (M, H, dM/dt) are device arrays in structure-of-arrays
+ *     layout [3][nz][ny][nx], x fastest, of the handle's precision
+ *     (double for LLGX_F64, float for LLGX_F32), contiguous, no padding.
+ *   - Pointers named *_dev are device pointers owned by the caller; the
+ *     library never frees them and reads/writes them only during the call's
+ *     enqueued work.  Pointers named *_host are host memory.
+ *   - All device work is enqueued on the HIP stream given to llgx_create.
+ *     Calls that return host scalars (llgx_step, llgx_self_tensor, ...)
+ *     synchronise that stream.
+ *   - A handle is not thread safe: one host thread per handle.
+ */
+#ifndef LLGX_H
+#define LLGX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t llgx_status;
+#define LLGX_OK 0
+#define LLGX_E_ARG (-1)         /* bad size, parameter or null pointer        */
+#define LLGX_E_STATE (-2)       /* call not valid in the handle's state       */
+#define LLGX_E_HIP (-3)         /* HIP runtime failure (message has details)  */
+#define LLGX_E_NONFINITE (-4)   /* NaN/Inf in the error norm of a step        */
+#define LLGX_E_OOM (-5)         /* device allocation failed                   */
+#define LLGX_E_UNSUPPORTED (-6) /* valid request this build does not provide  */
+
+#define LLGX_F64 0 /* fields, FFTs and stages in double                       */
+#define LLGX_F32 1 /* fields, FFTs and stages in float (error norm in double) */
+
+#define LLGX_SPEC_NATIVE 0 /* FFT intermediates stored in the working precision */
+#define LLGX_SPEC_BF16 1   /* FFT intermediates stored as bfloat16 (F32 only)  */
+#define LLGX_SPEC_F16 2    /* FFT intermediates stored as float16 (F32 only)   */
+
+/* Explicit methods named in Sec. II (coefficients from refs. [26]-[31]). */
+#define LLGX_RK4 0    /* classic 4th order, fixed step                        */
+#define LLGX_RKF45 1  /* Fehlberg, 4th order propagated, 5th order estimate   */
+#define LLGX_RKCK45 2 /* Cash-Karp, 4th order propagated, 5th order estimate  */
+#define LLGX_RKDP54 3 /* Dormand-Prince, 5th propagated, 4th estimate, FSAL   */
+#define LLGX_HEUN 4   /* adaptive Heun, 2nd propagated, 1st estimate          */
+#define LLGX_RK23 5   /* Bogacki-Shampine, 3rd propagated, 2nd estimate, FSAL */
+#define LLGX_RKF56 6  /* Fehlberg, 5th propagated, 6th estimate, 8 stages     */
+
+#define LLGX_EXTRAP_FULL (-1)    /* exact Eq. (2) at every stage              */
+#define LLGX_EXTRAP_MATCHED (-2) /* Eq. (6) with p = the propagated order n    */
+
+/* Problem of Sec. II: mesh, cell, material, applied field (Eq. (1)). */
+typedef struct {
+    int32_t nx, ny, nz;  /* cells per axis, each >= 1                        */
+    double dx, dy, dz;   /* cell size (m), > 0                               */
+    double Ms;           /* saturation magnetization (A/m), > 0              */
+    double A;            /* exchange stiffness (J/m), >= 0                   */
+    double K;            /* uniaxial anisotropy constant (J/m^3)             */
+    double easy[3];      /* anisotropy axis (normalised by the library)      */
+    double alpha;        /* Gilbert damping, >= 0                            */
+    double gamma;        /* gyromagnetic ratio of Eq. (1), m/(A s), > 0      */
+    double Ha[3];        /* applied field (A/m), constant for t >= 0         */
+} llgx_problem;
+
+/* Stepping of Eq. (3)-(4) with the controller of Eq. (5) and the
+ * extrapolation of Eq. (6).  llgx_stepper_defaults() fills the constants the
+ * paper fixes after Eq. (5): h_min 1 fs, h_max 3 ps, c_min 0.01, c_max 2,
+ * e_max 1e-5. */
+typedef struct {
+    int32_t method;        /* LLGX_RK4 ...                                     */
+    int32_t extrap;        /* LLGX_EXTRAP_FULL, LLGX_EXTRAP_MATCHED or p 0..5  */
+    int32_t adaptive;      /* 1: Eq. (5) controller (embedded pairs only)      */
+    int32_t renormalize;   /* 1: rescale |M| to Ms after every accepted step   */
+    int32_t exponent_mode; /* Eq. (5) exponent: 0 -> 1/(min(n,n^)+1), 1 -> 1/(n+1) */
+    double h;              /* step (fixed) or first trial step (adaptive), s   */
+    double h_min, h_max, c_min, c_max, e_max;
+} llgx_stepper;
+
+typedef struct {
+    double t;              /* time after the step                               */
+    double h_used;         /* accepted step                                     */
+    double h_next;         /* next step proposed by Eq. (5) (= h if fixed)      */
+    double err;            /* e of Sec. II: max over cells |h sum (c-c^) F|/Ms  */
+    int32_t rejected;      /* rejected attempts before acceptance               */
+    int32_t exact_evals;   /* Eq. (2) evaluations in this step                  */
+    int32_t extrap_evals;  /* Eq. (6) evaluations in this step                  */
+    int32_t forced;        /* 1 if accepted at h_min with err > e_max           */
+} llgx_step_info;
+
+typedef struct llgx_ctx* llgx_handle;
+
+/* Message of the last error on h (owned by h, valid until the next call on
+ * it); with h == NULL the message of the last failed llgx_create. */
+const char* llgx_last_error(llgx_handle h);
+
+/* Fill s with the Sec. II controller constants, method RK4, full demag,
+ * h = 1e-13 s, fixed step, no renormalisation. */
+void llgx_stepper_defaults(llgx_stepper* s);
+
+/* Create a handle for problem p (copied).  precision: LLGX_F64/LLGX_F32;
+ * spectral: LLGX_SPEC_* (16-bit storage requires LLGX_F32).  hip_stream: the
+ * hipStream_t all work is enqueued on (NULL = default stream).  Allocates
+ * the device workspace (state, stage buffers, extrapolation history, FFT
+ * buffers, k-space kernel).  Errors: LLGX_E_ARG, LLGX_E_OOM, LLGX_E_HIP. */
+llgx_status llgx_create(const llgx_problem* p, int32_t precision, int32_t spectral,
+                        void* hip_stream, llgx_handle* out);
+void llgx_destroy(llgx_handle h);
+
+/* Sec. II, Eq. (2) and ref. [24]: compute the demagnetizing tensor N for
+ * all cell offsets on the GPU in double precision (exact Newell form near,
+ * moment expansion far), transform it with the library's FFT passes in
+ * double, and store the real k-space kernel in the working precision.
+ * Idempotent.  Must precede any field or step call (else LLGX_E_STATE). */
+llgx_status llgx_precompute_demag(llgx_handle h);
+
+/* Use a caller-supplied real-space tensor instead of llgx_precompute_demag.
+ * N_host: double[6][2nz-1][2ny-1][2nx-1], components (xx,yy,zz,xy,xz,yz),
+ * index [c][dz+nz-1][dy+ny-1][dx+nx-1] for offset (dx,dy,dz) in cells; it
+ * must be even under (dx,dy,dz) -> -(dx,dy,dz).  The self term N00 used by
+ * Eq. (6) is read from offset 0. */
+llgx_status llgx_set_demag_tensor(llgx_handle h, const double* N_host);
+
+/* Copy the real-space tensor computed by llgx_precompute_demag for offsets
+ * 0..n-1 per axis: double[6][nz][ny][nx] (host). */
+llgx_status llgx_get_demag_tensor(llgx_handle h, double* N_host);
+
+/* N00 of Eq. (6): diagonal of the self term N(0). Synchronises. */
+llgx_status llgx_self_tensor(llgx_handle h, double n00[3]);
+
+/* Current magnetization (copied; the history of Eq. (6) is invalidated and
+ * priming restarts; t is kept). */
+llgx_status llgx_set_m(llgx_handle h, const void* M_dev);
+llgx_status llgx_get_m(llgx_handle h, void* M_dev);
+
+/* One exact evaluation of Eq. (2): H_dev = -sum_r N(r - r0) M(r). */
+llgx_status llgx_demag(llgx_handle h, const void* M_dev, void* H_dev);
+/* Effective field H_a + H_d + H_ex + H_an at M (terms named under Eq. (1)). */
+llgx_status llgx_heff(llgx_handle h, const void* M_dev, void* H_dev);
+/* F(t, M) of Eq. (1) in explicit Landau-Lifshitz form, exact demag. */
+llgx_status llgx_rhs(llgx_handle h, const void* M_dev, void* F_dev);
+
+/* One accepted step of Eq. (3)-(4) from the handle's (t, M).  With
+ * s->adaptive the Eq. (5) controller repeats rejected attempts and the next
+ * call starts from info->h_next; otherwise s->h is used.  A change of method
+ * or extrap between calls restarts priming.  Synchronises once per attempt
+ * when adaptive (to read e), else not at all.  Errors: LLGX_E_ARG,
+ * LLGX_E_STATE, LLGX_E_NONFINITE, LLGX_E_HIP. */
+llgx_status llgx_step(llgx_handle h, const llgx_stepper* s, llgx_step_info* info);
+
+/* nsteps fixed steps (s->adaptive must be 0) with no host synchronisation;
+ * with use_graph the steady-state step is captured once per history phase
+ * into HIP graphs and replayed.  info may be NULL. */
+llgx_status llgx_run_fixed(llgx_handle h, const llgx_stepper* s, int64_t nsteps, int32_t use_graph,
+                           llgx_step_info* info);
+
+/* Step until t_end, recording the mesh-averaged M every sample_dt into
+ * mavg_host (double[cap][3]); adaptive steps are shortened to land on sample
+ * times.  *nsamples receives the count written (including t = start). */
+llgx_status llgx_run(llgx_handle h, const llgx_stepper* s, double t_end, double sample_dt,
+                     double* mavg_host, int64_t cap, int64_t* nsamples);
+
+/* Time, proposed next step and counters of the handle. */
+llgx_status llgx_get_time(llgx_handle h, double* t, double* h_next);
+llgx_status llgx_set_time(llgx_handle h, double t);
+llgx_status llgx_counters(llgx_handle h, int64_t out[5]); /* exact, extrap, accepted, rejected, forced */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LLGX_H */

@@ -1,0 +1,266 @@
+"""Python binding of libllgx (include/llgx.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts Python
+values to the C structs, passes torch device pointers and the current HIP
+stream, and turns status codes into exceptions.  Importing it without the
+built library raises ImportError (build with ``python -m
+paper_2107_06729_amd.build_lib``).
+
+Names mirror the C ABI without the ``llgx_`` prefix; ``Sim`` bundles a handle.
+"""
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libllgx.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libllgx.so not built at {LIB_PATH}; run python -m paper_2107_06729_amd.build_lib")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, E_ARG, E_STATE, E_HIP, E_NONFINITE, E_OOM, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+F64, F32 = 0, 1
+SPEC_NATIVE, SPEC_BF16, SPEC_F16 = 0, 1, 2
+METHODS = {"RK4": 0, "RKF45": 1, "RKCK45": 2, "RKDP54": 3, "HEUN": 4, "RK23": 5, "RKF56": 6}
+EXTRAP_FULL, EXTRAP_MATCHED = -1, -2
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("Ms", ctypes.c_double), ("A", ctypes.c_double), ("K", ctypes.c_double),
+                ("easy", ctypes.c_double * 3), ("alpha", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("Ha", ctypes.c_double * 3)]
+
+
+class Stepper(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("extrap", ctypes.c_int32), ("adaptive", ctypes.c_int32),
+                ("renormalize", ctypes.c_int32), ("exponent_mode", ctypes.c_int32),
+                ("h", ctypes.c_double), ("h_min", ctypes.c_double), ("h_max", ctypes.c_double),
+                ("c_min", ctypes.c_double), ("c_max", ctypes.c_double), ("e_max", ctypes.c_double)]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("h_used", ctypes.c_double), ("h_next", ctypes.c_double),
+                ("err", ctypes.c_double), ("rejected", ctypes.c_int32), ("exact_evals", ctypes.c_int32),
+                ("extrap_evals", ctypes.c_int32), ("forced", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_H = ctypes.c_void_p
+_P = ctypes.c_void_p
+_S = ctypes.c_int32
+_sig = {
+    "llgx_last_error": (ctypes.c_char_p, [_H]),
+    "llgx_stepper_defaults": (None, [ctypes.POINTER(Stepper)]),
+    "llgx_create": (_S, [ctypes.POINTER(Problem), ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(_H)]),
+    "llgx_destroy": (None, [_H]),
+    "llgx_precompute_demag": (_S, [_H]),
+    "llgx_set_demag_tensor": (_S, [_H, _P]),
+    "llgx_get_demag_tensor": (_S, [_H, _P]),
+    "llgx_self_tensor": (_S, [_H, ctypes.POINTER(ctypes.c_double)]),
+    "llgx_set_m": (_S, [_H, _P]),
+    "llgx_get_m": (_S, [_H, _P]),
+    "llgx_demag": (_S, [_H, _P, _P]),
+    "llgx_heff": (_S, [_H, _P, _P]),
+    "llgx_rhs": (_S, [_H, _P, _P]),
+    "llgx_step": (_S, [_H, ctypes.POINTER(Stepper), ctypes.POINTER(StepInfo)]),
+    "llgx_run_fixed": (_S, [_H, ctypes.POINTER(Stepper), ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(StepInfo)]),
+    "llgx_run": (_S, [_H, ctypes.POINTER(Stepper), ctypes.c_double, ctypes.c_double, _P, ctypes.c_int64,
+                      ctypes.POINTER(ctypes.c_int64)]),
+    "llgx_get_time": (_S, [_H, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "llgx_set_time": (_S, [_H, ctypes.c_double]),
+    "llgx_counters": (_S, [_H, ctypes.POINTER(ctypes.c_int64)]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+class LlgxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"llgx error {code}: {msg}")
+        self.code = code
+
+
+def _check(code, handle):
+    if code != OK:
+        msg = _lib.llgx_last_error(handle)
+        raise LlgxError(code, msg.decode() if msg else "")
+
+
+def make_problem(p):
+    """Problem struct from a dict with keys n, cell, Ms, A, K, easy, alpha, gamma, Ha."""
+    s = Problem()
+    s.nx, s.ny, s.nz = (int(v) for v in p["n"])
+    s.dx, s.dy, s.dz = (float(v) for v in p["cell"])
+    s.Ms, s.A, s.K = float(p["Ms"]), float(p["A"]), float(p.get("K", 0.0))
+    s.easy[:] = [float(v) for v in p.get("easy", (0.0, 0.0, 1.0))]
+    s.alpha, s.gamma = float(p["alpha"]), float(p.get("gamma", 2.211e5))
+    s.Ha[:] = [float(v) for v in p.get("Ha", (0.0, 0.0, 0.0))]
+    return s
+
+
+def stepper_defaults():
+    s = Stepper()
+    _lib.llgx_stepper_defaults(ctypes.byref(s))
+    return s
+
+
+def make_stepper(method="RK4", extrap=None, h=1e-13, adaptive=False, renormalize=False, exponent_mode=0, **kw):
+    s = stepper_defaults()
+    s.method = METHODS[method] if isinstance(method, str) else int(method)
+    if extrap is None:
+        s.extrap = EXTRAP_FULL
+    elif extrap == "matched":
+        s.extrap = EXTRAP_MATCHED
+    else:
+        s.extrap = int(extrap)
+    s.h = float(h)
+    s.adaptive = int(bool(adaptive))
+    s.renormalize = int(bool(renormalize))
+    s.exponent_mode = int(exponent_mode)
+    for k, v in kw.items():
+        setattr(s, k, float(v))
+    return s
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Sim:
+    """One handle: a problem on one GPU in one precision, on one HIP stream."""
+
+    def __init__(self, problem, precision="f32", spectral=SPEC_NATIVE, stream=None, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.problem = problem
+        self.prec = F32 if precision in ("f32", F32) else F64
+        self.dtype = torch.float32 if self.prec == F32 else torch.float64
+        self.n = tuple(int(v) for v in problem["n"])
+        self.stream = stream
+        with torch.cuda.device(self.device):
+            self._h = _H()
+            _check(_lib.llgx_create(ctypes.byref(make_problem(problem)), self.prec, int(spectral),
+                                    _stream_ptr(stream), ctypes.byref(self._h)), None)
+
+    @property
+    def shape(self):
+        nx, ny, nz = self.n
+        return (3, nz, ny, nx)
+
+    def _dev(self, t):
+        t = self.torch.as_tensor(t)
+        if t.device != self.device or t.dtype != self.dtype:
+            t = t.to(device=self.device, dtype=self.dtype)
+        t = t.contiguous()
+        if tuple(t.shape) != self.shape:
+            raise ValueError(f"expected shape {self.shape}, got {tuple(t.shape)}")
+        return t
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.llgx_destroy(self._h)
+            self._h = _H()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def precompute_demag(self):
+        _check(_lib.llgx_precompute_demag(self._h), self._h)
+
+    def set_demag_tensor(self, Nfull):
+        import numpy as np
+        a = np.ascontiguousarray(Nfull, dtype=np.float64)
+        nx, ny, nz = self.n
+        if a.shape != (6, 2 * nz - 1, 2 * ny - 1, 2 * nx - 1):
+            raise ValueError("tensor shape must be (6, 2nz-1, 2ny-1, 2nx-1)")
+        _check(_lib.llgx_set_demag_tensor(self._h, a.ctypes.data_as(ctypes.c_void_p)), self._h)
+
+    def get_demag_tensor(self):
+        import numpy as np
+        nx, ny, nz = self.n
+        out = np.empty((6, nz, ny, nx))
+        _check(_lib.llgx_get_demag_tensor(self._h, out.ctypes.data_as(ctypes.c_void_p)), self._h)
+        return out
+
+    def self_tensor(self):
+        out = (ctypes.c_double * 3)()
+        _check(_lib.llgx_self_tensor(self._h, out), self._h)
+        return list(out)
+
+    def set_m(self, M):
+        M = self._dev(M)
+        _check(_lib.llgx_set_m(self._h, ctypes.c_void_p(M.data_ptr())), self._h)
+        self._keep = M  # the copy is enqueued: keep the source alive until the stream passes it
+
+    def get_m(self):
+        out = self.torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        _check(_lib.llgx_get_m(self._h, ctypes.c_void_p(out.data_ptr())), self._h)
+        return out
+
+    def _field(self, fn, M):
+        M = self._dev(M)
+        out = self.torch.empty_like(M)
+        _check(fn(self._h, ctypes.c_void_p(M.data_ptr()), ctypes.c_void_p(out.data_ptr())), self._h)
+        self._keep = M
+        return out
+
+    def demag(self, M):
+        return self._field(_lib.llgx_demag, M)
+
+    def heff(self, M):
+        return self._field(_lib.llgx_heff, M)
+
+    def rhs(self, M):
+        return self._field(_lib.llgx_rhs, M)
+
+    def step(self, stepper):
+        info = StepInfo()
+        _check(_lib.llgx_step(self._h, ctypes.byref(stepper), ctypes.byref(info)), self._h)
+        return info.as_dict()
+
+    def run_fixed(self, stepper, nsteps, use_graph=True):
+        info = StepInfo()
+        _check(_lib.llgx_run_fixed(self._h, ctypes.byref(stepper), int(nsteps), int(bool(use_graph)),
+                                   ctypes.byref(info)), self._h)
+        return info.as_dict()
+
+    def run(self, stepper, t_end, sample_dt, cap=None):
+        import numpy as np
+        t, _ = self.time()
+        if cap is None:
+            cap = int((t_end - t) / sample_dt) + 3 if sample_dt > 0 else 0
+        out = np.zeros((max(cap, 1), 3))
+        ns = ctypes.c_int64(0)
+        _check(_lib.llgx_run(self._h, ctypes.byref(stepper), float(t_end), float(sample_dt),
+                             out.ctypes.data_as(ctypes.c_void_p), int(cap), ctypes.byref(ns)), self._h)
+        return out[:ns.value]
+
+    def time(self):
+        t, h = ctypes.c_double(), ctypes.c_double()
+        _check(_lib.llgx_get_time(self._h, ctypes.byref(t), ctypes.byref(h)), self._h)
+        return t.value, h.value
+
+    def set_time(self, t):
+        _check(_lib.llgx_set_time(self._h, float(t)), self._h)
+
+    def counters(self):
+        out = (ctypes.c_int64 * 5)()
+        _check(_lib.llgx_counters(self._h, out), self._h)
+        return dict(zip(("exact", "extrap", "accepted", "rejected", "forced"), list(out)))

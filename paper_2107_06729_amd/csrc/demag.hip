@@ -1,0 +1,634 @@
+// Eq. (2) of the paper by zero-padded FFT convolution, and the setup of its
+// demagnetizing tensor (Sec. II, ref. [24]), for gfx950.
+//
+// Data layout (complex elements, working precision T):
+//   spectrum buffers are [comp][z][y][kx] with row stride SX >= Kx, where
+//   Kx = Px/2 + 1 columns of the real-to-complex x transform (1 if Px = 1).
+// Pass chain of one evaluation (5 kernels; fewer when an axis has length 1):
+//   xfwd  : stage combination M_k = M0 + sum h b F (Eq. 4), real->complex x FFT
+//   colfft: y forward (rows y >= ny are the zero padding, never loaded)
+//   zmul  : z forward, H = -N^ M with the 6-component symmetric k-space
+//           kernel, z inverse (only z < nz rows are loaded and stored)
+//   colfft: y inverse (only y < ny rows stored)
+//   xinv  : complex->real x FFT (x < nx kept) fused with H_eff and the LLG
+//           right-hand side (Eq. 1), or writing H_d / H_eff alone.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels.hpp"
+#include "physics.hpp"
+
+namespace llgx {
+
+constexpr int NT = 256;
+
+// ------------------------------------------------------------------------
+// tile choices (LDS budget per workgroup)
+template <typename T>
+constexpr int col_tile(int L) {
+    return sizeof(T) == 4 ? (L <= 512 ? 16 : 8) : (L <= 512 ? 8 : 4);
+}
+template <typename T>
+constexpr int zmul_tile(int L) {
+    return sizeof(T) == 4 ? (L <= 128 ? 16 : L == 256 ? 8 : L == 512 ? 4 : L == 1024 ? 2 : 1)
+                          : (L <= 128 ? 8 : L == 256 ? 4 : L == 512 ? 2 : 1);
+}
+template <typename T>
+constexpr int xfwd_rows(int LX) {
+    const int r = (sizeof(T) == 4 ? 2048 : 1024) / (LX > 0 ? LX : 1);
+    return r < 1 ? 1 : (r > 16 ? 16 : r);
+}
+template <typename T>
+constexpr int xinv_rows(int LX) {
+    const int r = (sizeof(T) == 4 ? 1024 : 512) / (LX > 0 ? LX : 1);
+    return r < 1 ? 1 : (r > 8 ? 8 : r);
+}
+
+template <typename T>
+__device__ __forceinline__ T combo_at(const Combo<T>& c, long i) {
+    T v = c.base[i];
+    for (int l = 0; l < c.nf; ++l) v += c.coef[l] * c.f[l][i];
+    return v;
+}
+
+// ------------------------------------------------------------------------
+// forward x pass: real rows of length nin (zero padded to 2 LX) -> LX+1 complex
+// A real sequence of length P = 2 LX is packed as z[j] = x[2j] + i x[2j+1],
+// transformed with a length-LX complex FFT and split with
+//   X[k] = (Z[k] + Z*[LX-k])/2 - i e^{-2 pi i k/P} (Z[k] - Z*[LX-k])/2.
+template <typename T, int LX, int ROWS>
+__global__ __launch_bounds__(NT) void k_xfwd(Combo<T> in, T* __restrict__ mk_out, int nin, long nrows,
+                                             cx<T>* __restrict__ spec, int SX, const cx<T>* __restrict__ twL,
+                                             const cx<T>* __restrict__ twP) {
+    using C = cx<T>;
+    const long row0 = (long)blockIdx.x * ROWS;
+    if constexpr (LX == 0) {
+        for (int r = threadIdx.x; r < ROWS; r += NT) {
+            const long g = row0 + r;
+            if (g < nrows) {
+                const T v = combo_at(in, g);
+                if (mk_out) mk_out[g] = v;
+                spec[g * SX] = C{v, T(0)};
+            }
+        }
+        return;
+    } else {
+        constexpr int CS = LX + 1;
+        __shared__ C buf[ROWS * CS];
+        for (int e = threadIdx.x; e < ROWS * LX; e += NT) {
+            const int r = e / LX, i = e - r * LX;
+            const long g = row0 + r;
+            C v{T(0), T(0)};
+            if (g < nrows) {
+                const long off = g * nin;
+                const int x0 = 2 * i;
+                if (x0 < nin) {
+                    v.x = combo_at(in, off + x0);
+                    if (mk_out) mk_out[off + x0] = v.x;
+                }
+                if (x0 + 1 < nin) {
+                    v.y = combo_at(in, off + x0 + 1);
+                    if (mk_out) mk_out[off + x0 + 1] = v.y;
+                }
+            }
+            buf[r * CS + i] = v;
+        }
+        __syncthreads();
+        lds_fft<T, LX, false, Cols<ROWS, CS, 1, false>, NT>(buf, twL);
+        for (int e = threadIdx.x; e < ROWS * (LX + 1); e += NT) {
+            const int r = e / (LX + 1), k = e - r * (LX + 1);
+            const long g = row0 + r;
+            if (g >= nrows) continue;
+            const C zk = buf[r * CS + (k & (LX - 1))];
+            const C zc = cconj(buf[r * CS + ((LX - k) & (LX - 1))]);
+            const C E{(zk.x + zc.x) * T(0.5), (zk.y + zc.y) * T(0.5)};
+            const C O{(zk.y - zc.y) * T(0.5), (zc.x - zk.x) * T(0.5)};  // -i (zk - zc)/2
+            spec[g * SX + k] = cadd(E, cmul(O, twP[k]));
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// inverse x pass: LX+1 complex -> real, keep x < nx; then per cell
+//   Z[k] = (X[k] + X*[LX-k]) + i e^{+2 pi i k/P} (X[k] - X*[LX-k]),
+//   z = IDFT_LX(Z), x[2j] = Re z[j], x[2j+1] = Im z[j].
+template <typename T, int LX, int ROWS, int MODE>
+__global__ __launch_bounds__(NT) void k_xinv(const cx<T>* __restrict__ spec, int SX, const T* __restrict__ M,
+                                             Phys<T> ph, XinvOut out, const cx<T>* __restrict__ twL,
+                                             const cx<T>* __restrict__ twP) {
+    using C = cx<T>;
+    constexpr int LXE = LX > 0 ? LX : 1;
+    constexpr int CS = LXE + 1;
+    __shared__ C buf[3 * ROWS * CS];
+    const long nrow = (long)ph.ny * ph.nz;
+    const long N = nrow * ph.nx;
+    const long row0 = (long)blockIdx.x * ROWS;
+    if constexpr (LX == 0) {
+        for (int lr = threadIdx.x; lr < 3 * ROWS; lr += NT) {
+            const int r = lr / 3, c = lr - 3 * r;
+            const long g = row0 + r;
+            if (g < nrow) buf[lr * CS] = spec[(c * nrow + g) * SX];
+        }
+        __syncthreads();
+    } else {
+        for (int e = threadIdx.x; e < 3 * ROWS * LX; e += NT) {
+            const int lr = e / LX, k = e - lr * LX;
+            const int r = lr / 3, c = lr - 3 * r;
+            const long g = row0 + r;
+            C Z{T(0), T(0)};
+            if (g < nrow) {
+                const cx<T>* row = spec + (c * nrow + g) * SX;
+                const C xk = row[k];
+                const C xc = cconj(row[LX - k]);
+                const C S = cadd(xk, xc);
+                const C wd = cmulc(csub(xk, xc), twP[k]);
+                Z = C{S.x - wd.y, S.y + wd.x};
+            }
+            buf[lr * CS + k] = Z;
+        }
+        __syncthreads();
+        lds_fft<T, LX, true, Cols<3 * ROWS, CS, 1, false>, NT>(buf, twL);
+    }
+    const int nx = ph.nx;
+    for (int e = threadIdx.x; e < ROWS * nx; e += NT) {
+        const int r = e / nx, x = e - r * nx;
+        const long g = row0 + r;
+        if (g >= nrow) continue;
+        T hd[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const C v = buf[(3 * r + c) * CS + (LX > 0 ? (x >> 1) : 0)];
+            hd[c] = (x & 1) ? v.y : v.x;
+        }
+        const long cell = g * nx + x;
+        if constexpr (MODE == XINV_DEMAG) {
+            T* H = (T*)out.h;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) H[c * N + cell] = hd[c];
+        } else {
+            const int y = (int)(g % ph.ny), z = (int)(g / ph.ny);
+            T m[3], H[3];
+            heff_at(M, N, cell, x, y, z, ph, hd, m, H);
+            if constexpr (MODE == XINV_HEFF) {
+                T* Ho = (T*)out.h;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) Ho[c * N + cell] = H[c];
+            } else {
+                T F[3];
+                llg_at(m, H, ph, F);
+                T* Fo = (T*)out.f;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) Fo[c * N + cell] = F[c];
+                if (out.g) {
+                    T* G = (T*)out.g;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) G[c * N + cell] = hd[c] + ph.n00[c] * m[c];
+                }
+                if (out.h) {
+                    T* Ho = (T*)out.h;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) Ho[c * N + cell] = hd[c];
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// strided column FFT: element (comp, outer, i, kx) at comp*cs + outer*os + i*is + kx
+template <typename T, int L, bool INV, int TK>
+__global__ __launch_bounds__(NT) void k_colfft(const cx<T>* __restrict__ src, long s_cs, long s_os, long s_is,
+                                               int n_in, cx<T>* __restrict__ dst, long d_cs, long d_os, long d_is,
+                                               int n_out, int Kx, const cx<T>* __restrict__ tw) {
+    using C = cx<T>;
+    __shared__ C buf[L * TK];
+    const int kx0 = blockIdx.x * TK;
+    const cx<T>* sp = src + blockIdx.z * s_cs + blockIdx.y * s_os + kx0;
+    for (int e = threadIdx.x; e < L * TK; e += NT) {
+        const int i = e / TK, col = e - i * TK;
+        C v{T(0), T(0)};
+        if (i < n_in && kx0 + col < Kx) v = sp[i * s_is + col];
+        buf[e] = v;
+    }
+    __syncthreads();
+    lds_fft<T, L, INV, Cols<TK, 1, TK, true>, NT>(buf, tw);
+    cx<T>* dp = dst + blockIdx.z * d_cs + blockIdx.y * d_os + kx0;
+    for (int e = threadIdx.x; e < n_out * TK; e += NT) {
+        const int i = e / TK, col = e - i * TK;
+        if (kx0 + col < Kx) dp[i * d_is + col] = buf[e];
+    }
+}
+
+// ------------------------------------------------------------------------
+// z forward, k-space product H^ = K^ M^ (K^ = -N^/(Px Py Pz), real and
+// symmetric, stored for |ky| <= Py/2, |kz| <= Pz/2; the components odd in y
+// (xy, yz) change sign for ky > Py/2, those odd in z (xz, yz) for kz > Pz/2),
+// z inverse.  In place on rows z < nz of the [3][nz][nyrows][SX] buffer.
+template <typename T, int LZ, int TK>
+__global__ __launch_bounds__(NT) void k_zmul(cx<T>* __restrict__ buf, int SX, int Kx, int nz, int nyrows, int Py,
+                                             int Pz, const T* __restrict__ kfold, int Kyf, int Kzf,
+                                             const cx<T>* __restrict__ tw) {
+    using C = cx<T>;
+    constexpr int NC = 3 * TK;
+    __shared__ C lb[LZ * NC];
+    const int kx0 = blockIdx.x * TK;
+    const int ky = blockIdx.y;
+    const long cs = (long)nz * nyrows * SX, zs = (long)nyrows * SX;
+    cx<T>* bp = buf + (long)ky * SX + kx0;
+    for (int e = threadIdx.x; e < LZ * NC; e += NT) {
+        const int z = e / NC, cc = e - z * NC;
+        const int c = cc / TK, col = cc - c * TK;
+        C v{T(0), T(0)};
+        if (z < nz && kx0 + col < Kx) v = bp[c * cs + z * zs + col];
+        lb[e] = v;
+    }
+    __syncthreads();
+    lds_fft<T, LZ, false, Cols<NC, 1, NC, true>, NT>(lb, tw);
+    const int kyf = (2 * ky <= Py) ? ky : Py - ky;
+    const T sy = (2 * ky > Py) ? T(-1) : T(1);
+    const long kcs = (long)Kzf * Kyf * SX;
+    for (int e = threadIdx.x; e < LZ * TK; e += NT) {
+        const int kz = e / TK, col = e - kz * TK;
+        const int kx = kx0 + col;
+        if (kx >= Kx) continue;
+        const int kzf = (2 * kz <= Pz) ? kz : Pz - kz;
+        const T sz = (2 * kz > Pz) ? T(-1) : T(1);
+        const T* kp = kfold + ((long)kzf * Kyf + kyf) * SX + kx;
+        const T nxx = kp[0], nyy = kp[kcs], nzz = kp[2 * kcs];
+        const T nxy = sy * kp[3 * kcs], nxz = sz * kp[4 * kcs], nyz = sy * sz * kp[5 * kcs];
+        C* p = lb + kz * NC + col;
+        const C mx = p[0], my = p[TK], mz = p[2 * TK];
+        p[0] = C{nxx * mx.x + nxy * my.x + nxz * mz.x, nxx * mx.y + nxy * my.y + nxz * mz.y};
+        p[TK] = C{nxy * mx.x + nyy * my.x + nyz * mz.x, nxy * mx.y + nyy * my.y + nyz * mz.y};
+        p[2 * TK] = C{nxz * mx.x + nyz * my.x + nzz * mz.x, nxz * mx.y + nyz * my.y + nzz * mz.y};
+    }
+    __syncthreads();
+    lds_fft<T, LZ, true, Cols<NC, 1, NC, true>, NT>(lb, tw);
+    for (int e = threadIdx.x; e < nz * NC; e += NT) {
+        const int z = e / NC, cc = e - z * NC;
+        const int c = cc / TK, col = cc - c * TK;
+        if (kx0 + col < Kx) bp[c * cs + z * zs + col] = lb[e];
+    }
+}
+
+// ------------------------------------------------------------------------
+// Newell tensor (ref. [24]) in double precision.
+// f and g are evaluated on |x|,|y|,|z|; g carries sign(x) sign(y).
+__device__ double newell_f(double x, double y, double z) {
+    x = fabs(x);
+    y = fabs(y);
+    z = fabs(z);
+    const double x2 = x * x, y2 = y * y, z2 = z * z;
+    const double R = sqrt(x2 + y2 + z2);
+    double t = (2.0 * x2 - y2 - z2) * R / 6.0;
+    const double rxz = sqrt(x2 + z2), rxy = sqrt(x2 + y2);
+    if (y > 0.0 && rxz > 0.0) t += 0.5 * y * (z2 - x2) * asinh(y / rxz);
+    if (z > 0.0 && rxy > 0.0) t += 0.5 * z * (y2 - x2) * asinh(z / rxy);
+    if (x > 0.0 && y > 0.0 && z > 0.0) t -= x * y * z * atan(y * z / (x * R));
+    return t;
+}
+
+__device__ double newell_g(double x, double y, double z) {
+    if (x == 0.0 || y == 0.0) return 0.0;
+    const double sgn = ((x < 0.0) != (y < 0.0)) ? -1.0 : 1.0;
+    x = fabs(x);
+    y = fabs(y);
+    z = fabs(z);
+    const double x2 = x * x, y2 = y * y, z2 = z * z;
+    const double R = sqrt(x2 + y2 + z2);
+    double t = -x * y * R / 3.0;
+    if (z > 0.0) {
+        t += x * y * z * asinh(z / sqrt(x2 + y2));
+        t -= z2 * z / 6.0 * atan(x * y / (z * R));
+        t -= 0.5 * z * y2 * atan(x * z / (y * R));
+        t -= 0.5 * z * x2 * atan(y * z / (x * R));
+    }
+    t += y / 6.0 * (3.0 * z2 - y2) * asinh(x / sqrt(y2 + z2));
+    t += x / 6.0 * (3.0 * z2 - x2) * asinh(y / sqrt(x2 + z2));
+    return sgn * t;
+}
+
+// 27-point second difference (weights 2, -1, -1 per axis) of the six
+// component functions, /(4 pi dx dy dz)
+__device__ void newell_exact(double X, double Y, double Z, double dx, double dy, double dz, double N[6]) {
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int a = -1; a <= 1; ++a) {
+        const double wa = a == 0 ? 2.0 : -1.0;
+        const double x = X + a * dx;
+        for (int b = -1; b <= 1; ++b) {
+            const double wb = b == 0 ? 2.0 : -1.0;
+            const double y = Y + b * dy;
+            for (int c = -1; c <= 1; ++c) {
+                const double w = wa * wb * (c == 0 ? 2.0 : -1.0);
+                const double z = Z + c * dz;
+                acc[0] += w * newell_f(x, y, z);
+                acc[1] += w * newell_f(y, x, z);
+                acc[2] += w * newell_f(z, y, x);
+                acc[3] += w * newell_g(x, y, z);
+                acc[4] += w * newell_g(x, z, y);
+                acc[5] += w * newell_g(y, z, x);
+            }
+        }
+    }
+    const double s = 1.0 / (4.0 * M_PI * dx * dy * dz);
+    for (int i = 0; i < 6; ++i) N[i] = acc[i] * s;
+}
+
+// Far field: moment expansion of the cell-pair tensor,
+//   N_ij(R) = -(V/4 pi) sum_gamma m_gamma D^(gamma+e_i+e_j) (1/r),
+//   m_gamma = prod_a 2 d_a^g_a/(g_a+2)!  (even g_a, |gamma| <= 2K),
+// with D^k(1/r) = k! a_k and the Taylor coefficients a_k of 1/r generated
+// layer by layer (|k| = n) from
+//   n r^2 a_k = -(2n-1) sum_i x_i a_{k-e_i} - (n-1) sum_i a_{k-2e_i}.
+constexpr int FAR_K = 6;
+constexpr int FAR_N = 2 * FAR_K + 2;
+constexpr double FAR_SWITCH = 6.0;  // far form for R >= FAR_SWITCH * max(dx,dy,dz)
+
+__device__ __forceinline__ int lidx(int n, int i, int j) { return i * (n + 1) - (i * (i - 1)) / 2 + j; }
+
+__device__ void newell_far(double X, double Y, double Z, double dx, double dy, double dz, double N[6]) {
+    constexpr int LMAX = (FAR_N + 1) * (FAR_N + 2) / 2;
+    double lay[3][LMAX];  // layers n-2, n-1, n (rotating)
+    double fact[FAR_N + 1];
+    fact[0] = 1.0;
+    for (int i = 1; i <= FAR_N; ++i) fact[i] = fact[i - 1] * i;
+    double pm[3][FAR_K + 1];  // 2 d^(2q)/(2q+2)!
+    const double d[3] = {dx, dy, dz};
+    for (int a = 0; a < 3; ++a) {
+        double p = 1.0;
+        for (int q = 0; q <= FAR_K; ++q) {
+            pm[a][q] = 2.0 * p / fact[2 * q + 2];
+            p *= d[a] * d[a];
+        }
+    }
+    const double r2 = X * X + Y * Y + Z * Z;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    int cur = 0, prev = 2, prev2 = 1;
+    lay[cur][0] = 1.0 / sqrt(r2);
+    for (int n = 1; n <= FAR_N; ++n) {
+        prev2 = prev;
+        prev = cur;
+        cur = (cur + 1) % 3;
+        for (int i = 0; i <= n; ++i) {
+            for (int j = 0; j <= n - i; ++j) {
+                const int l = n - i - j;
+                double s1 = 0.0, s2 = 0.0;
+                if (i >= 1) s1 += X * lay[prev][lidx(n - 1, i - 1, j)];
+                if (j >= 1) s1 += Y * lay[prev][lidx(n - 1, i, j - 1)];
+                if (l >= 1) s1 += Z * lay[prev][lidx(n - 1, i, j)];
+                if (n >= 2) {
+                    if (i >= 2) s2 += lay[prev2][lidx(n - 2, i - 2, j)];
+                    if (j >= 2) s2 += lay[prev2][lidx(n - 2, i, j - 2)];
+                    if (l >= 2) s2 += lay[prev2][lidx(n - 2, i, j)];
+                }
+                const double a = -((2 * n - 1) * s1 + (n - 1) * s2) / (n * r2);
+                lay[cur][lidx(n, i, j)] = a;
+                if (n < 2) continue;
+                const double da = a * fact[i] * fact[j] * fact[l];  // D^k (1/r)
+                const int k3[3] = {i, j, l};
+                // component (p,q): gamma = k - e_p - e_q must be even and non-negative
+                const int P[6] = {0, 1, 2, 0, 0, 1}, Q[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    int g[3] = {k3[0], k3[1], k3[2]};
+                    g[P[c]] -= 1;
+                    g[Q[c]] -= 1;
+                    if (g[0] < 0 || g[1] < 0 || g[2] < 0) continue;
+                    if ((g[0] | g[1] | g[2]) & 1) continue;
+                    acc[c] += pm[0][g[0] / 2] * pm[1][g[1] / 2] * pm[2][g[2] / 2] * da;
+                }
+            }
+        }
+    }
+    const double V = dx * dy * dz;
+    for (int c = 0; c < 6; ++c) N[c] = -V / (4.0 * M_PI) * acc[c];
+}
+
+__global__ void k_newell_octant(int nx, int ny, int nz, double dx, double dy, double dz, double* __restrict__ oct) {
+    const long n = (long)nx * ny * nz;
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    const int ix = (int)(idx % nx);
+    const int iy = (int)((idx / nx) % ny);
+    const int iz = (int)(idx / ((long)nx * ny));
+    // N is invariant under a common scaling of offsets and cell: use units of the largest side
+    const double s = fmax(dx, fmax(dy, dz));
+    const double ux = dx / s, uy = dy / s, uz = dz / s;
+    const double X = ix * ux, Y = iy * uy, Z = iz * uz;
+    const double R = sqrt(X * X + Y * Y + Z * Z);
+    double N[6];
+    if (R >= FAR_SWITCH)
+        newell_far(X, Y, Z, ux, uy, uz, N);
+    else
+        newell_exact(X, Y, Z, ux, uy, uz, N);
+    // components odd along an axis vanish at zero offset along it
+    if (ix == 0) N[3] = N[4] = 0.0;
+    if (iy == 0) N[3] = N[5] = 0.0;
+    if (iz == 0) N[4] = N[5] = 0.0;
+    for (int c = 0; c < 6; ++c) oct[c * n + idx] = N[c];
+}
+
+// place component comp of the octant at wrap-around indices of the padded
+// real grid [Pz][Py][Px] (zero elsewhere), with its parity signs
+__global__ void k_scatter_tensor(const double* __restrict__ oct, int comp, int nx, int ny, int nz, int Px, int Py,
+                                 int Pz, double* __restrict__ real) {
+    const long n = (long)nx * ny * nz;
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    const int ix = (int)(idx % nx);
+    const int iy = (int)((idx / nx) % ny);
+    const int iz = (int)(idx / ((long)nx * ny));
+    const bool ox = comp == 3 || comp == 4, oy = comp == 3 || comp == 5, oz = comp == 4 || comp == 5;
+    const double v = oct[comp * n + idx];
+    for (int sz = 0; sz < (iz > 0 ? 2 : 1); ++sz)
+        for (int sy = 0; sy < (iy > 0 ? 2 : 1); ++sy)
+            for (int sx = 0; sx < (ix > 0 ? 2 : 1); ++sx) {
+                const int pz = sz ? Pz - iz : iz, py = sy ? Py - iy : iy, px = sx ? Px - ix : ix;
+                double sg = 1.0;
+                if (ox && sx) sg = -sg;
+                if (oy && sy) sg = -sg;
+                if (oz && sz) sg = -sg;
+                real[((long)pz * Py + py) * Px + px] = sg * v;
+            }
+}
+
+// real part of one component's spectrum [Pz][Py][SX] -> folded kernel
+// [comp][Kzf][Kyf][SX] times scale; per-block max |Im| for the realness check
+template <typename T>
+__global__ __launch_bounds__(NT) void k_fold(const cx<double>* __restrict__ spec, int SX, int Kx, int Py, int Kyf,
+                                             int Kzf, double scale, int comp, T* __restrict__ kfold,
+                                             double* __restrict__ parts) {
+    __shared__ double red[NT];
+    const long n = (long)Kzf * Kyf * Kx;
+    double mx = 0.0;
+    for (long e = (long)blockIdx.x * NT + threadIdx.x; e < n; e += (long)gridDim.x * NT) {
+        const int kx = (int)(e % Kx);
+        const long r = e / Kx;
+        const int kyf = (int)(r % Kyf), kzf = (int)(r / Kyf);
+        const cx<double> v = spec[((long)kzf * Py + kyf) * SX + kx];
+        kfold[(((long)comp * Kzf + kzf) * Kyf + kyf) * SX + kx] = (T)(v.x * scale);
+        mx = fmax(mx, fabs(v.y * scale));
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) parts[blockIdx.x] = red[0];
+}
+
+// ------------------------------------------------------------------------
+// launchers
+
+#define LLGX_POW2_CASES(M) M(2) M(4) M(8) M(16) M(32) M(64) M(128) M(256) M(512) M(1024) M(2048)
+
+template <typename T>
+hipError_t launch_xfwd(hipStream_t s, int LX, const Combo<T>& in, T* mk_out, int nin, long nrows, cx<T>* spec,
+                       int SX, const cx<T>* twL, const cx<T>* twP) {
+#define XF(L)                                                                                         \
+    case L: {                                                                                         \
+        constexpr int R = xfwd_rows<T>(L);                                                            \
+        k_xfwd<T, L, R><<<(unsigned)((nrows + R - 1) / R), NT, 0, s>>>(in, mk_out, nin, nrows, spec, SX, \
+                                                                       twL, twP);                     \
+        break;                                                                                        \
+    }
+    switch (LX) {
+        case 0: {
+            constexpr int R = 256;
+            k_xfwd<T, 0, R><<<(unsigned)((nrows + R - 1) / R), NT, 0, s>>>(in, mk_out, nin, nrows, spec, SX, twL,
+                                                                           twP);
+            break;
+        }
+        LLGX_POW2_CASES(XF)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef XF
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xinv(hipStream_t s, int LX, int mode, const cx<T>* spec, int SX, const T* M, const Phys<T>& ph,
+                       const XinvOut& out, const cx<T>* twL, const cx<T>* twP) {
+    const long nrow = (long)ph.ny * ph.nz;
+#define XI_MODE(L, R)                                                                               \
+    {                                                                                               \
+        const unsigned nb = (unsigned)((nrow + R - 1) / R);                                         \
+        if (mode == XINV_DEMAG)                                                                     \
+            k_xinv<T, L, R, XINV_DEMAG><<<nb, NT, 0, s>>>(spec, SX, M, ph, out, twL, twP);          \
+        else if (mode == XINV_HEFF)                                                                 \
+            k_xinv<T, L, R, XINV_HEFF><<<nb, NT, 0, s>>>(spec, SX, M, ph, out, twL, twP);           \
+        else                                                                                        \
+            k_xinv<T, L, R, XINV_RHS><<<nb, NT, 0, s>>>(spec, SX, M, ph, out, twL, twP);            \
+    }
+#define XI(L)                                   \
+    case L: {                                   \
+        constexpr int R = xinv_rows<T>(L);      \
+        XI_MODE(L, R)                           \
+        break;                                  \
+    }
+    switch (LX) {
+        case 0: {
+            constexpr int R = 64;
+            XI_MODE(0, R)
+            break;
+        }
+        LLGX_POW2_CASES(XI)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef XI
+#undef XI_MODE
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_colfft(hipStream_t s, int L, bool inv, const cx<T>* src, long s_cs, long s_os, long s_is, int n_in,
+                         cx<T>* dst, long d_cs, long d_os, long d_is, int n_out, int Kx, int nouter, int ncomp,
+                         const cx<T>* tw) {
+#define CF(LL)                                                                                              \
+    case LL: {                                                                                              \
+        constexpr int TK = col_tile<T>(LL);                                                                 \
+        dim3 g((unsigned)((Kx + TK - 1) / TK), (unsigned)nouter, (unsigned)ncomp);                          \
+        if (inv)                                                                                            \
+            k_colfft<T, LL, true, TK><<<g, NT, 0, s>>>(src, s_cs, s_os, s_is, n_in, dst, d_cs, d_os, d_is,  \
+                                                       n_out, Kx, tw);                                      \
+        else                                                                                                \
+            k_colfft<T, LL, false, TK><<<g, NT, 0, s>>>(src, s_cs, s_os, s_is, n_in, dst, d_cs, d_os, d_is, \
+                                                        n_out, Kx, tw);                                     \
+        break;                                                                                              \
+    }
+    switch (L) {
+        LLGX_POW2_CASES(CF)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef CF
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_zmul(hipStream_t s, int LZ, cx<T>* buf, int SX, int Kx, int nz, int nyrows, int Py, int Pz,
+                       const T* kfold, int Kyf, int Kzf, const cx<T>* tw) {
+#define ZM(LL)                                                                                             \
+    case LL: {                                                                                             \
+        constexpr int TK = zmul_tile<T>(LL);                                                               \
+        dim3 g((unsigned)((Kx + TK - 1) / TK), (unsigned)nyrows, 1);                                       \
+        k_zmul<T, LL, TK><<<g, NT, 0, s>>>(buf, SX, Kx, nz, nyrows, Py, Pz, kfold, Kyf, Kzf, tw);           \
+        break;                                                                                             \
+    }
+    switch (LZ) {
+        case 1: {
+            constexpr int TK = 64;
+            dim3 g((unsigned)((Kx + TK - 1) / TK), (unsigned)nyrows, 1);
+            k_zmul<T, 1, TK><<<g, NT, 0, s>>>(buf, SX, Kx, nz, nyrows, Py, Pz, kfold, Kyf, Kzf, tw);
+            break;
+        }
+        LLGX_POW2_CASES(ZM)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef ZM
+    return hipGetLastError();
+}
+
+hipError_t launch_newell_octant(hipStream_t s, int nx, int ny, int nz, double dx, double dy, double dz,
+                                double* octant) {
+    const long n = (long)nx * ny * nz;
+    k_newell_octant<<<(unsigned)((n + 127) / 128), 128, 0, s>>>(nx, ny, nz, dx, dy, dz, octant);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_tensor(hipStream_t s, const double* octant, int comp, int nx, int ny, int nz, int Px,
+                                 int Py, int Pz, double* real) {
+    const long n = (long)nx * ny * nz;
+    k_scatter_tensor<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(octant, comp, nx, ny, nz, Px, Py, Pz, real);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fold(hipStream_t s, const cx<double>* spec, int SX, int Kx, int Py, int Pz, int Kyf, int Kzf,
+                       double scale, int comp, T* kfold, double* parts, int nparts) {
+    (void)Pz;
+    k_fold<T><<<(unsigned)nparts, NT, 0, s>>>(spec, SX, Kx, Py, Kyf, Kzf, scale, comp, kfold, parts);
+    return hipGetLastError();
+}
+
+#define INST(T)                                                                                                    \
+    template hipError_t launch_xfwd<T>(hipStream_t, int, const Combo<T>&, T*, int, long, cx<T>*, int,             \
+                                       const cx<T>*, const cx<T>*);                                               \
+    template hipError_t launch_xinv<T>(hipStream_t, int, int, const cx<T>*, int, const T*, const Phys<T>&,        \
+                                       const XinvOut&, const cx<T>*, const cx<T>*);                               \
+    template hipError_t launch_colfft<T>(hipStream_t, int, bool, const cx<T>*, long, long, long, int, cx<T>*, long, \
+                                         long, long, int, int, int, int, const cx<T>*);                           \
+    template hipError_t launch_zmul<T>(hipStream_t, int, cx<T>*, int, int, int, int, int, int, const T*, int, int, \
+                                       const cx<T>*);                                                             \
+    template hipError_t launch_fold<T>(hipStream_t, const cx<double>*, int, int, int, int, int, int, double, int, \
+                                       T*, double*, int);
+INST(float)
+INST(double)
+#undef INST
+
+}  // namespace llgx

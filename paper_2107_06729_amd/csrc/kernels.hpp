@@ -1,0 +1,100 @@
+// Kernel declarations and launch helpers shared by the HIP sources.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "fft_lds.hpp"
+
+namespace llgx {
+
+constexpr int MAX_F = 8;       // stage derivatives an Eq. (4) combination may read
+constexpr int MAX_HIST = 6;    // Eq. (6) nodes: p + 1 with p <= 5
+constexpr int MAX_LEN = 2048;  // largest padded FFT length per axis
+
+// Stage input of Eq. (4): M_k = base + sum_l coef[l] * f[l] (coef = h b_kl).
+template <typename T>
+struct Combo {
+    const T* base;
+    const T* f[MAX_F];
+    T coef[MAX_F];
+    int nf;
+};
+
+// Eq. (6) at one sub-step: H_d = sum_i w[i] g[i] - N00 M_k.
+template <typename T>
+struct Extrap {
+    const T* g[MAX_HIST];
+    T w[MAX_HIST];
+    int n;
+};
+
+// Error estimate of Eq. (3): per cell |sum_k db[k] f[k]| with db = h (c_k - c^_k).
+template <typename T>
+struct ErrSum {
+    const T* f[MAX_F];
+    double db[MAX_F];
+    int n;
+};
+
+// Material and field constants of the H_eff terms and the LLG right-hand side.
+template <typename T>
+struct Phys {
+    T exx, exy, exz;   // 2A/(mu0 Ms^2) / d^2 per axis
+    T ani;             // 2K/(mu0 Ms^2)
+    T u[3];            // anisotropy axis
+    T ha[3];           // applied field
+    T gp;              // gamma / (1 + alpha^2)
+    T gpa;             // gamma alpha / ((1 + alpha^2) Ms)
+    T n00[3];          // self term of Eq. (6)
+    int nx, ny, nz;
+};
+
+// Output selection of the inverse x pass.
+enum XinvMode { XINV_DEMAG = 0, XINV_HEFF = 1, XINV_RHS = 2 };
+
+struct XinvOut {
+    void* h;     // demag field (XINV_DEMAG) or H_eff (XINV_HEFF), may be null in XINV_RHS
+    void* f;     // dM/dt (XINV_RHS)
+    void* g;     // stored field G = H_d + N00 M of Eq. (6) (optional)
+};
+
+// Host-side launchers (demag.hip).  All lengths are powers of two.
+template <typename T>
+hipError_t launch_xfwd(hipStream_t s, int LX, const Combo<T>& in, T* mk_out, int nin, long nrows,
+                       cx<T>* spec, int SX, const cx<T>* twL, const cx<T>* twP);
+template <typename T>
+hipError_t launch_xinv(hipStream_t s, int LX, int mode, const cx<T>* spec, int SX, const T* M,
+                       const Phys<T>& ph, const XinvOut& out, const cx<T>* twL, const cx<T>* twP);
+template <typename T>
+hipError_t launch_colfft(hipStream_t s, int L, bool inv, const cx<T>* src, long s_cs, long s_os, long s_is,
+                         int n_in, cx<T>* dst, long d_cs, long d_os, long d_is, int n_out, int Kx,
+                         int nouter, int ncomp, const cx<T>* tw);
+template <typename T>
+hipError_t launch_zmul(hipStream_t s, int LZ, cx<T>* buf, int SX, int Kx, int nz, int nyrows, int Py, int Pz,
+                       const T* kfold, int Kyf, int Kzf, const cx<T>* tw);
+hipError_t launch_newell_octant(hipStream_t s, int nx, int ny, int nz, double dx, double dy, double dz,
+                                double* octant);
+hipError_t launch_scatter_tensor(hipStream_t s, const double* octant, int comp, int nx, int ny, int nz,
+                                 int Px, int Py, int Pz, double* real);
+template <typename T>
+hipError_t launch_fold(hipStream_t s, const cx<double>* spec, int SX, int Kx, int Py, int Pz, int Kyf, int Kzf,
+                       double scale, int comp, T* kfold, double* imag_max_parts, int nparts);
+
+// Stage kernels (llg.hip).
+template <typename T>
+hipError_t launch_combine(hipStream_t s, long n, const Combo<T>& c, T* out);
+template <typename T>
+hipError_t launch_extrap_rhs(hipStream_t s, const T* Mk, const Extrap<T>& ex, const Phys<T>& ph, T* F);
+template <typename T>
+hipError_t launch_final(hipStream_t s, long ncell, const Combo<T>& sol, const ErrSum<T>& es, double inv_ms,
+                        T* mnew, double* parts, int nparts);
+hipError_t launch_reduce_max(hipStream_t s, const double* parts, int nparts, double* out);
+template <typename T>
+hipError_t launch_renorm(hipStream_t s, long ncell, T* M, double Ms);
+template <typename T>
+hipError_t launch_mean(hipStream_t s, long ncell, const T* M, double* parts, int nparts);
+hipError_t launch_reduce_sum3(hipStream_t s, const double* parts, int nparts, double* out);
+template <typename T>
+hipError_t launch_cast(hipStream_t s, long n, const double* src, T* dst);
+
+}  // namespace llgx

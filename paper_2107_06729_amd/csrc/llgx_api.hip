@@ -1,0 +1,891 @@
+// Host runtime behind the C ABI of include/llgx.h: workspace and FFT plan,
+// demagnetizing-tensor setup, field evaluations, and the explicit stepping
+// of Sec. II (Eq. (3)-(6)) with the Eq. (5) controller, the history ring of
+// Eq. (6), priming, and HIP-graph replay of fixed steps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "llgx.h"
+#include "tableaux.hpp"
+
+namespace llgx {
+
+static thread_local std::string g_create_error;
+
+static int next_pow2(long v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+struct GraphKey {
+    const void* M;
+    int slot0;
+    std::vector<int> hist_slots;
+    double h;
+    bool operator<(const GraphKey& o) const {
+        if (M != o.M) return M < o.M;
+        if (slot0 != o.slot0) return slot0 < o.slot0;
+        if (hist_slots != o.hist_slots) return hist_slots < o.hist_slots;
+        return h < o.h;
+    }
+};
+
+struct Ctx {
+    llgx_problem p{};
+    int prec = LLGX_F64, spectral = LLGX_SPEC_NATIVE;
+    hipStream_t stream = nullptr;
+    std::string err;
+    size_t tsz = 8;  // bytes per real of the working precision
+
+    // plan
+    int nx = 1, ny = 1, nz = 1;
+    long ncell = 1;
+    int Px = 1, Py = 1, Pz = 1, LX = 0, Kx = 1, SX = 16, Kyf = 1, Kzf = 1;
+
+    // device workspace
+    void* kfold = nullptr;
+    void* specA = nullptr;
+    void* specB = nullptr;
+    std::map<int, void*> tw_work;  // twiddle tables in the working precision
+    std::map<int, void*> tw_f64;   // twiddle tables in double (tensor setup)
+    void* M = nullptr;
+    void* Mnew = nullptr;
+    void* Mk = nullptr;
+    void* F[MAX_F] = {};
+    void* G[MAX_HIST] = {};
+    double* parts = nullptr;
+    int nparts = 1;
+    double* scal = nullptr;     // [0] error norm, [1..3] sums for <M>
+    double* octant = nullptr;   // real-space tensor for offsets 0..n-1 (double)
+    bool have_kernel = false;
+    bool have_m = false;
+    double n00[3] = {0, 0, 0};
+
+    // stepping state
+    double t = 0.0, h_next = 0.0;
+    struct Hist {
+        double t;
+        int slot;
+    };
+    std::vector<Hist> hist;  // previous accepted iterations, oldest first
+    bool fsal_valid = false;
+    int cur_method = -1, cur_p = -100;
+    long long n_exact = 0, n_extrap = 0, n_acc = 0, n_rej = 0, n_forced = 0;
+
+    std::map<GraphKey, hipGraphExec_t> graphs;
+
+    llgx_status fail(llgx_status code, const char* fmt, ...) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        err = buf;
+        return code;
+    }
+};
+
+#define HIPCHK(ctx, expr)                                                                                   \
+    do {                                                                                                    \
+        hipError_t e_ = (expr);                                                                             \
+        if (e_ != hipSuccess)                                                                               \
+            return (ctx)->fail(e_ == hipErrorOutOfMemory ? LLGX_E_OOM : LLGX_E_HIP, "%s failed: %s (%s:%d)", \
+                               #expr, hipGetErrorString(e_), __FILE__, __LINE__);                           \
+    } while (0)
+
+static llgx_status dalloc(Ctx* c, void** p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return c->fail(e == hipErrorOutOfMemory ? LLGX_E_OOM : LLGX_E_HIP, "hipMalloc(%zu) failed: %s", bytes,
+                       hipGetErrorString(e));
+    }
+    return LLGX_OK;
+}
+
+// twiddle table e^{-2 pi i m/L}, m < L, built in double
+template <typename T>
+static llgx_status make_table(Ctx* c, std::map<int, void*>& tabs, int L) {
+    if (L < 2 || tabs.count(L)) return LLGX_OK;
+    std::vector<T> h(2 * (size_t)L);
+    for (int m = 0; m < L; ++m) {
+        const double a = 2.0 * M_PI * (double)m / (double)L;
+        h[2 * m] = (T)std::cos(a);
+        h[2 * m + 1] = (T)(-std::sin(a));
+    }
+    void* d = nullptr;
+    llgx_status st = dalloc(c, &d, h.size() * sizeof(T));
+    if (st) return st;
+    HIPCHK(c, hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    tabs[L] = d;
+    return LLGX_OK;
+}
+
+template <typename T>
+static const cx<T>* table(Ctx* c, int L, bool f64) {
+    auto& tabs = f64 ? c->tw_f64 : c->tw_work;
+    auto it = tabs.find(L);
+    return it == tabs.end() ? nullptr : (const cx<T>*)it->second;
+}
+
+template <typename T>
+static Phys<T> phys(const Ctx* c) {
+    const llgx_problem& p = c->p;
+    const double mu0 = 4e-7 * M_PI;
+    const double exf = 2.0 * p.A / (mu0 * p.Ms * p.Ms);
+    Phys<T> ph;
+    ph.exx = (T)(exf / (p.dx * p.dx));
+    ph.exy = (T)(exf / (p.dy * p.dy));
+    ph.exz = (T)(exf / (p.dz * p.dz));
+    ph.ani = (T)(2.0 * p.K / (mu0 * p.Ms * p.Ms));
+    double un = std::sqrt(p.easy[0] * p.easy[0] + p.easy[1] * p.easy[1] + p.easy[2] * p.easy[2]);
+    for (int i = 0; i < 3; ++i) {
+        ph.u[i] = (T)(un > 0 ? p.easy[i] / un : 0.0);
+        ph.ha[i] = (T)p.Ha[i];
+        ph.n00[i] = (T)c->n00[i];
+    }
+    const double gp = p.gamma / (1.0 + p.alpha * p.alpha);
+    ph.gp = (T)gp;
+    ph.gpa = (T)(gp * p.alpha / p.Ms);
+    ph.nx = c->nx;
+    ph.ny = c->ny;
+    ph.nz = c->nz;
+    return ph;
+}
+
+// ---------------------------------------------------------------------------
+// one exact evaluation of Eq. (2) on the stage input `in` (Eq. (4)), ending
+// in the inverse x pass selected by `mode`
+template <typename T>
+static llgx_status eval_exact(Ctx* c, const Combo<T>& in, T* mk_out, int mode, const T* Mrhs, const XinvOut& out) {
+    hipStream_t s = c->stream;
+    cx<T>* A = (cx<T>*)c->specA;
+    const cx<T>* twL = table<T>(c, c->LX, false);
+    const cx<T>* twP = table<T>(c, c->Px, false);
+    HIPCHK(c, launch_xfwd<T>(s, c->LX, in, mk_out, c->nx, 3L * c->ny * c->nz, A, c->SX, twL, twP));
+    cx<T>* work = A;
+    int nyrows = c->ny;
+    if (c->Py > 1) {
+        cx<T>* B = (cx<T>*)c->specB;
+        const long sa = (long)c->nz * c->ny * c->SX, sb = (long)c->nz * c->Py * c->SX;
+        HIPCHK(c, launch_colfft<T>(s, c->Py, false, A, sa, (long)c->ny * c->SX, c->SX, c->ny, B, sb,
+                                   (long)c->Py * c->SX, c->SX, c->Py, c->Kx, c->nz, 3, table<T>(c, c->Py, false)));
+        work = B;
+        nyrows = c->Py;
+    }
+    HIPCHK(c, launch_zmul<T>(s, c->Pz, work, c->SX, c->Kx, c->nz, nyrows, c->Py, c->Pz, (const T*)c->kfold, c->Kyf,
+                             c->Kzf, table<T>(c, c->Pz, false)));
+    if (c->Py > 1) {
+        cx<T>* B = (cx<T>*)c->specB;
+        const long sa = (long)c->nz * c->ny * c->SX, sb = (long)c->nz * c->Py * c->SX;
+        HIPCHK(c, launch_colfft<T>(s, c->Py, true, B, sb, (long)c->Py * c->SX, c->SX, c->Py, A, sa,
+                                   (long)c->ny * c->SX, c->SX, c->ny, c->Kx, c->nz, 3, table<T>(c, c->Py, false)));
+    }
+    HIPCHK(c, launch_xinv<T>(s, c->LX, mode, A, c->SX, Mrhs, phys<T>(c), out, twL, twP));
+    return LLGX_OK;
+}
+
+template <typename T>
+static Combo<T> plain(const void* base) {
+    Combo<T> cb{};
+    cb.base = (const T*)base;
+    cb.nf = 0;
+    return cb;
+}
+
+// ---------------------------------------------------------------------------
+// demagnetizing tensor -> folded real k-space kernel (double FFT passes)
+template <typename T>
+static llgx_status kernel_from_octant_or_real(Ctx* c, const std::vector<double>* full_host) {
+    hipStream_t s = c->stream;
+    const long preal = (long)c->Pz * c->Py * c->Px;
+    const long pspec = (long)c->Pz * c->Py * c->SX;
+    void* real = nullptr;
+    void* spec = nullptr;
+    llgx_status st = dalloc(c, &real, preal * sizeof(double));
+    if (st) return st;
+    st = dalloc(c, &spec, pspec * 2 * sizeof(double));
+    if (st) {
+        (void)hipFree(real);
+        return st;
+    }
+    if (!c->kfold) {
+        st = dalloc(c, &c->kfold, 6L * c->Kzf * c->Kyf * c->SX * sizeof(T));
+        if (st) {
+            (void)hipFree(real);
+            (void)hipFree(spec);
+            return st;
+        }
+        HIPCHK(c, hipMemsetAsync(c->kfold, 0, 6L * c->Kzf * c->Kyf * c->SX * sizeof(T), s));
+    }
+    for (int L : {c->LX, c->Px, c->Py, c->Pz}) {
+        st = make_table<double>(c, c->tw_f64, L);
+        if (st) return st;
+    }
+    const double scale = -1.0 / ((double)c->Px * c->Py * c->Pz);
+    std::vector<double> hreal;
+    for (int comp = 0; comp < 6; ++comp) {
+        if (full_host) {
+            // caller's tensor at wrap-around indices of the padded grid
+            hreal.assign(preal, 0.0);
+            const int fx = 2 * c->nx - 1, fy = 2 * c->ny - 1, fz = 2 * c->nz - 1;
+            for (int dz = -(c->nz - 1); dz < c->nz; ++dz)
+                for (int dy = -(c->ny - 1); dy < c->ny; ++dy)
+                    for (int dx = -(c->nx - 1); dx < c->nx; ++dx) {
+                        const long src = (((long)comp * fz + dz + c->nz - 1) * fy + dy + c->ny - 1) * fx + dx + c->nx - 1;
+                        const int pz = (dz + c->Pz) % c->Pz, py = (dy + c->Py) % c->Py, px = (dx + c->Px) % c->Px;
+                        hreal[((long)pz * c->Py + py) * c->Px + px] = (*full_host)[src];
+                    }
+            HIPCHK(c, hipMemcpyAsync(real, hreal.data(), preal * sizeof(double), hipMemcpyHostToDevice, s));
+        } else {
+            HIPCHK(c, hipMemsetAsync(real, 0, preal * sizeof(double), s));
+            HIPCHK(c, launch_scatter_tensor(s, c->octant, comp, c->nx, c->ny, c->nz, c->Px, c->Py, c->Pz,
+                                            (double*)real));
+        }
+        cx<double>* sp = (cx<double>*)spec;
+        HIPCHK(c, launch_xfwd<double>(s, c->LX, plain<double>(real), nullptr, c->Px, (long)c->Pz * c->Py, sp, c->SX,
+                                      table<double>(c, c->LX, true), table<double>(c, c->Px, true)));
+        if (c->Py > 1)
+            HIPCHK(c, launch_colfft<double>(s, c->Py, false, sp, 0, (long)c->Py * c->SX, c->SX, c->Py, sp, 0,
+                                            (long)c->Py * c->SX, c->SX, c->Py, c->Kx, c->Pz, 1,
+                                            table<double>(c, c->Py, true)));
+        if (c->Pz > 1)
+            HIPCHK(c, launch_colfft<double>(s, c->Pz, false, sp, 0, c->SX, (long)c->Py * c->SX, c->Pz, sp, 0, c->SX,
+                                            (long)c->Py * c->SX, c->Pz, c->Kx, c->Py, 1, table<double>(c, c->Pz, true)));
+        HIPCHK(c, launch_fold<T>(s, sp, c->SX, c->Kx, c->Py, c->Pz, c->Kyf, c->Kzf, scale, comp, (T*)c->kfold,
+                                 c->parts, c->nparts));
+    }
+    HIPCHK(c, hipStreamSynchronize(s));
+    (void)hipFree(real);
+    (void)hipFree(spec);
+    c->have_kernel = true;
+    return LLGX_OK;
+}
+
+static llgx_status precompute(Ctx* c) {
+    hipStream_t s = c->stream;
+    if (!c->octant) {
+        llgx_status st = dalloc(c, (void**)&c->octant, 6L * c->ncell * sizeof(double));
+        if (st) return st;
+    }
+    HIPCHK(c, launch_newell_octant(s, c->nx, c->ny, c->nz, c->p.dx, c->p.dy, c->p.dz, c->octant));
+    double n00[3];
+    for (int i = 0; i < 3; ++i)
+        HIPCHK(c, hipMemcpyAsync(&n00[i], c->octant + (long)i * c->ncell, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    for (int i = 0; i < 3; ++i) c->n00[i] = n00[i];
+    llgx_status st = c->prec == LLGX_F32 ? kernel_from_octant_or_real<float>(c, nullptr)
+                                         : kernel_from_octant_or_real<double>(c, nullptr);
+    return st;
+}
+
+// ---------------------------------------------------------------------------
+// stepping
+static int extrap_order(const Tableau* tab, int extrap) {
+    return extrap == LLGX_EXTRAP_MATCHED ? tab->order : extrap;
+}
+
+static std::vector<double> lagrange(const std::vector<double>& nodes, double t) {
+    std::vector<double> w(nodes.size());
+    for (size_t i = 0; i < nodes.size(); ++i) {
+        double li = 1.0;
+        for (size_t j = 0; j < nodes.size(); ++j)
+            if (j != i) li *= (t - nodes[j]) / (nodes[i] - nodes[j]);
+        w[i] = li;
+    }
+    return w;
+}
+
+// Host-side decisions of one attempt (pointers, slots, weights), so that the
+// same enqueue can run eagerly or be captured into a graph.
+struct Plan {
+    const Tableau* tab;
+    int p;            // -1: full evaluation
+    bool extrap;      // Eq. (6) used at stages >= 2
+    bool stage1;      // stage 1 must be evaluated (not FSAL reuse, not a retry)
+    int slot0;        // G slot receiving this iteration's stored field
+    double h;
+    bool want_err;
+};
+
+template <typename T>
+static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
+    const Tableau* tab = pl.tab;
+    const double h = pl.h;
+    if (pl.stage1) {
+        XinvOut out{nullptr, c->F[0], pl.p >= 0 ? c->G[pl.slot0] : nullptr};
+        llgx_status st = eval_exact<T>(c, plain<T>(c->M), nullptr, XINV_RHS, (const T*)c->M, out);
+        if (st) return st;
+    }
+    std::vector<double> nodes;
+    std::vector<int> slots;
+    if (pl.extrap) {
+        for (auto& hh : c->hist) {
+            nodes.push_back(hh.t - c->t);
+            slots.push_back(hh.slot);
+        }
+        nodes.push_back(0.0);
+        slots.push_back(pl.slot0);
+    }
+    for (int k = 1; k < tab->S; ++k) {
+        Combo<T> cb{};
+        cb.base = (const T*)c->M;
+        cb.nf = 0;
+        for (int l = 0; l < k; ++l) {
+            if (tab->a[k][l] == 0.0) continue;
+            cb.f[cb.nf] = (const T*)c->F[l];
+            cb.coef[cb.nf] = (T)(h * tab->a[k][l]);
+            cb.nf++;
+        }
+        if (pl.extrap) {
+            HIPCHK(c, launch_combine<T>(c->stream, 3 * c->ncell, cb, (T*)c->Mk));
+            Extrap<T> ex{};
+            const std::vector<double> w = lagrange(nodes, tab->c[k] * h);
+            ex.n = (int)w.size();
+            for (int i = 0; i < ex.n; ++i) {
+                ex.g[i] = (const T*)c->G[slots[i]];
+                ex.w[i] = (T)w[i];
+            }
+            HIPCHK(c, launch_extrap_rhs<T>(c->stream, (const T*)c->Mk, ex, phys<T>(c), (T*)c->F[k]));
+        } else {
+            XinvOut out{nullptr, c->F[k], nullptr};
+            llgx_status st = eval_exact<T>(c, cb, (T*)c->Mk, XINV_RHS, (const T*)c->Mk, out);
+            if (st) return st;
+        }
+    }
+    Combo<T> sol{};
+    sol.base = (const T*)c->M;
+    ErrSum<T> es{};
+    for (int k = 0; k < tab->S; ++k) {
+        if (tab->b[k] != 0.0) {
+            sol.f[sol.nf] = (const T*)c->F[k];
+            sol.coef[sol.nf] = (T)(h * tab->b[k]);
+            sol.nf++;
+        }
+        if (pl.want_err && tab->order_hat > 0 && tab->b[k] != tab->bh[k]) {
+            es.f[es.n] = (const T*)c->F[k];
+            es.db[es.n] = h * (tab->b[k] - tab->bh[k]);
+            es.n++;
+        }
+    }
+    HIPCHK(c, launch_final<T>(c->stream, c->ncell, sol, es, 1.0 / c->p.Ms, (T*)c->Mnew, c->parts, c->nparts));
+    if (pl.want_err) HIPCHK(c, launch_reduce_max(c->stream, c->parts, c->nparts, c->scal));
+    return LLGX_OK;
+}
+
+static int free_slot(const Ctx* c) {
+    for (int s = 0; s < MAX_HIST; ++s) {
+        bool used = false;
+        for (auto& hh : c->hist) used |= hh.slot == s;
+        if (!used) return s;
+    }
+    return -1;
+}
+
+template <typename T>
+static llgx_status commit(Ctx* c, const Plan& pl, double h_used) {
+    if (pl.p > 0) {
+        c->hist.push_back({c->t, pl.slot0});
+        while ((int)c->hist.size() > pl.p) c->hist.erase(c->hist.begin());
+    }
+    std::swap(c->M, c->Mnew);
+    c->fsal_valid = false;
+    if (pl.p < 0 && pl.tab->fsal) {
+        // the last stage was evaluated at the accepted M: it is stage 1 of the next step
+        std::swap(c->F[0], c->F[pl.tab->S - 1]);
+        c->fsal_valid = true;
+    }
+    c->t += h_used;
+    c->n_acc++;
+    return LLGX_OK;
+}
+
+static llgx_status check_stepper(Ctx* c, const llgx_stepper* s, const Tableau** tab, int* p) {
+    if (!s) return c->fail(LLGX_E_ARG, "null stepper");
+    *tab = tableau_for(s->method);
+    if (!*tab) return c->fail(LLGX_E_ARG, "unknown method %d", s->method);
+    *p = extrap_order(*tab, s->extrap);
+    if (*p < -1 || *p > MAX_HIST - 1) return c->fail(LLGX_E_ARG, "extrapolation order %d out of range", s->extrap);
+    if (s->adaptive && (*tab)->order_hat == 0) return c->fail(LLGX_E_ARG, "%s has no embedded estimate", (*tab)->name);
+    if (!(s->h > 0)) return c->fail(LLGX_E_ARG, "h must be > 0");
+    if (!c->have_kernel) return c->fail(LLGX_E_STATE, "demag kernel not computed (llgx_precompute_demag)");
+    if (!c->have_m) return c->fail(LLGX_E_STATE, "magnetization not set (llgx_set_m)");
+    if (s->method != c->cur_method || *p != c->cur_p) {
+        c->hist.clear();
+        c->fsal_valid = false;
+        c->cur_method = s->method;
+        c->cur_p = *p;
+        c->h_next = 0.0;
+    }
+    if (s->renormalize) c->fsal_valid = false;
+    return LLGX_OK;
+}
+
+template <typename T>
+static llgx_status do_step(Ctx* c, const llgx_stepper* s, llgx_step_info* info) {
+    const Tableau* tab;
+    int p;
+    llgx_status st = check_stepper(c, s, &tab, &p);
+    if (st) return st;
+    Plan pl{};
+    pl.tab = tab;
+    pl.p = p;
+    pl.extrap = p >= 0 && (int)c->hist.size() == p;
+    pl.stage1 = !c->fsal_valid;
+    pl.slot0 = free_slot(c);
+    pl.want_err = s->adaptive != 0;
+    double h = s->h;
+    if (s->adaptive) {
+        if (c->h_next > 0) h = c->h_next;
+        h = std::min(std::max(h, s->h_min), s->h_max);
+    }
+    const int q = s->exponent_mode == 1 ? tab->order : std::min(tab->order, tab->order_hat > 0 ? tab->order_hat : tab->order);
+    const long long ex0 = c->n_exact, xt0 = c->n_extrap;
+    int rejected = 0;
+    bool forced = false;
+    double err = -1.0, h_next = h;
+    for (;;) {
+        pl.h = h;
+        st = enqueue_attempt<T>(c, pl);
+        if (st) return st;
+        if (pl.stage1) c->n_exact++;
+        const int later = tab->S - 1;
+        if (pl.extrap)
+            c->n_extrap += later;
+        else
+            c->n_exact += later;
+        if (!s->adaptive) break;
+        HIPCHK(c, hipMemcpyAsync(&err, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (!std::isfinite(err)) return c->fail(LLGX_E_NONFINITE, "non-finite error estimate at t=%g", c->t);
+        const double cf =
+            err <= 0.0 ? s->c_max
+                       : std::min(std::max(std::pow(0.8 * s->e_max / err, 1.0 / (q + 1)), s->c_min), s->c_max);
+        if (err > s->e_max) {
+            if (h > s->h_min) {
+                rejected++;
+                h = std::min(std::max(h * cf, s->h_min), s->h_max);
+                pl.stage1 = false;  // stage 1 does not depend on h: reuse it
+                continue;
+            }
+            forced = true;
+        }
+        h_next = std::min(std::max(h * cf, s->h_min), s->h_max);
+        break;
+    }
+    st = commit<T>(c, pl, h);
+    if (st) return st;
+    if (s->renormalize) HIPCHK(c, launch_renorm<T>(c->stream, c->ncell, (T*)c->M, c->p.Ms));
+    c->h_next = s->adaptive ? h_next : h;
+    c->n_rej += rejected;
+    c->n_forced += forced;
+    if (info) {
+        info->t = c->t;
+        info->h_used = h;
+        info->h_next = c->h_next;
+        info->err = err;
+        info->rejected = rejected;
+        info->exact_evals = (int)(c->n_exact - ex0);
+        info->extrap_evals = (int)(c->n_extrap - xt0);
+        info->forced = forced;
+    }
+    return LLGX_OK;
+}
+
+template <typename T>
+static llgx_status do_run_fixed(Ctx* c, const llgx_stepper* s, int64_t nsteps, int use_graph, llgx_step_info* info) {
+    if (s && s->adaptive) return c->fail(LLGX_E_ARG, "llgx_run_fixed needs a fixed step (adaptive = 0)");
+    for (int64_t i = 0; i < nsteps; ++i) {
+        const Tableau* tab;
+        int p;
+        llgx_status st = check_stepper(c, s, &tab, &p);
+        if (st) return st;
+        const bool steady = (p < 0 && !tab->fsal) || (p >= 0 && (int)c->hist.size() == p) ||
+                            (p < 0 && tab->fsal && s->renormalize);
+        // the legacy default stream cannot be captured: replay needs a created stream
+        if (!use_graph || !steady || c->stream == nullptr) {
+            st = do_step<T>(c, s, info);
+            if (st) return st;
+            continue;
+        }
+        Plan pl{};
+        pl.tab = tab;
+        pl.p = p;
+        pl.extrap = p >= 0;
+        pl.stage1 = true;
+        pl.slot0 = free_slot(c);
+        pl.want_err = false;
+        pl.h = s->h;
+        GraphKey key{c->M, pl.slot0, {}, s->h};
+        for (auto& hh : c->hist) key.hist_slots.push_back(hh.slot);
+        // the Lagrange nodes are relative times: graphs are reused only while steps stay uniform
+        bool uniform = true;
+        for (size_t j = 0; j < c->hist.size(); ++j) {
+            const double expect = -(double)(c->hist.size() - j) * s->h;
+            if (std::fabs((c->hist[j].t - c->t) - expect) > 1e-9 * s->h) uniform = false;
+        }
+        if (!uniform) {
+            st = do_step<T>(c, s, info);
+            if (st) return st;
+            continue;
+        }
+        auto it = c->graphs.find(key);
+        if (it == c->graphs.end()) {
+            hipGraph_t g;
+            HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            st = enqueue_attempt<T>(c, pl);
+            hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+            if (st) return st;
+            if (e2 != hipSuccess) return c->fail(LLGX_E_HIP, "graph capture failed: %s", hipGetErrorString(e2));
+            hipGraphExec_t ge;
+            HIPCHK(c, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+            (void)hipGraphDestroy(g);
+            it = c->graphs.emplace(key, ge).first;
+        }
+        HIPCHK(c, hipGraphLaunch(it->second, c->stream));
+        c->n_exact += 1 + (pl.extrap ? 0 : tab->S - 1);
+        c->n_extrap += pl.extrap ? tab->S - 1 : 0;
+        st = commit<T>(c, pl, s->h);
+        if (st) return st;
+        if (s->renormalize) HIPCHK(c, launch_renorm<T>(c->stream, c->ncell, (T*)c->M, c->p.Ms));
+        c->h_next = s->h;
+        if (info) {
+            info->t = c->t;
+            info->h_used = s->h;
+            info->h_next = s->h;
+            info->err = -1.0;
+            info->rejected = 0;
+            info->exact_evals = 1 + (pl.extrap ? 0 : tab->S - 1);
+            info->extrap_evals = pl.extrap ? tab->S - 1 : 0;
+            info->forced = 0;
+        }
+    }
+    return LLGX_OK;
+}
+
+template <typename T>
+static llgx_status mean_m(Ctx* c, double out[3]) {
+    HIPCHK(c, launch_mean<T>(c->stream, c->ncell, (const T*)c->M, c->parts, c->nparts));
+    HIPCHK(c, launch_reduce_sum3(c->stream, c->parts, c->nparts, c->scal + 1));
+    HIPCHK(c, hipMemcpyAsync(out, c->scal + 1, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < 3; ++i) out[i] /= (double)c->ncell;
+    return LLGX_OK;
+}
+
+template <typename T>
+static llgx_status do_run(Ctx* c, const llgx_stepper* s, double t_end, double sample_dt, double* mavg, int64_t cap,
+                          int64_t* nsamples) {
+    int64_t ns = 0;
+    auto record = [&]() -> llgx_status {
+        if (!mavg || ns >= cap) return LLGX_OK;
+        llgx_status st = mean_m<T>(c, mavg + 3 * ns);
+        if (st) return st;
+        ns++;
+        return LLGX_OK;
+    };
+    llgx_stepper sc = *s;
+    llgx_status st = LLGX_OK;
+    double next_s = 0.0;
+    if (sample_dt > 0) {
+        st = record();
+        if (st) return st;
+        next_s = c->t + sample_dt;
+    }
+    const double tol = 1e-9 * s->h;
+    while (c->t < t_end - tol) {
+        const Tableau* tab;
+        int p;
+        st = check_stepper(c, &sc, &tab, &p);
+        if (st) return st;
+        const double target = sample_dt > 0 ? std::min(next_s, t_end) : t_end;
+        bool shortened = false;
+        double h_prop = c->h_next > 0 ? c->h_next : sc.h;
+        if (sc.adaptive && c->t + h_prop > target) {
+            c->h_next = target - c->t;
+            shortened = true;
+        }
+        llgx_step_info info;
+        st = do_step<T>(c, &sc, &info);
+        if (st) return st;
+        if (shortened) c->h_next = std::max(c->h_next, h_prop);
+        if (sample_dt > 0 && c->t >= next_s - 1e-9 * info.h_used) {
+            st = record();
+            if (st) return st;
+            next_s += sample_dt;
+        }
+    }
+    if (nsamples) *nsamples = ns;
+    return LLGX_OK;
+}
+
+static void release(Ctx* c) {
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    void* ptrs[] = {c->kfold, c->specA, c->specB, c->M, c->Mnew, c->Mk, c->parts, c->scal, c->octant};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    for (int i = 0; i < MAX_F; ++i)
+        if (c->F[i]) (void)hipFree(c->F[i]);
+    for (int i = 0; i < MAX_HIST; ++i)
+        if (c->G[i]) (void)hipFree(c->G[i]);
+    for (auto& kv : c->tw_work) (void)hipFree(kv.second);
+    for (auto& kv : c->tw_f64) (void)hipFree(kv.second);
+}
+
+}  // namespace llgx
+
+using namespace llgx;
+
+// ===========================================================================
+// C ABI
+
+extern "C" {
+
+const char* llgx_last_error(llgx_handle h) {
+    if (!h) return g_create_error.c_str();
+    return ((Ctx*)h)->err.c_str();
+}
+
+void llgx_stepper_defaults(llgx_stepper* s) {
+    if (!s) return;
+    std::memset(s, 0, sizeof *s);
+    s->method = LLGX_RK4;
+    s->extrap = LLGX_EXTRAP_FULL;
+    s->adaptive = 0;
+    s->renormalize = 0;
+    s->exponent_mode = 0;
+    s->h = 1e-13;
+    s->h_min = 1e-15;
+    s->h_max = 3e-12;
+    s->c_min = 0.01;
+    s->c_max = 2.0;
+    s->e_max = 1e-5;
+}
+
+llgx_status llgx_create(const llgx_problem* p, int32_t precision, int32_t spectral, void* hip_stream,
+                        llgx_handle* out) {
+    g_create_error.clear();
+    if (!p || !out) {
+        g_create_error = "null argument";
+        return LLGX_E_ARG;
+    }
+    *out = nullptr;
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1 || !(p->dx > 0) || !(p->dy > 0) || !(p->dz > 0) || !(p->Ms > 0) ||
+        !(p->gamma > 0) || p->A < 0 || p->alpha < 0) {
+        g_create_error = "invalid problem (sizes >= 1, cell > 0, Ms > 0, gamma > 0, A >= 0, alpha >= 0)";
+        return LLGX_E_ARG;
+    }
+    if (precision != LLGX_F32 && precision != LLGX_F64) {
+        g_create_error = "precision must be LLGX_F32 or LLGX_F64";
+        return LLGX_E_ARG;
+    }
+    if (spectral != LLGX_SPEC_NATIVE) {
+        g_create_error = "16-bit spectral storage is not available in this build";
+        return LLGX_E_UNSUPPORTED;
+    }
+    Ctx* c = new Ctx();
+    c->p = *p;
+    c->prec = precision;
+    c->spectral = spectral;
+    c->stream = (hipStream_t)hip_stream;
+    c->tsz = precision == LLGX_F32 ? 4 : 8;
+    c->nx = p->nx;
+    c->ny = p->ny;
+    c->nz = p->nz;
+    c->ncell = (long)p->nx * p->ny * p->nz;
+    c->Px = p->nx > 1 ? next_pow2(2L * p->nx - 1) : 1;
+    c->Py = p->ny > 1 ? next_pow2(2L * p->ny - 1) : 1;
+    c->Pz = p->nz > 1 ? next_pow2(2L * p->nz - 1) : 1;
+    if (c->Px > MAX_LEN || c->Py > MAX_LEN || c->Pz > MAX_LEN) {
+        g_create_error = "mesh too large: padded FFT length per axis above 2048";
+        delete c;
+        return LLGX_E_UNSUPPORTED;
+    }
+    c->LX = c->Px > 1 ? c->Px / 2 : 0;
+    c->Kx = c->Px > 1 ? c->Px / 2 + 1 : 1;
+    c->SX = (c->Kx + 15) / 16 * 16;
+    c->Kyf = c->Py > 1 ? c->Py / 2 + 1 : 1;
+    c->Kzf = c->Pz > 1 ? c->Pz / 2 + 1 : 1;
+    const size_t cbytes = 2 * c->tsz;
+    const size_t vbytes = 3 * (size_t)c->ncell * c->tsz;
+    llgx_status st = LLGX_OK;
+    auto A = [&](void** ptr, size_t bytes) {
+        if (st == LLGX_OK) st = dalloc(c, ptr, bytes);
+    };
+    A(&c->specA, 3 * (size_t)c->nz * c->ny * c->SX * cbytes);
+    if (c->Py > 1) A(&c->specB, 3 * (size_t)c->nz * c->Py * c->SX * cbytes);
+    A(&c->M, vbytes);
+    A(&c->Mnew, vbytes);
+    A(&c->Mk, vbytes);
+    for (int i = 0; i < MAX_F; ++i) A(&c->F[i], vbytes);
+    for (int i = 0; i < MAX_HIST; ++i) A(&c->G[i], vbytes);
+    c->nparts = (int)std::min<long>(1024, std::max<long>(1, (c->ncell + 255) / 256));
+    A((void**)&c->parts, 3 * (size_t)c->nparts * sizeof(double));
+    A((void**)&c->scal, 8 * sizeof(double));
+    if (st == LLGX_OK) {
+        for (int L : {c->LX, c->Px, c->Py, c->Pz}) {
+            if (st) break;
+            st = c->prec == LLGX_F32 ? make_table<float>(c, c->tw_work, L) : make_table<double>(c, c->tw_work, L);
+        }
+    }
+    if (st != LLGX_OK) {
+        g_create_error = c->err;
+        release(c);
+        delete c;
+        return st;
+    }
+    *out = (llgx_handle)c;
+    return LLGX_OK;
+}
+
+void llgx_destroy(llgx_handle h) {
+    if (!h) return;
+    Ctx* c = (Ctx*)h;
+    (void)hipStreamSynchronize(c->stream);
+    release(c);
+    delete c;
+}
+
+llgx_status llgx_precompute_demag(llgx_handle h) {
+    if (!h) return LLGX_E_ARG;
+    Ctx* c = (Ctx*)h;
+    if (c->have_kernel && c->octant) return LLGX_OK;
+    return precompute(c);
+}
+
+llgx_status llgx_set_demag_tensor(llgx_handle h, const double* N_host) {
+    if (!h) return LLGX_E_ARG;
+    Ctx* c = (Ctx*)h;
+    if (!N_host) return c->fail(LLGX_E_ARG, "null tensor");
+    const long nfull = 6L * (2 * c->nx - 1) * (2 * c->ny - 1) * (2 * c->nz - 1);
+    std::vector<double> full(N_host, N_host + nfull);
+    const long o = (((long)(c->nz - 1) * (2 * c->ny - 1) + (c->ny - 1)) * (2 * c->nx - 1)) + (c->nx - 1);
+    const long cs = (long)(2 * c->nz - 1) * (2 * c->ny - 1) * (2 * c->nx - 1);
+    for (int i = 0; i < 3; ++i) c->n00[i] = full[i * cs + o];
+    c->hist.clear();
+    c->fsal_valid = false;
+    return c->prec == LLGX_F32 ? kernel_from_octant_or_real<float>(c, &full)
+                               : kernel_from_octant_or_real<double>(c, &full);
+}
+
+llgx_status llgx_get_demag_tensor(llgx_handle h, double* N_host) {
+    if (!h) return LLGX_E_ARG;
+    Ctx* c = (Ctx*)h;
+    if (!N_host) return c->fail(LLGX_E_ARG, "null output");
+    if (!c->octant) return c->fail(LLGX_E_STATE, "tensor not computed on the device (llgx_precompute_demag)");
+    HIPCHK(c, hipMemcpyAsync(N_host, c->octant, 6L * c->ncell * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LLGX_OK;
+}
+
+llgx_status llgx_self_tensor(llgx_handle h, double n00[3]) {
+    if (!h || !n00) return LLGX_E_ARG;
+    Ctx* c = (Ctx*)h;
+    if (!c->have_kernel) return c->fail(LLGX_E_STATE, "demag kernel not computed");
+    for (int i = 0; i < 3; ++i) n00[i] = c->n00[i];
+    return LLGX_OK;
+}
+
+llgx_status llgx_set_m(llgx_handle h, const void* M_dev) {
+    if (!h) return LLGX_E_ARG;
+    Ctx* c = (Ctx*)h;
+    if (!M_dev) return c->fail(LLGX_E_ARG, "null M");
+    HIPCHK(c, hipMemcpyAsync(c->M, M_dev, 3 * (size_t)c->ncell * c->tsz, hipMemcpyDeviceToDevice, c->stream));
+    c->have_m = true;
+    c->hist.clear();
+    c->fsal_valid = false;
+    return LLGX_OK;
+}
+
+llgx_status llgx_get_m(llgx_handle h, void* M_dev) {
+    if (!h) return LLGX_E_ARG;
+    Ctx* c = (Ctx*)h;
+    if (!M_dev) return c->fail(LLGX_E_ARG, "null M");
+    if (!c->have_m) return c->fail(LLGX_E_STATE, "magnetization not set");
+    HIPCHK(c, hipMemcpyAsync(M_dev, c->M, 3 * (size_t)c->ncell * c->tsz, hipMemcpyDeviceToDevice, c->stream));
+    return LLGX_OK;
+}
+
+static llgx_status field_call(llgx_handle h, const void* M_dev, void* out_dev, int mode) {
+    if (!h) return LLGX_E_ARG;
+    Ctx* c = (Ctx*)h;
+    if (!M_dev || !out_dev) return c->fail(LLGX_E_ARG, "null pointer");
+    if (!c->have_kernel) return c->fail(LLGX_E_STATE, "demag kernel not computed (llgx_precompute_demag)");
+    XinvOut out{nullptr, nullptr, nullptr};
+    if (mode == XINV_RHS)
+        out.f = out_dev;
+    else
+        out.h = out_dev;
+    if (c->prec == LLGX_F32)
+        return eval_exact<float>(c, plain<float>(M_dev), nullptr, mode, (const float*)M_dev, out);
+    return eval_exact<double>(c, plain<double>(M_dev), nullptr, mode, (const double*)M_dev, out);
+}
+
+llgx_status llgx_demag(llgx_handle h, const void* M_dev, void* H_dev) { return field_call(h, M_dev, H_dev, XINV_DEMAG); }
+llgx_status llgx_heff(llgx_handle h, const void* M_dev, void* H_dev) { return field_call(h, M_dev, H_dev, XINV_HEFF); }
+llgx_status llgx_rhs(llgx_handle h, const void* M_dev, void* F_dev) { return field_call(h, M_dev, F_dev, XINV_RHS); }
+
+llgx_status llgx_step(llgx_handle h, const llgx_stepper* s, llgx_step_info* info) {
+    if (!h) return LLGX_E_ARG;
+    Ctx* c = (Ctx*)h;
+    return c->prec == LLGX_F32 ? do_step<float>(c, s, info) : do_step<double>(c, s, info);
+}
+
+llgx_status llgx_run_fixed(llgx_handle h, const llgx_stepper* s, int64_t nsteps, int32_t use_graph,
+                           llgx_step_info* info) {
+    if (!h) return LLGX_E_ARG;
+    Ctx* c = (Ctx*)h;
+    if (nsteps < 0) return c->fail(LLGX_E_ARG, "nsteps < 0");
+    return c->prec == LLGX_F32 ? do_run_fixed<float>(c, s, nsteps, use_graph, info)
+                               : do_run_fixed<double>(c, s, nsteps, use_graph, info);
+}
+
+llgx_status llgx_run(llgx_handle h, const llgx_stepper* s, double t_end, double sample_dt, double* mavg_host,
+                     int64_t cap, int64_t* nsamples) {
+    if (!h) return LLGX_E_ARG;
+    Ctx* c = (Ctx*)h;
+    if (!s) return c->fail(LLGX_E_ARG, "null stepper");
+    return c->prec == LLGX_F32 ? do_run<float>(c, s, t_end, sample_dt, mavg_host, cap, nsamples)
+                               : do_run<double>(c, s, t_end, sample_dt, mavg_host, cap, nsamples);
+}
+
+llgx_status llgx_get_time(llgx_handle h, double* t, double* h_next) {
+    if (!h) return LLGX_E_ARG;
+    Ctx* c = (Ctx*)h;
+    if (t) *t = c->t;
+    if (h_next) *h_next = c->h_next;
+    return LLGX_OK;
+}
+
+llgx_status llgx_set_time(llgx_handle h, double t) {
+    if (!h) return LLGX_E_ARG;
+    Ctx* c = (Ctx*)h;
+    c->t = t;
+    c->hist.clear();
+    c->fsal_valid = false;
+    return LLGX_OK;
+}
+
+llgx_status llgx_counters(llgx_handle h, int64_t out[5]) {
+    if (!h || !out) return LLGX_E_ARG;
+    Ctx* c = (Ctx*)h;
+    out[0] = c->n_exact;
+    out[1] = c->n_extrap;
+    out[2] = c->n_acc;
+    out[3] = c->n_rej;
+    out[4] = c->n_forced;
+    return LLGX_OK;
+}
+
+}  // extern "C"

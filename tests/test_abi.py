@@ -1,0 +1,48 @@
+"""The C-ABI library loads and exports every function include/llgx.h declares
+(no compute calls: this runs without a GPU)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "llgx.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(llgx_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("llgx_create", "llgx_precompute_demag", "llgx_demag", "llgx_step", "llgx_run_fixed",
+                 "llgx_set_m", "llgx_get_m", "llgx_destroy", "llgx_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2107_06729_amd as llgx
+    lib = ctypes.CDLL(llgx.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert missing == []
+    # the binding wraps exactly the declared set
+    assert sorted(llgx.EXPORTED) == declared_functions()
+
+
+def test_defaults_and_argument_errors_without_gpu():
+    import paper_2107_06729_amd as llgx
+    s = llgx.stepper_defaults()
+    assert (s.h_min, s.h_max, s.c_min, s.c_max, s.e_max) == (1e-15, 3e-12, 0.01, 2.0, 1e-5)
+    # invalid problems are rejected before any device call
+    bad = llgx.make_problem({"n": (0, 2, 2), "cell": (1e-9,) * 3, "Ms": 8e5, "A": 1e-11, "alpha": 0.02})
+    h = llgx._H()
+    assert llgx._lib.llgx_create(ctypes.byref(bad), llgx.F32, 0, None, ctypes.byref(h)) == llgx.E_ARG
+    assert b"invalid problem" in llgx._lib.llgx_last_error(None)
+    ok = llgx.make_problem({"n": (4, 2, 2), "cell": (1e-9,) * 3, "Ms": 8e5, "A": 1e-11, "alpha": 0.02})
+    assert llgx._lib.llgx_create(ctypes.byref(ok), 7, 0, None, ctypes.byref(h)) == llgx.E_ARG
+    big = llgx.make_problem({"n": (4096, 2, 2), "cell": (1e-9,) * 3, "Ms": 8e5, "A": 1e-11, "alpha": 0.02})
+    assert llgx._lib.llgx_create(ctypes.byref(big), llgx.F32, 0, None, ctypes.byref(h)) == llgx.E_UNSUPPORTED
