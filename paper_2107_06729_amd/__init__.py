@@ -18,6 +18,11 @@ LIB_PATH = os.path.join(_HERE, "libllgx.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libllgx.so not built at {LIB_PATH}; run python -m paper_2107_06729_amd.build_lib")
 
+# PyTorch's HIP runtime must be loaded first: libllgx resolves libamdhip64 by
+# soname to that same instance, so torch streams and device pointers are valid
+# in the library (two HIP runtimes in one process do not share a device).
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 OK, E_ARG, E_STATE, E_HIP, E_NONFINITE, E_OOM, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6

@@ -17,6 +17,21 @@ LIB = os.path.join(PKG, "libllgx.so")
 SOURCES = ["demag.hip", "llg.hip", "llgx_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+
+def torch_lib_dir():
+    """Directory of the HIP runtime that PyTorch loads.  The library links that
+    runtime (not /opt/rocm's) so that torch's streams, device memory and ours
+    live in one HIP runtime instance of the process."""
+    import importlib.util
+    spec = importlib.util.find_spec("torch")
+    if spec is None or spec.origin is None:
+        raise RuntimeError("PyTorch (ROCm) is required to build libllgx")
+    d = os.path.join(os.path.dirname(spec.origin), "lib")
+    if not os.path.exists(os.path.join(d, "libamdhip64.so")):
+        raise RuntimeError(f"no libamdhip64.so in {d}")
+    return d
+
 ARCH = "gfx950"
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
@@ -49,7 +64,9 @@ def build(verbose=False, jobs=None):
     with ThreadPoolExecutor(jobs) as ex:
         list(ex.map(lambda c: _run(c, verbose), cmds))
     tmp = LIB + ".tmp"
-    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs, verbose)
+    tl = torch_lib_dir()
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-no-hip-rt", "-o", tmp] + objs
+         + ["-L", tl, "-l:libamdhip64.so", f"-Wl,-rpath,{tl}"], verbose)
     os.replace(tmp, LIB)
     return LIB
 
