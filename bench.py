@@ -1,0 +1,311 @@
+"""Benchmark of the demag-extrapolated explicit LLG hot path on one MI355X.
+
+One step = one RK4 iteration of the 256x256x16 Permalloy slab (5 nm cells,
+h = 250 fs) in FP32 with 4th-order extrapolation of the demagnetizing field:
+one exact FFT evaluation of Eq. (2) (5 kernels), three extrapolated sub-step
+fields (Eq. (6)) with their stage combinations, and the final Eq. (3) update.
+Steps are replayed from HIP graphs with no host synchronisation.
+
+value = demagnetizing-field evaluations per second delivered to the RK
+stages (4 per step: 1 exact + 3 extrapolated).  Also reported: exact Eq. (2)
+evaluations per second (FP32, FP64), simulated ns/h, the same step with full
+FP64 evaluation at every stage, the FP32 field and trajectory error against
+FP64, a per-kernel roofline from HIP events, and the CPU oracle's rate.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "demag-field evals/s & simulated ns/h at 256x256x16, FP32 vs FP64, err<=1e-5"
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = {
+    "xfwd": "demag.hip", "yfwd": "demag.hip", "zmul": "demag.hip", "yinv": "demag.hip", "xinv": "demag.hip",
+    "combine": "llg.hip", "extrap": "llg.hip", "final": "llg.hip",
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(n, tsz, p, nnz_comb=1, nnz_final=4):
+    """Algorithmic HBM bytes per launch of each kernel (one read of every input
+    and one write of every output; neighbour reads of M counted once)."""
+    nx, ny, nz = n
+    N = nx * ny * nz
+    Px = 2 * nx if nx > 1 else 1
+    Py = 2 * ny if ny > 1 else 1
+    Pz = 2 * nz if nz > 1 else 1
+    Kx = Px // 2 + 1 if Px > 1 else 1
+    Kyf = Py // 2 + 1 if Py > 1 else 1
+    Kzf = Pz // 2 + 1 if Pz > 1 else 1
+    cb = 2 * tsz
+    vec = 3 * N * tsz
+    sA = 3 * Kx * ny * nz * cb
+    sB = 3 * Kx * Py * nz * cb
+    kern = 6 * Kx * Kyf * Kzf * tsz
+    return {
+        "xfwd": vec + sA,                         # stage 1: M0 in, spectrum out
+        "yfwd": sA + sB,
+        "zmul": 2 * sB + kern,
+        "yinv": sB + sA,
+        "xinv": sA + vec + vec + vec,             # spectrum + M in; F and G out
+        "combine": (1 + nnz_comb) * vec + vec,
+        "extrap": (1 + (p + 1)) * vec + vec,      # M_k and p+1 stored fields in; F out
+        "final": (1 + nnz_final) * vec + vec,
+    }
+
+
+def source_hash(fname):
+    with open(os.path.join(ROOT, "paper_2107_06729_amd", "csrc", fname), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current source of the kernel (else None)."""
+    try:
+        d = json.load(open(PROFILE_TRAFFIC))
+    except (OSError, ValueError):
+        return None
+    e = d.get("kernels", {}).get(kernel)
+    if not e or e.get("source_sha256_16") != source_hash(KERNEL_SOURCES[kernel]):
+        return None
+    return e.get("bytes_per_launch")
+
+
+def timed_steps(sim, stepper, k, torch, stream):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run_fixed(stepper, k, use_graph=True)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(prob, M0, h, p, steps=2):
+    """The oracle as it stands (oracle.integrate.Integrator, single-threaded
+    NumPy/SciPy), steady-state RK4 + p-order extrapolation steps on the same
+    mesh.  The tensor is the oracle's own; the p history entries are zero
+    fields (the cost of a step does not depend on their values), so no
+    priming steps are spent."""
+    import numpy as np
+    from oracle import integrate, newell
+    Nf = newell.tensor_full(prob["n"], prob["cell"])
+    it = integrate.Integrator(prob, M0, method="RK4", h=h, adaptive=False, extrap=p, Nfull=Nf)
+    it.hist = [(-(p - j) * h, np.zeros_like(M0)) for j in range(p)]
+    it.step()  # warm caches and allocator
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        it.step()
+    dt = time.perf_counter() - t0
+    return 4 * steps / dt, dt, steps
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build runs the hot path on a single MI355X "
+              "(the multi-GPU decomposition is described in DESIGN.md, not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2107_06729_amd as llgx
+    import workloads
+
+    prob = workloads.SLAB_256x256x16
+    n = prob["n"]
+    Ms = prob["Ms"]
+    h = 250e-15
+    p = 4
+    K, W = args.steps, args.warmup
+    stream = torch.cuda.Stream()
+    dev = "cuda:0"
+    M0 = workloads.uniform_m(n, Ms, workloads.SLAB_256x256x16_DIR)
+    rec = {}
+
+    # ---- primary: FP32, RK4 + p=4, graph replay ---------------------------
+    log("setup fp32 ...")
+    s32 = llgx.Sim(prob, "f32", stream=stream)
+    t_setup = time.perf_counter()
+    s32.precompute_demag()
+    torch.cuda.synchronize()
+    rec["setup_s_f32"] = time.perf_counter() - t_setup
+    with torch.cuda.stream(stream):
+        s32.set_m(torch.as_tensor(M0, dtype=torch.float32, device=dev))
+    st32 = llgx.make_stepper("RK4", extrap=p, h=h)
+    log("warmup ...")
+    s32.run_fixed(st32, p + W, use_graph=True)   # p priming steps, graph capture
+    log(f"timed {K} steps ...")
+    dt = timed_steps(s32, st32, K, torch, stream)
+    ms_step = 1e3 * dt / K
+    evals_per_s = 4 * K / dt
+    sim_ns_per_h = h * 1e9 * K / dt * 3600.0
+    c = s32.counters()
+
+    # ---- per-kernel timing with HIP events on the library's stream --------
+    kprof_steps = min(K, 50)
+    s32.profile(True)
+    s32.run_fixed(st32, kprof_steps, use_graph=True)  # eager while profiling
+    prof = s32.profile_read()
+    s32.profile(False)
+    kb = kernel_bytes(n, 4, p)
+    per_kernel = {}
+    for k, (ms, cnt) in prof.items():
+        if cnt == 0:
+            continue
+        avg_ms = ms / cnt
+        e = {"avg_us": 1e3 * avg_ms, "launches_per_step": cnt / kprof_steps,
+             "share_of_step": (ms / kprof_steps) / ms_step}
+        if k in kb:
+            e["alg_bytes"] = kb[k]
+            e["gbs"] = kb[k] / (avg_ms * 1e-3) / 1e9
+        per_kernel[k] = e
+    dom = max((k for k in per_kernel if k in kb),
+              key=lambda k: per_kernel[k]["avg_us"] * per_kernel[k]["launches_per_step"])
+    dk = per_kernel[dom]
+    traffic = measured_traffic(dom)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+                "alg_bytes_per_launch": dk["alg_bytes"], "avg_launch_us": dk["avg_us"]}
+    step_alg = sum(kb[k] * per_kernel[k]["launches_per_step"] for k in per_kernel if k in kb)
+    rec["step_alg_bytes"] = step_alg
+    rec["step_gbs"] = step_alg / (ms_step * 1e-3) / 1e9
+    rec["step_roofline_frac"] = rec["step_gbs"] / HBM_PEAK_GBS
+
+    extras = {}
+    if not args.no_extras:
+        # ---- exact Eq. (2) throughput, FP32 and FP64 ----------------------
+        Mr = workloads.random_m(n, Ms, workloads.SLAB_256x256x16_SEED)
+        s64 = llgx.Sim(prob, "f64", stream=stream)
+        s64.precompute_demag()
+        with torch.cuda.stream(stream):
+            M32 = torch.as_tensor(Mr, dtype=torch.float32, device=dev)
+            M64 = torch.as_tensor(Mr, dtype=torch.float64, device=dev)
+            for sim_, Mt, tag in ((s32, M32, "f32"), (s64, M64, "f64")):
+                sim_.demag(Mt)
+                torch.cuda.synchronize()
+                R = 100
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(R):
+                    Hd = sim_.demag(Mt)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                extras[f"exact_evals_per_s_{tag}"] = R / (e0.elapsed_time(e1) * 1e-3)
+            H32 = s32.demag(M32).double()
+            H64 = s64.demag(M64)
+            torch.cuda.synchronize()
+        extras["field_err_f32_vs_f64_over_Ms"] = float((H32 - H64).abs().max().item() / Ms)
+        extras["exact_eval_speedup_f32_over_f64"] = extras["exact_evals_per_s_f32"] / extras["exact_evals_per_s_f64"]
+
+        # ---- the same step with full FP64 evaluation at every stage --------
+        log("fp64 full ...")
+        with torch.cuda.stream(stream):
+            s64.set_m(torch.as_tensor(M0, dtype=torch.float64, device=dev))
+        st64 = llgx.make_stepper("RK4", extrap=None, h=h)
+        s64.run_fixed(st64, p + W, use_graph=True)
+        dt64 = timed_steps(s64, st64, K, torch, stream)
+        extras["fp64_full_evals_per_s"] = 4 * K / dt64
+        extras["fp64_full_sim_ns_per_h"] = h * 1e9 * K / dt64 * 3600.0
+        extras["fp64_full_ms_per_step"] = 1e3 * dt64 / K
+        extras["speedup_f32_extrap_over_f64_full"] = extras["fp64_full_ms_per_step"] / ms_step
+        # trajectory after the same number of steps from the same start
+        nsteps = p + W + K + kprof_steps
+        left = nsteps - (p + W + K)
+        s64.run_fixed(st64, left, use_graph=True)
+        with torch.cuda.stream(stream):
+            Ma = s32.get_m().double()
+            Mb = s64.get_m()
+        torch.cuda.synchronize()
+        d = (Ma - Mb)
+        extras["traj_steps"] = nsteps
+        extras["traj_max_err_over_Ms"] = float(d.abs().max().item() / Ms)
+        extras["traj_eps_eq7_map"] = float(d.pow(2).sum(0).sqrt().mean().item() / Ms)
+        extras["traj_mean_m_f32"] = [float(v) for v in Ma.reshape(3, -1).mean(1).cpu()]
+
+        # ---- adaptive Dormand-Prince, FP32 + p=4 vs FP64 full (short window) ---
+        log("adaptive rkdp54 ...")
+        win = 5e-12
+        for tag, prec, ex in (("f32_p4", "f32", 4), ("f64_full", "f64", None)):
+            sa = llgx.Sim(prob, prec, stream=stream)
+            sa.precompute_demag()
+            with torch.cuda.stream(stream):
+                sa.set_m(torch.as_tensor(M0, dtype=torch.float32 if prec == "f32" else torch.float64, device=dev))
+            sta = llgx.make_stepper("RKDP54", extrap=ex, h=1e-13, adaptive=True)
+            sa.run(sta, 1e-12, 0)  # warm-up window
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            t_start, _ = sa.time()
+            sa.run(sta, t_start + win, 0)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            cc = sa.counters()
+            extras[f"rkdp54_{tag}_sim_ns_per_h"] = win * 1e9 / wall * 3600.0
+            extras[f"rkdp54_{tag}_counters"] = cc
+            sa.close()
+        extras["rkdp54_speedup_f32_p4_over_f64_full"] = (extras["rkdp54_f32_p4_sim_ns_per_h"]
+                                                          / extras["rkdp54_f64_full_sim_ns_per_h"])
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        v, secs, nst = cpu_baseline(prob, M0, h, p)
+        cpu = {"value": v, "unit": "evals/s", "cores": 1, "kind": "oracle",
+               "sample": f"{nst} steady-state RK4+p{p} steps (4 field evaluations each) of the 256x256x16 "
+                         f"slab, oracle.integrate.Integrator (NumPy/SciPy FP64, one thread), {secs:.1f} s; "
+                         f"tensor setup and one warm-up step untimed"}
+
+    out = {
+        "metric": METRIC,
+        "value": evals_per_s,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "Permalloy slab 256x256x16 cells of 5 nm (Ms 8e5 A/m, A 13 pJ/m, alpha 0.02), "
+                               "H_a (-20,1,0) kA/m, uniform start along (1,0.25,0.1); RK4 h=250 fs with "
+                               "4th-order demag extrapolation (1 exact + 3 extrapolated fields per step), FP32, "
+                               "graph-replayed steps",
+                   "mesh": list(n), "method": "RK4", "extrap_p": p, "h_s": h, "precision": "f32",
+                   "parallelism": "single GPU"},
+        "sim_ns_per_h": sim_ns_per_h,
+        "exact_evals_per_step": 1,
+        "extrap_evals_per_step": 3,
+        "counters": c,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": per_kernel,
+    }
+    out.update(rec)
+    out.update(extras)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

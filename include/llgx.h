@@ -171,6 +171,24 @@ llgx_status llgx_run_fixed(llgx_handle h, const llgx_stepper* s, int64_t nsteps,
 llgx_status llgx_run(llgx_handle h, const llgx_stepper* s, double t_end, double sample_dt,
                      double* mavg_host, int64_t cap, int64_t* nsamples);
 
+/* Per-kernel timing.  With profiling enabled, every kernel the handle
+ * launches eagerly is bracketed by HIP events on the handle's stream (graph
+ * replay is disabled meanwhile).  llgx_profile_read synchronises, returns the
+ * summed milliseconds and launch counts per kernel kind since the last read,
+ * and resets them. */
+#define LLGX_K_XFWD 0    /* stage combination + forward real-to-complex x pass */
+#define LLGX_K_YFWD 1    /* forward y pass                                    */
+#define LLGX_K_ZMUL 2    /* z forward, k-space tensor product, z inverse      */
+#define LLGX_K_YINV 3    /* inverse y pass                                    */
+#define LLGX_K_XINV 4    /* inverse x pass fused with H_eff and the LLG RHS   */
+#define LLGX_K_COMBINE 5 /* stage input M_k = M0 + h sum b F (Eq. 4)          */
+#define LLGX_K_EXTRAP 6  /* Eq. (6) field + H_eff + LLG RHS at a sub-step     */
+#define LLGX_K_FINAL 7   /* Eq. (3) update and error-norm partials            */
+#define LLGX_K_OTHER 8   /* reductions, renormalisation                       */
+#define LLGX_K_COUNT 9
+llgx_status llgx_profile(llgx_handle h, int32_t enable);
+llgx_status llgx_profile_read(llgx_handle h, double ms[LLGX_K_COUNT], int64_t launches[LLGX_K_COUNT]);
+
 /* Time, proposed next step and counters of the handle. */
 llgx_status llgx_get_time(llgx_handle h, double* t, double* h_next);
 llgx_status llgx_set_time(llgx_handle h, double t);

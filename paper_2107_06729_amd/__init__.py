@@ -3,8 +3,8 @@
 Every computation runs in the HIP library; this module converts Python
 values to the C structs, passes torch device pointers and the current HIP
 stream, and turns status codes into exceptions.  Importing it without the
-built library raises ImportError (build with ``python -m
-paper_2107_06729_amd.build_lib``).
+built library raises ImportError (build with
+``python paper_2107_06729_amd/build_lib.py``).
 
 Names mirror the C ABI without the ``llgx_`` prefix; ``Sim`` bundles a handle.
 """
@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libllgx.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"libllgx.so not built at {LIB_PATH}; run python -m paper_2107_06729_amd.build_lib")
+    raise ImportError(f"libllgx.so not built at {LIB_PATH}; run python paper_2107_06729_amd/build_lib.py")
 
 # PyTorch's HIP runtime must be loaded first: libllgx resolves libamdhip64 by
 # soname to that same instance, so torch streams and device pointers are valid
@@ -80,7 +80,10 @@ _sig = {
     "llgx_get_time": (_S, [_H, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "llgx_set_time": (_S, [_H, ctypes.c_double]),
     "llgx_counters": (_S, [_H, ctypes.POINTER(ctypes.c_int64)]),
+    "llgx_profile": (_S, [_H, ctypes.c_int32]),
+    "llgx_profile_read": (_S, [_H, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
 }
+KERNELS = ("xfwd", "yfwd", "zmul", "yinv", "xinv", "combine", "extrap", "final", "other")
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
     _f.restype = _res
@@ -264,6 +267,15 @@ class Sim:
 
     def set_time(self, t):
         _check(_lib.llgx_set_time(self._h, float(t)), self._h)
+
+    def profile(self, enable=True):
+        _check(_lib.llgx_profile(self._h, int(bool(enable))), self._h)
+
+    def profile_read(self):
+        ms = (ctypes.c_double * len(KERNELS))()
+        cnt = (ctypes.c_int64 * len(KERNELS))()
+        _check(_lib.llgx_profile_read(self._h, ms, cnt), self._h)
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNELS)}
 
     def counters(self):
         out = (ctypes.c_int64 * 5)()

@@ -1,6 +1,6 @@
 """Build libllgx.so (the C-ABI library of include/llgx.h) for gfx950 with hipcc.
 
-Usage: python -m paper_2107_06729_amd.build_lib   (or __graft_entry__.build()).
+Usage: python paper_2107_06729_amd/build_lib.py   (or __graft_entry__.build()).
 Objects go to paper_2107_06729_amd/_build/, the library next to this file.
 """
 

@@ -84,6 +84,16 @@ struct Ctx {
 
     std::map<GraphKey, hipGraphExec_t> graphs;
 
+    // per-kernel event timing (eager launches only)
+    bool prof = false;
+    struct Mark {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks;
+    std::vector<hipEvent_t> spare;
+    int open_kind = -1;
+
     llgx_status fail(llgx_status code, const char* fmt, ...) {
         char buf[512];
         va_list ap;
@@ -112,6 +122,43 @@ static llgx_status dalloc(Ctx* c, void** p, size_t bytes) {
     }
     return LLGX_OK;
 }
+
+static hipEvent_t take_event(Ctx* c) {
+    if (!c->spare.empty()) {
+        hipEvent_t e = c->spare.back();
+        c->spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// bracket the next launch with events when profiling
+struct ProfScope {
+    Ctx* c;
+    hipEvent_t a = nullptr;
+    int kind;
+    ProfScope(Ctx* c_, int kind_) : c(c_), kind(kind_) {
+        if (c->prof) {
+            a = take_event(c);
+            if (a) (void)hipEventRecord(a, c->stream);
+        }
+    }
+    ~ProfScope() {
+        if (a) {
+            hipEvent_t b = take_event(c);
+            if (b) {
+                (void)hipEventRecord(b, c->stream);
+                c->marks.push_back({kind, a, b});
+            } else {
+                c->spare.push_back(a);
+            }
+        }
+    }
+};
+
+#define PROF(kind) ProfScope prof_scope_(c, kind)
 
 // twiddle table e^{-2 pi i m/L}, m < L, built in double
 template <typename T>
@@ -172,26 +219,37 @@ static llgx_status eval_exact(Ctx* c, const Combo<T>& in, T* mk_out, int mode, c
     cx<T>* A = (cx<T>*)c->specA;
     const cx<T>* twL = table<T>(c, c->LX, false);
     const cx<T>* twP = table<T>(c, c->Px, false);
-    HIPCHK(c, launch_xfwd<T>(s, c->LX, in, mk_out, c->nx, 3L * c->ny * c->nz, A, c->SX, twL, twP));
+    {
+        PROF(LLGX_K_XFWD);
+        HIPCHK(c, launch_xfwd<T>(s, c->LX, in, mk_out, c->nx, 3L * c->ny * c->nz, A, c->SX, twL, twP));
+    }
     cx<T>* work = A;
     int nyrows = c->ny;
     if (c->Py > 1) {
         cx<T>* B = (cx<T>*)c->specB;
         const long sa = (long)c->nz * c->ny * c->SX, sb = (long)c->nz * c->Py * c->SX;
+        PROF(LLGX_K_YFWD);
         HIPCHK(c, launch_colfft<T>(s, c->Py, false, A, sa, (long)c->ny * c->SX, c->SX, c->ny, B, sb,
                                    (long)c->Py * c->SX, c->SX, c->Py, c->Kx, c->nz, 3, table<T>(c, c->Py, false)));
         work = B;
         nyrows = c->Py;
     }
-    HIPCHK(c, launch_zmul<T>(s, c->Pz, work, c->SX, c->Kx, c->nz, nyrows, c->Py, c->Pz, (const T*)c->kfold, c->Kyf,
-                             c->Kzf, table<T>(c, c->Pz, false)));
+    {
+        PROF(LLGX_K_ZMUL);
+        HIPCHK(c, launch_zmul<T>(s, c->Pz, work, c->SX, c->Kx, c->nz, nyrows, c->Py, c->Pz, (const T*)c->kfold,
+                                 c->Kyf, c->Kzf, table<T>(c, c->Pz, false)));
+    }
     if (c->Py > 1) {
         cx<T>* B = (cx<T>*)c->specB;
         const long sa = (long)c->nz * c->ny * c->SX, sb = (long)c->nz * c->Py * c->SX;
+        PROF(LLGX_K_YINV);
         HIPCHK(c, launch_colfft<T>(s, c->Py, true, B, sb, (long)c->Py * c->SX, c->SX, c->Py, A, sa,
                                    (long)c->ny * c->SX, c->SX, c->ny, c->Kx, c->nz, 3, table<T>(c, c->Py, false)));
     }
-    HIPCHK(c, launch_xinv<T>(s, c->LX, mode, A, c->SX, Mrhs, phys<T>(c), out, twL, twP));
+    {
+        PROF(LLGX_K_XINV);
+        HIPCHK(c, launch_xinv<T>(s, c->LX, mode, A, c->SX, Mrhs, phys<T>(c), out, twL, twP));
+    }
     return LLGX_OK;
 }
 
@@ -348,7 +406,10 @@ static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
             cb.nf++;
         }
         if (pl.extrap) {
-            HIPCHK(c, launch_combine<T>(c->stream, 3 * c->ncell, cb, (T*)c->Mk));
+            {
+                PROF(LLGX_K_COMBINE);
+                HIPCHK(c, launch_combine<T>(c->stream, 3 * c->ncell, cb, (T*)c->Mk));
+            }
             Extrap<T> ex{};
             const std::vector<double> w = lagrange(nodes, tab->c[k] * h);
             ex.n = (int)w.size();
@@ -356,6 +417,7 @@ static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
                 ex.g[i] = (const T*)c->G[slots[i]];
                 ex.w[i] = (T)w[i];
             }
+            PROF(LLGX_K_EXTRAP);
             HIPCHK(c, launch_extrap_rhs<T>(c->stream, (const T*)c->Mk, ex, phys<T>(c), (T*)c->F[k]));
         } else {
             XinvOut out{nullptr, c->F[k], nullptr};
@@ -378,8 +440,14 @@ static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
             es.n++;
         }
     }
-    HIPCHK(c, launch_final<T>(c->stream, c->ncell, sol, es, 1.0 / c->p.Ms, (T*)c->Mnew, c->parts, c->nparts));
-    if (pl.want_err) HIPCHK(c, launch_reduce_max(c->stream, c->parts, c->nparts, c->scal));
+    {
+        PROF(LLGX_K_FINAL);
+        HIPCHK(c, launch_final<T>(c->stream, c->ncell, sol, es, 1.0 / c->p.Ms, (T*)c->Mnew, c->parts, c->nparts));
+    }
+    if (pl.want_err) {
+        PROF(LLGX_K_OTHER);
+        HIPCHK(c, launch_reduce_max(c->stream, c->parts, c->nparts, c->scal));
+    }
     return LLGX_OK;
 }
 
@@ -485,7 +553,10 @@ static llgx_status do_step(Ctx* c, const llgx_stepper* s, llgx_step_info* info) 
     }
     st = commit<T>(c, pl, h);
     if (st) return st;
-    if (s->renormalize) HIPCHK(c, launch_renorm<T>(c->stream, c->ncell, (T*)c->M, c->p.Ms));
+    if (s->renormalize) {
+        PROF(LLGX_K_OTHER);
+        HIPCHK(c, launch_renorm<T>(c->stream, c->ncell, (T*)c->M, c->p.Ms));
+    }
     c->h_next = s->adaptive ? h_next : h;
     c->n_rej += rejected;
     c->n_forced += forced;
@@ -513,7 +584,7 @@ static llgx_status do_run_fixed(Ctx* c, const llgx_stepper* s, int64_t nsteps, i
         const bool steady = (p < 0 && !tab->fsal) || (p >= 0 && (int)c->hist.size() == p) ||
                             (p < 0 && tab->fsal && s->renormalize);
         // the legacy default stream cannot be captured: replay needs a created stream
-        if (!use_graph || !steady || c->stream == nullptr) {
+        if (!use_graph || !steady || c->stream == nullptr || c->prof) {
             st = do_step<T>(c, s, info);
             if (st) return st;
             continue;
@@ -630,6 +701,11 @@ static llgx_status do_run(Ctx* c, const llgx_stepper* s, double t_end, double sa
 }
 
 static void release(Ctx* c) {
+    for (auto& m : c->marks) {
+        (void)hipEventDestroy(m.a);
+        (void)hipEventDestroy(m.b);
+    }
+    for (auto e : c->spare) (void)hipEventDestroy(e);
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
     void* ptrs[] = {c->kfold, c->specA, c->specB, c->M, c->Mnew, c->Mk, c->parts, c->scal, c->octant};
@@ -858,6 +934,32 @@ llgx_status llgx_run(llgx_handle h, const llgx_stepper* s, double t_end, double 
     if (!s) return c->fail(LLGX_E_ARG, "null stepper");
     return c->prec == LLGX_F32 ? do_run<float>(c, s, t_end, sample_dt, mavg_host, cap, nsamples)
                                : do_run<double>(c, s, t_end, sample_dt, mavg_host, cap, nsamples);
+}
+
+llgx_status llgx_profile(llgx_handle h, int32_t enable) {
+    if (!h) return LLGX_E_ARG;
+    ((Ctx*)h)->prof = enable != 0;
+    return LLGX_OK;
+}
+
+llgx_status llgx_profile_read(llgx_handle h, double ms[LLGX_K_COUNT], int64_t launches[LLGX_K_COUNT]) {
+    if (!h || !ms || !launches) return LLGX_E_ARG;
+    Ctx* c = (Ctx*)h;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < LLGX_K_COUNT; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    for (auto& m : c->marks) {
+        float t = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&t, m.a, m.b));
+        ms[m.kind] += t;
+        launches[m.kind]++;
+        c->spare.push_back(m.a);
+        c->spare.push_back(m.b);
+    }
+    c->marks.clear();
+    return LLGX_OK;
 }
 
 llgx_status llgx_get_time(llgx_handle h, double* t, double* h_next) {
