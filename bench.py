@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = {
     "xfwd": "demag.hip", "yfwd": "demag.hip", "zmul": "demag.hip", "yinv": "demag.hip", "xinv": "demag.hip",
-    "combine": "llg.hip", "extrap": "llg.hip", "final": "llg.hip",
+    "combine": "llg.hip", "extrap": "llg.hip", "final": "llg.hip", "epoly": "llg.hip",
 }
 
 
@@ -62,8 +62,12 @@ def kernel_bytes(n, tsz, p, nnz_comb=1, nnz_final=4):
         "yinv": sB + sA,
         "xinv": sA + vec + vec + vec,             # spectrum + M in; F and G out
         "combine": (1 + nnz_comb) * vec + vec,
-        "extrap": (1 + (p + 1)) * vec + vec,      # M_k and p+1 stored fields in; F out
-        "final": (1 + nnz_final) * vec + vec,
+        "extrap": 3 * vec,                        # M_k and one Eq. (6) field in; F out
+        # last sub-step fused with Eq. (3): M_k, its Eq. (6) field, M0 and
+        # F_1..F_{S-1} in; M out (F_S stays in registers)
+        "final": (2 + 1 + (nnz_final - 1)) * vec + vec,
+        # Eq. (6) at the distinct sub-step times: p+1 stored fields in, n_times out
+        "epoly": (p + 1) * vec + 2 * vec,
     }
 
 
@@ -191,6 +195,22 @@ def main():
     rec["step_alg_bytes"] = step_alg
     rec["step_gbs"] = step_alg / (ms_step * 1e-3) / 1e9
     rec["step_roofline_frac"] = rec["step_gbs"] / HBM_PEAK_GBS
+
+    # practical HBM reference: a plain device copy of 256 MiB (torch), and the
+    # calibration kernel for the FETCH_SIZE / WRITE_SIZE counters
+    with torch.cuda.stream(stream):
+        csrc = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        cdst = torch.empty_like(csrc)
+        cdst.copy_(csrc)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(10):
+            cdst.copy_(csrc)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        rec["copy_256MiB_gbs"] = 10 * 2 * csrc.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        del csrc, cdst
 
     extras = {}
     if not args.no_extras:

@@ -182,10 +182,12 @@ llgx_status llgx_run(llgx_handle h, const llgx_stepper* s, double t_end, double 
 #define LLGX_K_YINV 3    /* inverse y pass                                    */
 #define LLGX_K_XINV 4    /* inverse x pass fused with H_eff and the LLG RHS   */
 #define LLGX_K_COMBINE 5 /* stage input M_k = M0 + h sum b F (Eq. 4)          */
-#define LLGX_K_EXTRAP 6  /* Eq. (6) field + H_eff + LLG RHS at a sub-step     */
-#define LLGX_K_FINAL 7   /* Eq. (3) update and error-norm partials            */
-#define LLGX_K_OTHER 8   /* reductions, renormalisation                       */
-#define LLGX_K_COUNT 9
+#define LLGX_K_EXTRAP 6  /* Eq. (6) sub-step field + H_eff + LLG RHS          */
+#define LLGX_K_FINAL 7   /* Eq. (3) update and error-norm partials (fused with
+                            the last sub-step when it is extrapolated)       */
+#define LLGX_K_EPOLY 8   /* Eq. (6) fields for every distinct sub-step time   */
+#define LLGX_K_OTHER 9   /* reductions, renormalisation                       */
+#define LLGX_K_COUNT 10
 llgx_status llgx_profile(llgx_handle h, int32_t enable);
 llgx_status llgx_profile_read(llgx_handle h, double ms[LLGX_K_COUNT], int64_t launches[LLGX_K_COUNT]);
 

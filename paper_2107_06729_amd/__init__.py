@@ -83,7 +83,7 @@ _sig = {
     "llgx_profile": (_S, [_H, ctypes.c_int32]),
     "llgx_profile_read": (_S, [_H, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
 }
-KERNELS = ("xfwd", "yfwd", "zmul", "yinv", "xinv", "combine", "extrap", "final", "other")
+KERNELS = ("xfwd", "yfwd", "zmul", "yinv", "xinv", "combine", "extrap", "final", "epoly", "other")
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
     _f.restype = _res

@@ -18,6 +18,7 @@
 
 #include "kernels.hpp"
 #include "physics.hpp"
+#include "tile_io.hpp"
 
 namespace llgx {
 
@@ -31,8 +32,8 @@ constexpr int col_tile(int L) {
 }
 template <typename T>
 constexpr int zmul_tile(int L) {
-    return sizeof(T) == 4 ? (L <= 128 ? 16 : L == 256 ? 8 : L == 512 ? 4 : L == 1024 ? 2 : 1)
-                          : (L <= 128 ? 8 : L == 256 ? 4 : L == 512 ? 2 : 1);
+    return sizeof(T) == 4 ? (L <= 64 ? 16 : L == 128 ? 8 : L == 256 ? 4 : 2)
+                          : (L <= 64 ? 8 : L == 128 ? 4 : L == 256 ? 2 : 1);
 }
 template <typename T>
 constexpr int xfwd_rows(int LX) {
@@ -75,27 +76,70 @@ __global__ __launch_bounds__(NT) void k_xfwd(Combo<T> in, T* __restrict__ mk_out
         return;
     } else {
         constexpr int CS = LX + 1;
+        constexpr int TOT = ROWS * LX, PER = (TOT + NT - 1) / NT;
         __shared__ C buf[ROWS * CS];
-        for (int e = threadIdx.x; e < ROWS * LX; e += NT) {
+        __shared__ C twl[LX];
+        __shared__ C twp[LX + 1];
+        TwStage<T, LX, NT> tw1;
+        TwStage<T, LX + 1, NT> tw2;
+        tw1.fetch(twL);
+        tw2.fetch(twP);
+        // element pair (x[2i], x[2i+1]) of row g; staged: all loads of one
+        // operand are issued before they are used
+        C v[PER];
+        long off[PER];
+        int x0[PER];
+        bool ok[PER];
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int e = threadIdx.x + m * NT;
             const int r = e / LX, i = e - r * LX;
             const long g = row0 + r;
-            C v{T(0), T(0)};
-            if (g < nrows) {
-                const long off = g * nin;
-                const int x0 = 2 * i;
-                if (x0 < nin) {
-                    v.x = combo_at(in, off + x0);
-                    if (mk_out) mk_out[off + x0] = v.x;
-                }
-                if (x0 + 1 < nin) {
-                    v.y = combo_at(in, off + x0 + 1);
-                    if (mk_out) mk_out[off + x0 + 1] = v.y;
+            x0[m] = 2 * i;
+            off[m] = g * nin + 2 * i;
+            ok[m] = (TOT % NT == 0 || e < TOT) && g < nrows && 2 * i < nin;
+        }
+        const bool pairs = (nin & 1) == 0;  // rows start 8/16-byte aligned: load both reals at once
+        auto load2 = [&](const T* __restrict__ p, int m) -> C {
+            C w{T(0), T(0)};
+            if (ok[m]) {
+                if (pairs) {
+                    w = *(const C*)(p + off[m]);
+                } else {
+                    w.x = p[off[m]];
+                    if (x0[m] + 1 < nin) w.y = p[off[m] + 1];
                 }
             }
-            buf[r * CS + i] = v;
+            return w;
+        };
+#pragma unroll
+        for (int m = 0; m < PER; ++m) v[m] = load2(in.base, m);
+        for (int l = 0; l < in.nf; ++l) {
+            C w[PER];
+#pragma unroll
+            for (int m = 0; m < PER; ++m) w[m] = load2(in.f[l], m);
+            const T cf = in.coef[l];
+#pragma unroll
+            for (int m = 0; m < PER; ++m) {
+                v[m].x += cf * w[m].x;
+                v[m].y += cf * w[m].y;
+            }
         }
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int e = threadIdx.x + m * NT;
+            if (TOT % NT != 0 && e >= TOT) continue;
+            const int r = e / LX, i = e - r * LX;
+            buf[r * CS + i] = v[m];
+            if (mk_out && ok[m]) {
+                mk_out[off[m]] = v[m].x;
+                if (x0[m] + 1 < nin) mk_out[off[m] + 1] = v[m].y;
+            }
+        }
+        tw1.put(twl);
+        tw2.put(twp);
         __syncthreads();
-        lds_fft<T, LX, false, Cols<ROWS, CS, 1, false>, NT>(buf, twL);
+        lds_fft<T, LX, false, Cols<ROWS, CS, 1, false>, NT>(buf, twl);
         for (int e = threadIdx.x; e < ROWS * (LX + 1); e += NT) {
             const int r = e / (LX + 1), k = e - r * (LX + 1);
             const long g = row0 + r;
@@ -104,7 +148,7 @@ __global__ __launch_bounds__(NT) void k_xfwd(Combo<T> in, T* __restrict__ mk_out
             const C zc = cconj(buf[r * CS + ((LX - k) & (LX - 1))]);
             const C E{(zk.x + zc.x) * T(0.5), (zk.y + zc.y) * T(0.5)};
             const C O{(zk.y - zc.y) * T(0.5), (zc.x - zk.x) * T(0.5)};  // -i (zk - zc)/2
-            spec[g * SX + k] = cadd(E, cmul(O, twP[k]));
+            spec[g * SX + k] = cadd(E, cmul(O, twp[k]));
         }
     }
 }
@@ -121,6 +165,7 @@ __global__ __launch_bounds__(NT) void k_xinv(const cx<T>* __restrict__ spec, int
     constexpr int LXE = LX > 0 ? LX : 1;
     constexpr int CS = LXE + 1;
     __shared__ C buf[3 * ROWS * CS];
+    __shared__ C twl[LXE];
     const long nrow = (long)ph.ny * ph.nz;
     const long N = nrow * ph.nx;
     const long row0 = (long)blockIdx.x * ROWS;
@@ -132,23 +177,41 @@ __global__ __launch_bounds__(NT) void k_xinv(const cx<T>* __restrict__ spec, int
         }
         __syncthreads();
     } else {
-        for (int e = threadIdx.x; e < 3 * ROWS * LX; e += NT) {
+        constexpr int TOT = 3 * ROWS * LX, PER = (TOT + NT - 1) / NT;
+        TwStage<T, LX, NT> tw1;
+        tw1.fetch(twL);
+        // post-twiddles of this thread's k (fetched with the spectrum)
+        C wk[PER];
+        C xa[PER], xb[PER];
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int e = threadIdx.x + m * NT;
             const int lr = e / LX, k = e - lr * LX;
             const int r = lr / 3, c = lr - 3 * r;
             const long g = row0 + r;
-            C Z{T(0), T(0)};
-            if (g < nrow) {
+            xa[m] = C{T(0), T(0)};
+            xb[m] = C{T(0), T(0)};
+            wk[m] = twP[k];
+            if ((TOT % NT == 0 || e < TOT) && g < nrow) {
                 const cx<T>* row = spec + (c * nrow + g) * SX;
-                const C xk = row[k];
-                const C xc = cconj(row[LX - k]);
-                const C S = cadd(xk, xc);
-                const C wd = cmulc(csub(xk, xc), twP[k]);
-                Z = C{S.x - wd.y, S.y + wd.x};
+                xa[m] = row[k];
+                xb[m] = row[LX - k];
             }
-            buf[lr * CS + k] = Z;
         }
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int e = threadIdx.x + m * NT;
+            if (TOT % NT != 0 && e >= TOT) continue;
+            const int lr = e / LX, k = e - lr * LX;
+            const C xk = xa[m];
+            const C xc = cconj(xb[m]);
+            const C S = cadd(xk, xc);
+            const C wd = cmulc(csub(xk, xc), wk[m]);
+            buf[lr * CS + k] = C{S.x - wd.y, S.y + wd.x};
+        }
+        tw1.put(twl);
         __syncthreads();
-        lds_fft<T, LX, true, Cols<3 * ROWS, CS, 1, false>, NT>(buf, twL);
+        lds_fft<T, LX, true, Cols<3 * ROWS, CS, 1, false>, NT>(buf, twl);
     }
     const int nx = ph.nx;
     for (int e = threadIdx.x; e < ROWS * nx; e += NT) {
@@ -203,21 +266,17 @@ __global__ __launch_bounds__(NT) void k_colfft(const cx<T>* __restrict__ src, lo
                                                int n_out, int Kx, const cx<T>* __restrict__ tw) {
     using C = cx<T>;
     __shared__ C buf[L * TK];
+    __shared__ C twl[L];
     const int kx0 = blockIdx.x * TK;
     const cx<T>* sp = src + blockIdx.z * s_cs + blockIdx.y * s_os + kx0;
-    for (int e = threadIdx.x; e < L * TK; e += NT) {
-        const int i = e / TK, col = e - i * TK;
-        C v{T(0), T(0)};
-        if (i < n_in && kx0 + col < Kx) v = sp[i * s_is + col];
-        buf[e] = v;
-    }
+    TwStage<T, L, NT> tws;
+    tws.fetch(tw);
+    load_tile<T, L, TK, NT>(buf, sp, s_is, n_in, Kx - kx0);
+    tws.put(twl);
     __syncthreads();
-    lds_fft<T, L, INV, Cols<TK, 1, TK, true>, NT>(buf, tw);
+    lds_fft<T, L, INV, Cols<TK, 1, TK, true>, NT>(buf, twl);
     cx<T>* dp = dst + blockIdx.z * d_cs + blockIdx.y * d_os + kx0;
-    for (int e = threadIdx.x; e < n_out * TK; e += NT) {
-        const int i = e / TK, col = e - i * TK;
-        if (kx0 + col < Kx) dp[i * d_is + col] = buf[e];
-    }
+    store_tile<T, L, TK, NT>(dp, d_is, buf, n_out, Kx - kx0);
 }
 
 // ------------------------------------------------------------------------
@@ -225,50 +284,95 @@ __global__ __launch_bounds__(NT) void k_colfft(const cx<T>* __restrict__ src, lo
 // symmetric, stored for |ky| <= Py/2, |kz| <= Pz/2; the components odd in y
 // (xy, yz) change sign for ky > Py/2, those odd in z (xz, yz) for kz > Pz/2),
 // z inverse.  In place on rows z < nz of the [3][nz][nyrows][SX] buffer.
+// One workgroup takes the rows ky = q and ky = Py - q, which share the folded
+// kernel, so every folded value is read from memory once.
 template <typename T, int LZ, int TK>
 __global__ __launch_bounds__(NT) void k_zmul(cx<T>* __restrict__ buf, int SX, int Kx, int nz, int nyrows, int Py,
                                              int Pz, const T* __restrict__ kfold, int Kyf, int Kzf,
                                              const cx<T>* __restrict__ tw) {
     using C = cx<T>;
-    constexpr int NC = 3 * TK;
+    using P = typename Pack<T>::type;
+    constexpr int PN = Pack<T>::N;
+    constexpr int NC = 6 * TK;              // 2 rows x 3 components x TK columns
+    constexpr int KZF = LZ / 2 + 1;         // folded kz extent (LZ = Pz)
+    constexpr int PR = TK / PN, TOT = LZ * 6 * PR, PER = (TOT + NT - 1) / NT;
+    constexpr int KTOT = KZF * TK * 6, KPER = (KTOT + NT - 1) / NT;
+    static_assert(TK % PN == 0, "tile width");
     __shared__ C lb[LZ * NC];
+    __shared__ T kl[KZF * 6 * TK];
+    __shared__ C twl[LZ > 1 ? LZ : 1];
     const int kx0 = blockIdx.x * TK;
-    const int ky = blockIdx.y;
+    const int q = blockIdx.y;                // 0 <= q <= Py/2
+    const int nrow = (2 * q == Py || q == 0) ? 1 : 2;
+    const int ncol = Kx - kx0;
     const long cs = (long)nz * nyrows * SX, zs = (long)nyrows * SX;
-    cx<T>* bp = buf + (long)ky * SX + kx0;
-    for (int e = threadIdx.x; e < LZ * NC; e += NT) {
-        const int z = e / NC, cc = e - z * NC;
-        const int c = cc / TK, col = cc - c * TK;
-        C v{T(0), T(0)};
-        if (z < nz && kx0 + col < Kx) v = bp[c * cs + z * zs + col];
-        lb[e] = v;
+    cx<T>* bp0 = buf + (long)q * SX + kx0;
+    cx<T>* bp1 = buf + (long)(Py - q) * SX + kx0;
+    TwStage<T, (LZ > 1 ? LZ : 1), NT> tws;
+    if (LZ > 1) tws.fetch(tw);
+    // staged loads: LDS row (z*2 + w)*3 + c holds component c of row z of ky row w
+    P r[PER];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+        const int e = threadIdx.x + m * NT;
+        const int row = e / PR, j = e - row * PR;
+        const int z = row / 6, wc = row - 6 * z, w = wc / 3, c = wc - 3 * w;
+        r[m] = Pack<T>::zero();
+        if ((TOT % NT == 0 || e < TOT) && z < nz && w < nrow && j * PN < ncol)
+            r[m] = *(const P*)((w ? bp1 : bp0) + c * cs + z * zs + j * PN);
     }
+    // folded kernel values of this column tile for kz <= Pz/2 (stored [kzf][comp][col])
+    T kr[KPER];
+#pragma unroll
+    for (int m = 0; m < KPER; ++m) {
+        const int e = threadIdx.x + m * NT;
+        const int kzf = e / (6 * TK), rem = e - kzf * 6 * TK, comp = rem / TK, col = rem - comp * TK;
+        kr[m] = T(0);
+        if ((KTOT % NT == 0 || e < KTOT) && kzf < Kzf && col < ncol)
+            kr[m] = kfold[(((long)comp * Kzf + kzf) * Kyf + q) * SX + kx0 + col];
+    }
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+        const int e = threadIdx.x + m * NT;
+        if (TOT % NT == 0 || e < TOT) *(P*)(lb + e * PN) = r[m];
+    }
+#pragma unroll
+    for (int m = 0; m < KPER; ++m) {
+        const int e = threadIdx.x + m * NT;
+        if (KTOT % NT == 0 || e < KTOT) kl[e] = kr[m];
+    }
+    if (LZ > 1) tws.put(twl);
     __syncthreads();
-    lds_fft<T, LZ, false, Cols<NC, 1, NC, true>, NT>(lb, tw);
-    const int kyf = (2 * ky <= Py) ? ky : Py - ky;
-    const T sy = (2 * ky > Py) ? T(-1) : T(1);
-    const long kcs = (long)Kzf * Kyf * SX;
-    for (int e = threadIdx.x; e < LZ * TK; e += NT) {
-        const int kz = e / TK, col = e - kz * TK;
-        const int kx = kx0 + col;
-        if (kx >= Kx) continue;
+    lds_fft<T, LZ, false, Cols<NC, 1, NC, true>, NT>(lb, twl);
+    for (int e = threadIdx.x; e < LZ * 2 * TK; e += NT) {
+        const int kz = e / (2 * TK), rem = e - kz * 2 * TK, w = rem / TK, col = rem - w * TK;
+        if (col >= ncol || w >= nrow) continue;
         const int kzf = (2 * kz <= Pz) ? kz : Pz - kz;
         const T sz = (2 * kz > Pz) ? T(-1) : T(1);
-        const T* kp = kfold + ((long)kzf * Kyf + kyf) * SX + kx;
-        const T nxx = kp[0], nyy = kp[kcs], nzz = kp[2 * kcs];
-        const T nxy = sy * kp[3 * kcs], nxz = sz * kp[4 * kcs], nyz = sy * sz * kp[5 * kcs];
-        C* p = lb + kz * NC + col;
+        const T sy = w ? T(-1) : T(1);
+        const T* kp = kl + kzf * 6 * TK + col;
+        const T nxx = kp[0], nyy = kp[TK], nzz = kp[2 * TK];
+        const T nxy = sy * kp[3 * TK], nxz = sz * kp[4 * TK], nyz = sy * sz * kp[5 * TK];
+        C* p = lb + kz * NC + w * 3 * TK + col;
         const C mx = p[0], my = p[TK], mz = p[2 * TK];
         p[0] = C{nxx * mx.x + nxy * my.x + nxz * mz.x, nxx * mx.y + nxy * my.y + nxz * mz.y};
         p[TK] = C{nxy * mx.x + nyy * my.x + nyz * mz.x, nxy * mx.y + nyy * my.y + nyz * mz.y};
         p[2 * TK] = C{nxz * mx.x + nyz * my.x + nzz * mz.x, nxz * mx.y + nyz * my.y + nzz * mz.y};
     }
     __syncthreads();
-    lds_fft<T, LZ, true, Cols<NC, 1, NC, true>, NT>(lb, tw);
-    for (int e = threadIdx.x; e < nz * NC; e += NT) {
-        const int z = e / NC, cc = e - z * NC;
-        const int c = cc / TK, col = cc - c * TK;
-        if (kx0 + col < Kx) bp[c * cs + z * zs + col] = lb[e];
+    lds_fft<T, LZ, true, Cols<NC, 1, NC, true>, NT>(lb, twl);
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+        const int e = threadIdx.x + m * NT;
+        if (TOT % NT == 0 || e < TOT) r[m] = *(const P*)(lb + e * PN);
+    }
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+        const int e = threadIdx.x + m * NT;
+        const int row = e / PR, j = e - row * PR;
+        const int z = row / 6, wc = row - 6 * z, w = wc / 3, c = wc - 3 * w;
+        if ((TOT % NT == 0 || e < TOT) && z < nz && w < nrow && j * PN < ncol)
+            *(P*)((w ? bp1 : bp0) + c * cs + z * zs + j * PN) = r[m];
     }
 }
 
@@ -575,18 +679,18 @@ hipError_t launch_zmul(hipStream_t s, int LZ, cx<T>* buf, int SX, int Kx, int nz
 #define ZM(LL)                                                                                             \
     case LL: {                                                                                             \
         constexpr int TK = zmul_tile<T>(LL);                                                               \
-        dim3 g((unsigned)((Kx + TK - 1) / TK), (unsigned)nyrows, 1);                                       \
+        dim3 g((unsigned)((Kx + TK - 1) / TK), (unsigned)(Py / 2 + 1), 1);                                 \
         k_zmul<T, LL, TK><<<g, NT, 0, s>>>(buf, SX, Kx, nz, nyrows, Py, Pz, kfold, Kyf, Kzf, tw);           \
         break;                                                                                             \
     }
     switch (LZ) {
         case 1: {
-            constexpr int TK = 64;
-            dim3 g((unsigned)((Kx + TK - 1) / TK), (unsigned)nyrows, 1);
+            constexpr int TK = 32;
+            dim3 g((unsigned)((Kx + TK - 1) / TK), (unsigned)(Py / 2 + 1), 1);
             k_zmul<T, 1, TK><<<g, NT, 0, s>>>(buf, SX, Kx, nz, nyrows, Py, Pz, kfold, Kyf, Kzf, tw);
             break;
         }
-        LLGX_POW2_CASES(ZM)
+        ZM(2) ZM(4) ZM(8) ZM(16) ZM(32) ZM(64) ZM(128) ZM(256) ZM(512) ZM(1024)
         default:
             return hipErrorInvalidValue;
     }

@@ -28,12 +28,32 @@ struct Extrap {
     int n;
 };
 
-// Error estimate of Eq. (3): per cell |sum_k db[k] f[k]| with db = h (c_k - c^_k).
+// Eq. (6) for several sub-step times at once: out[j] = sum_i w[j][i] g[i].
 template <typename T>
-struct ErrSum {
+struct EPoly {
+    const T* g[MAX_HIST];
+    T w[MAX_F][MAX_HIST];
+    T* out[MAX_F];
+    int ng, nd;
+};
+
+// 2-D launch of the per-cell kernels (x along threads, mesh rows along blocks).
+struct CellGrid {
+    dim3 grid, block;
+    long nblocks;
+};
+CellGrid cell_grid(int nx, int ny, int nz);
+
+// Eq. (3): M = M0 + sum_k cb[k] f[k] (cb = h c_k) and, when err is set, the
+// per-cell estimate |sum_k ce[k] f[k]| (ce = h (c_k - c^_k)) over the union of
+// the stage derivatives either sum uses.
+template <typename T>
+struct Final {
     const T* f[MAX_F];
-    double db[MAX_F];
+    T cb[MAX_F];
+    double ce[MAX_F];
     int n;
+    int err;
 };
 
 // Material and field constants of the H_eff terms and the LLG right-hand side.
@@ -86,8 +106,13 @@ hipError_t launch_combine(hipStream_t s, long n, const Combo<T>& c, T* out);
 template <typename T>
 hipError_t launch_extrap_rhs(hipStream_t s, const T* Mk, const Extrap<T>& ex, const Phys<T>& ph, T* F);
 template <typename T>
-hipError_t launch_final(hipStream_t s, long ncell, const Combo<T>& sol, const ErrSum<T>& es, double inv_ms,
-                        T* mnew, double* parts, int nparts);
+hipError_t launch_epoly(hipStream_t s, long n, const EPoly<T>& ep);
+template <typename T>
+hipError_t launch_stage_final(hipStream_t s, const T* Mk, const Extrap<T>& ex, const Phys<T>& ph, const T* M0,
+                              const Final<T>& fs, double inv_ms, T* mnew, double* parts);
+template <typename T>
+hipError_t launch_final(hipStream_t s, long ncell, const T* base, const Final<T>& fs, double inv_ms, T* mnew,
+                        double* parts, int nparts);
 hipError_t launch_reduce_max(hipStream_t s, const double* parts, int nparts, double* out);
 template <typename T>
 hipError_t launch_renorm(hipStream_t s, long ncell, T* M, double Ms);

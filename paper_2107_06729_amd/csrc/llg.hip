@@ -1,28 +1,77 @@
 // Streaming kernels of one explicit step (Eq. (3)-(4)) and of the
 // extrapolated sub-steps (Eq. (6)), for gfx950.
 //
-// * k_combine     : M_k = M0 + sum_l (h b_kl) F_l                  (Eq. 4)
-// * k_extrap_rhs  : H_d = sum_i L_i G_i - N00 M_k at a sub-step, then
-//                   H_eff and the LLG right-hand side              (Eq. 6, 1)
-// * k_final       : M = M0 + h sum c_k F_k and, per cell,
-//                   |h sum (c_k - c^_k) F_k| / Ms accumulated in double;
-//                   per-block maxima then one reduction block       (Eq. 3)
-// * k_renorm, k_mean, k_cast: |M| = Ms rescaling, <M>, precision cast.
-// Reductions write per-block partials with ordinary vector stores and are
-// finished by a single-block kernel (no atomics, deterministic order).
+// * k_combine    : M_k = M0 + sum_l (h b_kl) F_l                        (Eq. 4)
+// * k_epoly      : E_j = sum_i L_i(t_j) G_i for every distinct sub-step time
+//                  t_j of the tableau: one pass over the p+1 stored fields
+//                  serves all stages                                     (Eq. 6)
+// * k_stage      : H_d = sum_i w_i g_i - N00 M_k (g: stored or E fields),
+//                  H_eff and the LLG right-hand side at a sub-step      (Eq. 6, 1)
+// * k_stage_final: the last sub-step fused with M = M0 + h sum c_k F_k and
+//                  the per-cell error |h sum (c_k - c^_k) F_k| / Ms      (Eq. 3)
+// * k_final      : Eq. (3) update and error when the last stage is exact
+// * k_renorm, k_mean, k_cast, reductions.
+// Per-cell kernels run on a 2-D grid (x along threads, rows of the mesh
+// along blocks) so cell coordinates need no divisions.  Reductions write
+// per-block partials with vector stores and are finished by one block (no
+// atomics, deterministic order).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 
 #include "kernels.hpp"
 #include "physics.hpp"
+#include "tile_io.hpp"
 
 namespace llgx {
 
 constexpr int NTS = 256;
 
+// ---------------------------------------------------------------------------
+// 16-byte vector access: 4 floats or 2 doubles per pack
+template <typename T> struct Vec;
+template <> struct Vec<float> {
+    using type = float4;
+    static constexpr int N = 4;
+    static __device__ __forceinline__ float get(const type& v, int i) {
+        return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+    }
+    static __device__ __forceinline__ void set(type& v, int i, float a) {
+        if (i == 0) v.x = a; else if (i == 1) v.y = a; else if (i == 2) v.z = a; else v.w = a;
+    }
+};
+template <> struct Vec<double> {
+    using type = double2;
+    static constexpr int N = 2;
+    static __device__ __forceinline__ double get(const type& v, int i) { return i == 0 ? v.x : v.y; }
+    static __device__ __forceinline__ void set(type& v, int i, double a) {
+        if (i == 0) v.x = a; else v.y = a;
+    }
+};
+
+template <typename T, int NF>
+__global__ __launch_bounds__(NTS) void k_combine(long npack, Combo<T> c, T* __restrict__ out) {
+    using V = typename Vec<T>::type;
+    constexpr int VN = Vec<T>::N;
+    for (long i = (long)blockIdx.x * NTS + threadIdx.x; i < npack; i += (long)gridDim.x * NTS) {
+        V b = ((const V*)c.base)[i];
+        V f[NF > 0 ? NF : 1];
+#pragma unroll
+        for (int l = 0; l < NF; ++l) f[l] = ((const V*)c.f[l])[i];
+#pragma unroll
+        for (int q = 0; q < VN; ++q) {
+            T v = Vec<T>::get(b, q);
+#pragma unroll
+            for (int l = 0; l < NF; ++l) v += c.coef[l] * Vec<T>::get(f[l], q);
+            Vec<T>::set(b, q, v);
+        }
+        ((V*)out)[i] = b;
+    }
+}
+
+// unaligned or ragged fallback
 template <typename T>
-__global__ __launch_bounds__(NTS) void k_combine(long n, Combo<T> c, T* __restrict__ out) {
+__global__ __launch_bounds__(NTS) void k_combine_scalar(long n, Combo<T> c, T* __restrict__ out) {
     for (long i = (long)blockIdx.x * NTS + threadIdx.x; i < n; i += (long)gridDim.x * NTS) {
         T v = c.base[i];
         for (int l = 0; l < c.nf; ++l) v += c.coef[l] * c.f[l][i];
@@ -30,45 +79,175 @@ __global__ __launch_bounds__(NTS) void k_combine(long n, Combo<T> c, T* __restri
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(NTS) void k_extrap_rhs(const T* __restrict__ Mk, Extrap<T> ex, Phys<T> ph,
-                                                    T* __restrict__ F) {
-    const long N = (long)ph.nx * ph.ny * ph.nz;
-    for (long cell = (long)blockIdx.x * NTS + threadIdx.x; cell < N; cell += (long)gridDim.x * NTS) {
-        const int x = (int)(cell % ph.nx);
-        const long r = cell / ph.nx;
-        const int y = (int)(r % ph.ny), z = (int)(r / ph.ny);
-        T hd[3];
+// E_j = sum_i w[j][i] g_i, vectorised over 16-byte packs
+template <typename T, int NG>
+__global__ __launch_bounds__(NTS) void k_epoly(long npack, EPoly<T> ep) {
+    using V = typename Vec<T>::type;
+    constexpr int VN = Vec<T>::N;
+    for (long i = (long)blockIdx.x * NTS + threadIdx.x; i < npack; i += (long)gridDim.x * NTS) {
+        V g[NG];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            T acc = -ph.n00[c] * Mk[c * N + cell];
-            for (int i = 0; i < ex.n; ++i) acc += ex.w[i] * ex.g[i][c * N + cell];
-            hd[c] = acc;
+        for (int k = 0; k < NG; ++k) g[k] = ((const V*)ep.g[k])[i];
+        for (int j = 0; j < ep.nd; ++j) {
+            V o;
+#pragma unroll
+            for (int q = 0; q < VN; ++q) {
+                T v = T(0);
+#pragma unroll
+                for (int k = 0; k < NG; ++k) v += ep.w[j][k] * Vec<T>::get(g[k], q);
+                Vec<T>::set(o, q, v);
+            }
+            ((V*)ep.out[j])[i] = o;
         }
-        T m[3], H[3], f[3];
-        heff_at(Mk, N, cell, x, y, z, ph, hd, m, H);
-        llg_at(m, H, ph, f);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) F[c * N + cell] = f[c];
     }
 }
 
+template <typename T, int NG>
+__global__ __launch_bounds__(NTS) void k_epoly_scalar(long n, EPoly<T> ep) {
+    for (long i = (long)blockIdx.x * NTS + threadIdx.x; i < n; i += (long)gridDim.x * NTS) {
+        T g[NG];
+#pragma unroll
+        for (int k = 0; k < NG; ++k) g[k] = ep.g[k][i];
+        for (int j = 0; j < ep.nd; ++j) {
+            T v = T(0);
+#pragma unroll
+            for (int k = 0; k < NG; ++k) v += ep.w[j][k] * g[k];
+            ep.out[j][i] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per-cell sub-step kernels on a 2-D grid: blockDim (TX, RY), blockIdx.x over
+// row groups (row = y + ny z), blockIdx.y over x segments
+struct CellIdx {
+    int x, y, z;
+    long cell;
+    bool ok;
+};
+
 template <typename T>
-__global__ __launch_bounds__(NTS) void k_final(long ncell, Combo<T> sol, ErrSum<T> es, double inv_ms,
+__device__ __forceinline__ CellIdx cell_index(const Phys<T>& ph) {
+    CellIdx c;
+    c.x = blockIdx.y * blockDim.x + threadIdx.x;
+    const int row = blockIdx.x * blockDim.y + threadIdx.y;
+    c.ok = c.x < ph.nx && row < ph.ny * ph.nz;
+    c.y = row % ph.ny;
+    c.z = row / ph.ny;
+    c.cell = (long)row * ph.nx + c.x;
+    return c;
+}
+
+template <typename T, int NG>
+__device__ __forceinline__ void stage_rhs(const T* __restrict__ Mk, const Extrap<T>& ex, const Phys<T>& ph,
+                                          const CellIdx& ci, long N, T m[3], T f[3]) {
+    T g[NG][3];
+#pragma unroll
+    for (int i = 0; i < NG; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) g[i][c] = ex.g[i][c * N + ci.cell];
+    T hd[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        T acc = -ph.n00[c] * Mk[c * N + ci.cell];
+#pragma unroll
+        for (int i = 0; i < NG; ++i) acc += ex.w[i] * g[i][c];
+        hd[c] = acc;
+    }
+    T H[3];
+    heff_at(Mk, N, ci.cell, ci.x, ci.y, ci.z, ph, hd, m, H);
+    llg_at(m, H, ph, f);
+}
+
+template <typename T, int NG>
+__global__ __launch_bounds__(NTS) void k_stage(const T* __restrict__ Mk, Extrap<T> ex, Phys<T> ph,
+                                               T* __restrict__ F) {
+    const long N = (long)ph.nx * ph.ny * ph.nz;
+    const CellIdx ci = cell_index(ph);
+    if (!ci.ok) return;
+    T m[3], f[3];
+    stage_rhs<T, NG>(Mk, ex, ph, ci, N, m, f);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) F[c * N + ci.cell] = f[c];
+}
+
+// last sub-step fused with Eq. (3): fs lists the stage derivatives used by
+// the update or the estimate; its final entry (index fs.n - 1) is this
+// stage's own F_S, which is taken from registers and never stored
+template <typename T, int NG, int NF>
+__global__ __launch_bounds__(NTS) void k_stage_final(const T* __restrict__ Mk, Extrap<T> ex, Phys<T> ph,
+                                                     const T* __restrict__ M0, Final<T> fs, double inv_ms,
+                                                     T* __restrict__ mnew, double* __restrict__ parts) {
+    __shared__ double red[NTS];
+    const long N = (long)ph.nx * ph.ny * ph.nz;
+    const CellIdx ci = cell_index(ph);
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    double emax = 0.0;
+    if (ci.ok) {
+        T m[3], fS[3];
+        stage_rhs<T, NG>(Mk, ex, ph, ci, N, m, fS);
+        T m0[3], f[NF > 1 ? NF - 1 : 1][3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) m0[c] = M0[c * N + ci.cell];
+#pragma unroll
+        for (int k = 0; k < NF - 1; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) f[k][c] = fs.f[k][c * N + ci.cell];
+        double e2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T v = m0[c];
+#pragma unroll
+            for (int k = 0; k < NF - 1; ++k) v += fs.cb[k] * f[k][c];
+            v += fs.cb[NF - 1] * fS[c];
+            mnew[c * N + ci.cell] = v;
+            if (fs.err) {
+                double d = 0.0;
+#pragma unroll
+                for (int k = 0; k < NF - 1; ++k) d += fs.ce[k] * (double)f[k][c];
+                d += fs.ce[NF - 1] * (double)fS[c];
+                e2 += d * d;
+            }
+        }
+        emax = sqrt(e2) * inv_ms;
+        if (e2 != e2) emax = e2;
+    }
+    red[tid] = emax;
+    __syncthreads();
+    for (int s = NTS / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+            const double a = red[tid], b = red[tid + s];
+            red[tid] = (a != a || b != b) ? (a + b) : fmax(a, b);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) parts[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+}
+
+template <typename T, int NF>
+__global__ __launch_bounds__(NTS) void k_final(long ncell, const T* __restrict__ base, Final<T> fs, double inv_ms,
                                                T* __restrict__ mnew, double* __restrict__ parts) {
     __shared__ double red[NTS];
     double emax = 0.0;
     for (long cell = (long)blockIdx.x * NTS + threadIdx.x; cell < ncell; cell += (long)gridDim.x * NTS) {
+        T m0[3], f[NF][3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) m0[c] = base[c * ncell + cell];
+#pragma unroll
+        for (int k = 0; k < NF; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) f[k][c] = fs.f[k][c * ncell + cell];
         double e2 = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const long i = c * ncell + cell;
-            T v = sol.base[i];
-            for (int l = 0; l < sol.nf; ++l) v += sol.coef[l] * sol.f[l][i];
-            mnew[i] = v;
-            if (es.n > 0) {
+            T v = m0[c];
+#pragma unroll
+            for (int k = 0; k < NF; ++k) v += fs.cb[k] * f[k][c];
+            mnew[c * ncell + cell] = v;
+            if (fs.err) {
                 double d = 0.0;
-                for (int k = 0; k < es.n; ++k) d += es.db[k] * (double)es.f[k][i];
+#pragma unroll
+                for (int k = 0; k < NF; ++k) d += fs.ce[k] * (double)f[k][c];
                 e2 += d * d;
             }
         }
@@ -177,23 +356,102 @@ static unsigned grid_for(long n) {
     return (unsigned)(b < 1 ? 1 : b);
 }
 
+CellGrid cell_grid(int nx, int ny, int nz) {
+    int tx = 1;
+    while (tx < nx && tx < NTS) tx <<= 1;
+    const int ry = NTS / tx;
+    const long rows = (long)ny * nz;
+    CellGrid g;
+    g.block = dim3((unsigned)tx, (unsigned)ry, 1);
+    g.grid = dim3((unsigned)((rows + ry - 1) / ry), (unsigned)((nx + tx - 1) / tx), 1);
+    g.nblocks = (long)g.grid.x * g.grid.y;
+    return g;
+}
+
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
 template <typename T>
 hipError_t launch_combine(hipStream_t s, long n, const Combo<T>& c, T* out) {
-    k_combine<T><<<grid_for(n), NTS, 0, s>>>(n, c, out);
+    constexpr int VN = Vec<T>::N;
+    bool vec = (n % VN) == 0 && aligned16(c.base) && aligned16(out);
+    for (int l = 0; l < c.nf; ++l) vec = vec && aligned16(c.f[l]);
+    if (!vec) {
+        k_combine_scalar<T><<<grid_for(n), NTS, 0, s>>>(n, c, out);
+        return hipGetLastError();
+    }
+    const long np = n / VN;
+    const unsigned g = grid_for(np);
+    switch (c.nf) {
+#define CB(K) \
+    case K: k_combine<T, K><<<g, NTS, 0, s>>>(np, c, out); break;
+        CB(0) CB(1) CB(2) CB(3) CB(4) CB(5) CB(6) CB(7) CB(8)
+#undef CB
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_epoly(hipStream_t s, long n, const EPoly<T>& ep) {
+    constexpr int VN = Vec<T>::N;
+    bool vec = (n % VN) == 0;
+    for (int k = 0; k < ep.ng; ++k) vec = vec && aligned16(ep.g[k]);
+    for (int j = 0; j < ep.nd; ++j) vec = vec && aligned16(ep.out[j]);
+    const long np = vec ? n / VN : n;
+    const unsigned g = grid_for(np);
+    switch (ep.ng) {
+#define EP(K)                                               \
+    case K:                                                 \
+        if (vec)                                            \
+            k_epoly<T, K><<<g, NTS, 0, s>>>(np, ep);        \
+        else                                                \
+            k_epoly_scalar<T, K><<<g, NTS, 0, s>>>(np, ep); \
+        break;
+        EP(1) EP(2) EP(3) EP(4) EP(5) EP(6)
+#undef EP
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_extrap_rhs(hipStream_t s, const T* Mk, const Extrap<T>& ex, const Phys<T>& ph, T* F) {
-    const long N = (long)ph.nx * ph.ny * ph.nz;
-    k_extrap_rhs<T><<<grid_for(N), NTS, 0, s>>>(Mk, ex, ph, F);
+    const CellGrid cg = cell_grid(ph.nx, ph.ny, ph.nz);
+    switch (ex.n) {
+#define EX(K) \
+    case K: k_stage<T, K><<<cg.grid, cg.block, 0, s>>>(Mk, ex, ph, F); break;
+        EX(1) EX(2) EX(3) EX(4) EX(5) EX(6)
+#undef EX
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_final(hipStream_t s, long ncell, const Combo<T>& sol, const ErrSum<T>& es, double inv_ms, T* mnew,
+hipError_t launch_stage_final(hipStream_t s, const T* Mk, const Extrap<T>& ex, const Phys<T>& ph, const T* M0,
+                              const Final<T>& fs, double inv_ms, T* mnew, double* parts) {
+    const CellGrid cg = cell_grid(ph.nx, ph.ny, ph.nz);
+    if (ex.n != 1) return hipErrorInvalidValue;
+    switch (fs.n) {
+#define SF(K) \
+    case K: k_stage_final<T, 1, K><<<cg.grid, cg.block, 0, s>>>(Mk, ex, ph, M0, fs, inv_ms, mnew, parts); break;
+        SF(1) SF(2) SF(3) SF(4) SF(5) SF(6) SF(7) SF(8)
+#undef SF
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_final(hipStream_t s, long ncell, const T* base, const Final<T>& fs, double inv_ms, T* mnew,
                         double* parts, int nparts) {
-    k_final<T><<<(unsigned)nparts, NTS, 0, s>>>(ncell, sol, es, inv_ms, mnew, parts);
+    switch (fs.n) {
+#define FN(K) \
+    case K: k_final<T, K><<<(unsigned)nparts, NTS, 0, s>>>(ncell, base, fs, inv_ms, mnew, parts); break;
+        FN(1) FN(2) FN(3) FN(4) FN(5) FN(6) FN(7) FN(8)
+#undef FN
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -227,9 +485,11 @@ hipError_t launch_cast(hipStream_t s, long n, const double* src, T* dst) {
 
 #define INST(T)                                                                                                  \
     template hipError_t launch_combine<T>(hipStream_t, long, const Combo<T>&, T*);                               \
+    template hipError_t launch_epoly<T>(hipStream_t, long, const EPoly<T>&);                                     \
     template hipError_t launch_extrap_rhs<T>(hipStream_t, const T*, const Extrap<T>&, const Phys<T>&, T*);        \
-    template hipError_t launch_final<T>(hipStream_t, long, const Combo<T>&, const ErrSum<T>&, double, T*, double*, \
-                                        int);                                                                    \
+    template hipError_t launch_stage_final<T>(hipStream_t, const T*, const Extrap<T>&, const Phys<T>&, const T*,  \
+                                              const Final<T>&, double, T*, double*);                             \
+    template hipError_t launch_final<T>(hipStream_t, long, const T*, const Final<T>&, double, T*, double*, int); \
     template hipError_t launch_renorm<T>(hipStream_t, long, T*, double);                                         \
     template hipError_t launch_mean<T>(hipStream_t, long, const T*, double*, int);                               \
     template hipError_t launch_cast<T>(hipStream_t, long, const double*, T*);

@@ -63,8 +63,10 @@ struct Ctx {
     void* Mk = nullptr;
     void* F[MAX_F] = {};
     void* G[MAX_HIST] = {};
+    void* E[MAX_F] = {};        // Eq. (6) fields at the distinct sub-step times of a step
     double* parts = nullptr;
-    int nparts = 1;
+    int nparts = 1;             // blocks of the 1-D reduction kernels
+    long nparts_alloc = 1;      // capacity of parts (also covers the 2-D cell grid)
     double* scal = nullptr;     // [0] error norm, [1..3] sums for <M>
     double* octant = nullptr;   // real-space tensor for offsets 0..n-1 (double)
     bool have_kernel = false;
@@ -387,6 +389,9 @@ static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
     }
     std::vector<double> nodes;
     std::vector<int> slots;
+    // distinct sub-step times of stages 2..S: field index per stage
+    std::vector<double> times;
+    std::vector<int> field_of(tab->S, -1);
     if (pl.extrap) {
         for (auto& hh : c->hist) {
             nodes.push_back(hh.t - c->t);
@@ -394,7 +399,49 @@ static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
         }
         nodes.push_back(0.0);
         slots.push_back(pl.slot0);
+        for (int k = 1; k < tab->S; ++k) {
+            if (pl.p == 0 || tab->c[k] == 0.0) continue;  // G0 itself
+            int j = -1;
+            for (size_t q = 0; q < times.size(); ++q)
+                if (times[q] == tab->c[k]) j = (int)q;
+            if (j < 0) {
+                j = (int)times.size();
+                times.push_back(tab->c[k]);
+            }
+            field_of[k] = j;
+        }
+        if (!times.empty()) {
+            EPoly<T> ep{};
+            ep.ng = (int)nodes.size();
+            ep.nd = (int)times.size();
+            for (int i = 0; i < ep.ng; ++i) ep.g[i] = (const T*)c->G[slots[i]];
+            for (int j = 0; j < ep.nd; ++j) {
+                const std::vector<double> w = lagrange(nodes, times[j] * h);
+                for (int i = 0; i < ep.ng; ++i) ep.w[j][i] = (T)w[i];
+                ep.out[j] = (T*)c->E[j];
+            }
+            PROF(LLGX_K_EPOLY);
+            HIPCHK(c, launch_epoly<T>(c->stream, 3 * c->ncell, ep));
+        }
     }
+    // Eq. (3) operands: stage derivatives used by the update or by the estimate
+    Final<T> fs{};
+    fs.err = pl.want_err && tab->order_hat > 0;
+    auto add_final = [&](int k) {
+        const bool use_e = fs.err && tab->b[k] != tab->bh[k];
+        fs.f[fs.n] = (const T*)c->F[k];
+        fs.cb[fs.n] = (T)(h * tab->b[k]);
+        fs.ce[fs.n] = use_e ? h * (tab->b[k] - tab->bh[k]) : 0.0;
+        fs.n++;
+    };
+    for (int k = 0; k < tab->S; ++k) {
+        const bool last_fused = pl.extrap && k == tab->S - 1;
+        if (last_fused) break;
+        const bool use_b = tab->b[k] != 0.0;
+        const bool use_e = fs.err && tab->b[k] != tab->bh[k];
+        if (use_b || use_e) add_final(k);
+    }
+    bool fused_final = false;
     for (int k = 1; k < tab->S; ++k) {
         Combo<T> cb{};
         cb.base = (const T*)c->M;
@@ -411,42 +458,35 @@ static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
                 HIPCHK(c, launch_combine<T>(c->stream, 3 * c->ncell, cb, (T*)c->Mk));
             }
             Extrap<T> ex{};
-            const std::vector<double> w = lagrange(nodes, tab->c[k] * h);
-            ex.n = (int)w.size();
-            for (int i = 0; i < ex.n; ++i) {
-                ex.g[i] = (const T*)c->G[slots[i]];
-                ex.w[i] = (T)w[i];
+            ex.n = 1;
+            ex.w[0] = T(1);
+            ex.g[0] = field_of[k] < 0 ? (const T*)c->G[pl.slot0] : (const T*)c->E[field_of[k]];
+            ProfScope ps(c, k == tab->S - 1 ? LLGX_K_FINAL : LLGX_K_EXTRAP);
+            if (k == tab->S - 1) {
+                add_final(k);  // own derivative, last entry
+                HIPCHK(c, launch_stage_final<T>(c->stream, (const T*)c->Mk, ex, phys<T>(c), (const T*)c->M, fs,
+                                                1.0 / c->p.Ms, (T*)c->Mnew, c->parts));
+                fused_final = true;
+            } else {
+                HIPCHK(c, launch_extrap_rhs<T>(c->stream, (const T*)c->Mk, ex, phys<T>(c), (T*)c->F[k]));
             }
-            PROF(LLGX_K_EXTRAP);
-            HIPCHK(c, launch_extrap_rhs<T>(c->stream, (const T*)c->Mk, ex, phys<T>(c), (T*)c->F[k]));
         } else {
             XinvOut out{nullptr, c->F[k], nullptr};
             llgx_status st = eval_exact<T>(c, cb, (T*)c->Mk, XINV_RHS, (const T*)c->Mk, out);
             if (st) return st;
         }
     }
-    Combo<T> sol{};
-    sol.base = (const T*)c->M;
-    ErrSum<T> es{};
-    for (int k = 0; k < tab->S; ++k) {
-        if (tab->b[k] != 0.0) {
-            sol.f[sol.nf] = (const T*)c->F[k];
-            sol.coef[sol.nf] = (T)(h * tab->b[k]);
-            sol.nf++;
-        }
-        if (pl.want_err && tab->order_hat > 0 && tab->b[k] != tab->bh[k]) {
-            es.f[es.n] = (const T*)c->F[k];
-            es.db[es.n] = h * (tab->b[k] - tab->bh[k]);
-            es.n++;
-        }
-    }
-    {
+    int nred = c->nparts;
+    if (fused_final) {
+        nred = (int)cell_grid(c->nx, c->ny, c->nz).nblocks;
+    } else {
         PROF(LLGX_K_FINAL);
-        HIPCHK(c, launch_final<T>(c->stream, c->ncell, sol, es, 1.0 / c->p.Ms, (T*)c->Mnew, c->parts, c->nparts));
+        HIPCHK(c, launch_final<T>(c->stream, c->ncell, (const T*)c->M, fs, 1.0 / c->p.Ms, (T*)c->Mnew, c->parts,
+                                  c->nparts));
     }
     if (pl.want_err) {
         PROF(LLGX_K_OTHER);
-        HIPCHK(c, launch_reduce_max(c->stream, c->parts, c->nparts, c->scal));
+        HIPCHK(c, launch_reduce_max(c->stream, c->parts, nred, c->scal));
     }
     return LLGX_OK;
 }
@@ -715,6 +755,8 @@ static void release(Ctx* c) {
         if (c->F[i]) (void)hipFree(c->F[i]);
     for (int i = 0; i < MAX_HIST; ++i)
         if (c->G[i]) (void)hipFree(c->G[i]);
+    for (int i = 0; i < MAX_F; ++i)
+        if (c->E[i]) (void)hipFree(c->E[i]);
     for (auto& kv : c->tw_work) (void)hipFree(kv.second);
     for (auto& kv : c->tw_f64) (void)hipFree(kv.second);
 }
@@ -783,8 +825,8 @@ llgx_status llgx_create(const llgx_problem* p, int32_t precision, int32_t spectr
     c->Px = p->nx > 1 ? next_pow2(2L * p->nx - 1) : 1;
     c->Py = p->ny > 1 ? next_pow2(2L * p->ny - 1) : 1;
     c->Pz = p->nz > 1 ? next_pow2(2L * p->nz - 1) : 1;
-    if (c->Px > MAX_LEN || c->Py > MAX_LEN || c->Pz > MAX_LEN) {
-        g_create_error = "mesh too large: padded FFT length per axis above 2048";
+    if (c->Px > MAX_LEN || c->Py > MAX_LEN || c->Pz > MAX_LEN / 2) {
+        g_create_error = "mesh too large: padded FFT length above 2048 (x, y) or 1024 (z)";
         delete c;
         return LLGX_E_UNSUPPORTED;
     }
@@ -806,8 +848,10 @@ llgx_status llgx_create(const llgx_problem* p, int32_t precision, int32_t spectr
     A(&c->Mk, vbytes);
     for (int i = 0; i < MAX_F; ++i) A(&c->F[i], vbytes);
     for (int i = 0; i < MAX_HIST; ++i) A(&c->G[i], vbytes);
+    for (int i = 0; i < MAX_F - 1; ++i) A(&c->E[i], vbytes);
     c->nparts = (int)std::min<long>(1024, std::max<long>(1, (c->ncell + 255) / 256));
-    A((void**)&c->parts, 3 * (size_t)c->nparts * sizeof(double));
+    c->nparts_alloc = std::max<long>(c->nparts, cell_grid(c->nx, c->ny, c->nz).nblocks);
+    A((void**)&c->parts, 3 * (size_t)c->nparts_alloc * sizeof(double));
     A((void**)&c->scal, 8 * sizeof(double));
     if (st == LLGX_OK) {
         for (int L : {c->LX, c->Px, c->Py, c->Pz}) {
