@@ -191,6 +191,26 @@ llgx_status llgx_run(llgx_handle h, const llgx_stepper* s, double t_end, double 
 llgx_status llgx_profile(llgx_handle h, int32_t enable);
 llgx_status llgx_profile_read(llgx_handle h, double ms[LLGX_K_COUNT], int64_t launches[LLGX_K_COUNT]);
 
+/* ---- Batches of independent samples -------------------------------------
+ * n samples of possibly different meshes and applied fields (parameter and
+ * field sweeps) stepped together.  Samples whose problems are equal except
+ * for Ha share one set of kernels: every launch covers all of them (FFT
+ * passes over all their rows, per-sample applied fields).  With use_graph,
+ * one steady-state step of all samples is captured into a HIP graph (one per
+ * history phase) and replayed.  Fixed step only; all samples share the
+ * stepper and the time.  llgx_batch_set_m on any sample restarts priming of
+ * its group.  Per-sample M is [3][nz][ny][nx] of the batch precision. */
+typedef struct llgx_batch_s* llgx_batch;
+llgx_status llgx_batch_create(int32_t n, const llgx_problem* problems, int32_t precision, void* hip_stream,
+                              llgx_batch* out);
+void llgx_batch_destroy(llgx_batch b);
+const char* llgx_batch_last_error(llgx_batch b);
+llgx_status llgx_batch_precompute_demag(llgx_batch b);
+llgx_status llgx_batch_set_m(llgx_batch b, int32_t i, const void* M_dev);
+llgx_status llgx_batch_get_m(llgx_batch b, int32_t i, void* M_dev);
+llgx_status llgx_batch_run_fixed(llgx_batch b, const llgx_stepper* s, int64_t nsteps, int32_t use_graph);
+llgx_status llgx_batch_info(llgx_batch b, int32_t* ngroups, int64_t* total_cells, double* t);
+
 /* Time, proposed next step and counters of the handle. */
 llgx_status llgx_get_time(llgx_handle h, double* t, double* h_next);
 llgx_status llgx_set_time(llgx_handle h, double t);

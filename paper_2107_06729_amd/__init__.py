@@ -80,6 +80,15 @@ _sig = {
     "llgx_get_time": (_S, [_H, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "llgx_set_time": (_S, [_H, ctypes.c_double]),
     "llgx_counters": (_S, [_H, ctypes.POINTER(ctypes.c_int64)]),
+    "llgx_batch_create": (_S, [ctypes.c_int32, ctypes.POINTER(Problem), ctypes.c_int32, _P, ctypes.POINTER(_H)]),
+    "llgx_batch_destroy": (None, [_H]),
+    "llgx_batch_last_error": (ctypes.c_char_p, [_H]),
+    "llgx_batch_precompute_demag": (_S, [_H]),
+    "llgx_batch_set_m": (_S, [_H, ctypes.c_int32, _P]),
+    "llgx_batch_get_m": (_S, [_H, ctypes.c_int32, _P]),
+    "llgx_batch_run_fixed": (_S, [_H, ctypes.POINTER(Stepper), ctypes.c_int64, ctypes.c_int32]),
+    "llgx_batch_info": (_S, [_H, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                             ctypes.POINTER(ctypes.c_double)]),
     "llgx_profile": (_S, [_H, ctypes.c_int32]),
     "llgx_profile_read": (_S, [_H, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
 }
@@ -281,3 +290,67 @@ class Sim:
         out = (ctypes.c_int64 * 5)()
         _check(_lib.llgx_counters(self._h, out), self._h)
         return dict(zip(("exact", "extrap", "accepted", "rejected", "forced"), list(out)))
+
+
+def _bcheck(code, handle):
+    if code != OK:
+        msg = _lib.llgx_batch_last_error(handle)
+        raise LlgxError(code, msg.decode() if msg else "")
+
+
+class Batch:
+    """Independent samples (list of problem dicts) stepped together."""
+
+    def __init__(self, problems, precision="f32", stream=None, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.problems = list(problems)
+        self.prec = F32 if precision in ("f32", F32) else F64
+        self.dtype = torch.float32 if self.prec == F32 else torch.float64
+        arr = (Problem * len(self.problems))(*[make_problem(p) for p in self.problems])
+        with torch.cuda.device(self.device):
+            self._h = _H()
+            _bcheck(_lib.llgx_batch_create(len(self.problems), arr, self.prec, _stream_ptr(stream),
+                                           ctypes.byref(self._h)), None)
+        self._keep = []
+
+    def shape(self, i):
+        nx, ny, nz = (int(v) for v in self.problems[i]["n"])
+        return (3, nz, ny, nx)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.llgx_batch_destroy(self._h)
+            self._h = _H()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def precompute_demag(self):
+        _bcheck(_lib.llgx_batch_precompute_demag(self._h), self._h)
+
+    def set_m(self, i, M):
+        t = self.torch.as_tensor(M).to(device=self.device, dtype=self.dtype).contiguous()
+        if tuple(t.shape) != self.shape(i):
+            raise ValueError(f"expected shape {self.shape(i)}, got {tuple(t.shape)}")
+        _bcheck(_lib.llgx_batch_set_m(self._h, int(i), ctypes.c_void_p(t.data_ptr())), self._h)
+        self._keep.append(t)
+
+    def get_m(self, i):
+        out = self.torch.empty(self.shape(i), dtype=self.dtype, device=self.device)
+        _bcheck(_lib.llgx_batch_get_m(self._h, int(i), ctypes.c_void_p(out.data_ptr())), self._h)
+        return out
+
+    def run_fixed(self, stepper, nsteps, use_graph=True):
+        _bcheck(_lib.llgx_batch_run_fixed(self._h, ctypes.byref(stepper), int(nsteps), int(bool(use_graph))),
+                self._h)
+        self._keep = []
+
+    def info(self):
+        ng, nc, t = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_double()
+        _bcheck(_lib.llgx_batch_info(self._h, ctypes.byref(ng), ctypes.byref(nc), ctypes.byref(t)), self._h)
+        return {"groups": ng.value, "cells": nc.value, "t": t.value}

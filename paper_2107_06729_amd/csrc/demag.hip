@@ -169,6 +169,10 @@ __global__ __launch_bounds__(NT) void k_xinv(const cx<T>* __restrict__ spec, int
     const long nrow = (long)ph.ny * ph.nz;
     const long N = nrow * ph.nx;
     const long row0 = (long)blockIdx.x * ROWS;
+    const int b = blockIdx.y;  // sample
+    spec += (long)b * 3 * nrow * SX;
+    if (M) M += (long)b * 3 * N;
+    const long vo = (long)b * 3 * N;
     if constexpr (LX == 0) {
         for (int lr = threadIdx.x; lr < 3 * ROWS; lr += NT) {
             const int r = lr / 3, c = lr - 3 * r;
@@ -226,30 +230,30 @@ __global__ __launch_bounds__(NT) void k_xinv(const cx<T>* __restrict__ spec, int
         }
         const long cell = g * nx + x;
         if constexpr (MODE == XINV_DEMAG) {
-            T* H = (T*)out.h;
+            T* H = (T*)out.h + vo;
 #pragma unroll
             for (int c = 0; c < 3; ++c) H[c * N + cell] = hd[c];
         } else {
             const int y = (int)(g % ph.ny), z = (int)(g / ph.ny);
             T m[3], H[3];
-            heff_at(M, N, cell, x, y, z, ph, hd, m, H);
+            heff_at(M, N, cell, x, y, z, b, ph, hd, m, H);
             if constexpr (MODE == XINV_HEFF) {
-                T* Ho = (T*)out.h;
+                T* Ho = (T*)out.h + vo;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) Ho[c * N + cell] = H[c];
             } else {
                 T F[3];
                 llg_at(m, H, ph, F);
-                T* Fo = (T*)out.f;
+                T* Fo = (T*)out.f + vo;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) Fo[c * N + cell] = F[c];
                 if (out.g) {
-                    T* G = (T*)out.g;
+                    T* G = (T*)out.g + vo;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) G[c * N + cell] = hd[c] + ph.n00[c] * m[c];
                 }
                 if (out.h) {
-                    T* Ho = (T*)out.h;
+                    T* Ho = (T*)out.h + vo;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) Ho[c * N + cell] = hd[c];
                 }
@@ -306,6 +310,7 @@ __global__ __launch_bounds__(NT) void k_zmul(cx<T>* __restrict__ buf, int SX, in
     const int nrow = (2 * q == Py || q == 0) ? 1 : 2;
     const int ncol = Kx - kx0;
     const long cs = (long)nz * nyrows * SX, zs = (long)nyrows * SX;
+    buf += (long)blockIdx.z * 3 * cs;  // sample
     cx<T>* bp0 = buf + (long)q * SX + kx0;
     cx<T>* bp1 = buf + (long)(Py - q) * SX + kx0;
     TwStage<T, (LZ > 1 ? LZ : 1), NT> tws;
@@ -619,7 +624,7 @@ hipError_t launch_xinv(hipStream_t s, int LX, int mode, const cx<T>* spec, int S
     const long nrow = (long)ph.ny * ph.nz;
 #define XI_MODE(L, R)                                                                               \
     {                                                                                               \
-        const unsigned nb = (unsigned)((nrow + R - 1) / R);                                         \
+        const dim3 nb((unsigned)((nrow + R - 1) / R), (unsigned)ph.nb, 1);                          \
         if (mode == XINV_DEMAG)                                                                     \
             k_xinv<T, L, R, XINV_DEMAG><<<nb, NT, 0, s>>>(spec, SX, M, ph, out, twL, twP);          \
         else if (mode == XINV_HEFF)                                                                 \
@@ -675,18 +680,18 @@ hipError_t launch_colfft(hipStream_t s, int L, bool inv, const cx<T>* src, long 
 
 template <typename T>
 hipError_t launch_zmul(hipStream_t s, int LZ, cx<T>* buf, int SX, int Kx, int nz, int nyrows, int Py, int Pz,
-                       const T* kfold, int Kyf, int Kzf, const cx<T>* tw) {
+                       const T* kfold, int Kyf, int Kzf, const cx<T>* tw, int nb) {
 #define ZM(LL)                                                                                             \
     case LL: {                                                                                             \
         constexpr int TK = zmul_tile<T>(LL);                                                               \
-        dim3 g((unsigned)((Kx + TK - 1) / TK), (unsigned)(Py / 2 + 1), 1);                                 \
+        dim3 g((unsigned)((Kx + TK - 1) / TK), (unsigned)(Py / 2 + 1), (unsigned)nb);                      \
         k_zmul<T, LL, TK><<<g, NT, 0, s>>>(buf, SX, Kx, nz, nyrows, Py, Pz, kfold, Kyf, Kzf, tw);           \
         break;                                                                                             \
     }
     switch (LZ) {
         case 1: {
             constexpr int TK = 32;
-            dim3 g((unsigned)((Kx + TK - 1) / TK), (unsigned)(Py / 2 + 1), 1);
+            dim3 g((unsigned)((Kx + TK - 1) / TK), (unsigned)(Py / 2 + 1), (unsigned)nb);
             k_zmul<T, 1, TK><<<g, NT, 0, s>>>(buf, SX, Kx, nz, nyrows, Py, Pz, kfold, Kyf, Kzf, tw);
             break;
         }
@@ -728,7 +733,7 @@ hipError_t launch_fold(hipStream_t s, const cx<double>* spec, int SX, int Kx, in
     template hipError_t launch_colfft<T>(hipStream_t, int, bool, const cx<T>*, long, long, long, int, cx<T>*, long, \
                                          long, long, int, int, int, int, const cx<T>*);                           \
     template hipError_t launch_zmul<T>(hipStream_t, int, cx<T>*, int, int, int, int, int, int, const T*, int, int, \
-                                       const cx<T>*);                                                             \
+                                       const cx<T>*, int);                                                        \
     template hipError_t launch_fold<T>(hipStream_t, const cx<double>*, int, int, int, int, int, int, double, int, \
                                        T*, double*, int);
 INST(float)

@@ -42,7 +42,7 @@ struct CellGrid {
     dim3 grid, block;
     long nblocks;
 };
-CellGrid cell_grid(int nx, int ny, int nz);
+CellGrid cell_grid(int nx, int ny, int nz, int nb);
 
 // Eq. (3): M = M0 + sum_k cb[k] f[k] (cb = h c_k) and, when err is set, the
 // per-cell estimate |sum_k ce[k] f[k]| (ce = h (c_k - c^_k)) over the union of
@@ -66,7 +66,9 @@ struct Phys {
     T gp;              // gamma / (1 + alpha^2)
     T gpa;             // gamma alpha / ((1 + alpha^2) Ms)
     T n00[3];          // self term of Eq. (6)
+    const T* hab;      // per-sample applied field [nb][3] (device), or null: ha for all
     int nx, ny, nz;
+    int nb;            // samples of this mesh processed by one launch
 };
 
 // Output selection of the inverse x pass.
@@ -91,7 +93,7 @@ hipError_t launch_colfft(hipStream_t s, int L, bool inv, const cx<T>* src, long 
                          int nouter, int ncomp, const cx<T>* tw);
 template <typename T>
 hipError_t launch_zmul(hipStream_t s, int LZ, cx<T>* buf, int SX, int Kx, int nz, int nyrows, int Py, int Pz,
-                       const T* kfold, int Kyf, int Kzf, const cx<T>* tw);
+                       const T* kfold, int Kyf, int Kzf, const cx<T>* tw, int nb);
 hipError_t launch_newell_octant(hipStream_t s, int nx, int ny, int nz, double dx, double dy, double dz,
                                 double* octant);
 hipError_t launch_scatter_tensor(hipStream_t s, const double* octant, int comp, int nx, int ny, int nz,
@@ -111,11 +113,11 @@ template <typename T>
 hipError_t launch_stage_final(hipStream_t s, const T* Mk, const Extrap<T>& ex, const Phys<T>& ph, const T* M0,
                               const Final<T>& fs, double inv_ms, T* mnew, double* parts);
 template <typename T>
-hipError_t launch_final(hipStream_t s, long ncell, const T* base, const Final<T>& fs, double inv_ms, T* mnew,
+hipError_t launch_final(hipStream_t s, long ncell, int nb, const T* base, const Final<T>& fs, double inv_ms, T* mnew,
                         double* parts, int nparts);
 hipError_t launch_reduce_max(hipStream_t s, const double* parts, int nparts, double* out);
 template <typename T>
-hipError_t launch_renorm(hipStream_t s, long ncell, T* M, double Ms);
+hipError_t launch_renorm(hipStream_t s, long ncell, int nb, T* M, double Ms);
 template <typename T>
 hipError_t launch_mean(hipStream_t s, long ncell, const T* M, double* parts, int nparts);
 hipError_t launch_reduce_sum3(hipStream_t s, const double* parts, int nparts, double* out);

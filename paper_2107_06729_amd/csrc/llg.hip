@@ -121,8 +121,9 @@ __global__ __launch_bounds__(NTS) void k_epoly_scalar(long n, EPoly<T> ep) {
 // per-cell sub-step kernels on a 2-D grid: blockDim (TX, RY), blockIdx.x over
 // row groups (row = y + ny z), blockIdx.y over x segments
 struct CellIdx {
-    int x, y, z;
-    long cell;
+    int x, y, z, b;   // cell coordinates and sample
+    long cell;        // cell index within the sample
+    long off;         // offset of the sample's [3][N] block
     bool ok;
 };
 
@@ -131,21 +132,26 @@ __device__ __forceinline__ CellIdx cell_index(const Phys<T>& ph) {
     CellIdx c;
     c.x = blockIdx.y * blockDim.x + threadIdx.x;
     const int row = blockIdx.x * blockDim.y + threadIdx.y;
-    c.ok = c.x < ph.nx && row < ph.ny * ph.nz;
-    c.y = row % ph.ny;
-    c.z = row / ph.ny;
-    c.cell = (long)row * ph.nx + c.x;
+    const int rows = ph.ny * ph.nz;
+    c.ok = c.x < ph.nx && row < rows * ph.nb;
+    c.b = row / rows;
+    const int rl = row - c.b * rows;
+    c.y = rl % ph.ny;
+    c.z = rl / ph.ny;
+    c.cell = (long)rl * ph.nx + c.x;
+    c.off = (long)c.b * 3 * ((long)rows * ph.nx);
     return c;
 }
 
 template <typename T, int NG>
 __device__ __forceinline__ void stage_rhs(const T* __restrict__ Mk, const Extrap<T>& ex, const Phys<T>& ph,
                                           const CellIdx& ci, long N, T m[3], T f[3]) {
+    Mk += ci.off;
     T g[NG][3];
 #pragma unroll
     for (int i = 0; i < NG; ++i)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) g[i][c] = ex.g[i][c * N + ci.cell];
+        for (int c = 0; c < 3; ++c) g[i][c] = ex.g[i][ci.off + c * N + ci.cell];
     T hd[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -155,7 +161,7 @@ __device__ __forceinline__ void stage_rhs(const T* __restrict__ Mk, const Extrap
         hd[c] = acc;
     }
     T H[3];
-    heff_at(Mk, N, ci.cell, ci.x, ci.y, ci.z, ph, hd, m, H);
+    heff_at(Mk, N, ci.cell, ci.x, ci.y, ci.z, ci.b, ph, hd, m, H);
     llg_at(m, H, ph, f);
 }
 
@@ -168,7 +174,7 @@ __global__ __launch_bounds__(NTS) void k_stage(const T* __restrict__ Mk, Extrap<
     T m[3], f[3];
     stage_rhs<T, NG>(Mk, ex, ph, ci, N, m, f);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) F[c * N + ci.cell] = f[c];
+    for (int c = 0; c < 3; ++c) F[ci.off + c * N + ci.cell] = f[c];
 }
 
 // last sub-step fused with Eq. (3): fs lists the stage derivatives used by
@@ -188,11 +194,11 @@ __global__ __launch_bounds__(NTS) void k_stage_final(const T* __restrict__ Mk, E
         stage_rhs<T, NG>(Mk, ex, ph, ci, N, m, fS);
         T m0[3], f[NF > 1 ? NF - 1 : 1][3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) m0[c] = M0[c * N + ci.cell];
+        for (int c = 0; c < 3; ++c) m0[c] = M0[ci.off + c * N + ci.cell];
 #pragma unroll
         for (int k = 0; k < NF - 1; ++k)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) f[k][c] = fs.f[k][c * N + ci.cell];
+            for (int c = 0; c < 3; ++c) f[k][c] = fs.f[k][ci.off + c * N + ci.cell];
         double e2 = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -200,7 +206,7 @@ __global__ __launch_bounds__(NTS) void k_stage_final(const T* __restrict__ Mk, E
 #pragma unroll
             for (int k = 0; k < NF - 1; ++k) v += fs.cb[k] * f[k][c];
             v += fs.cb[NF - 1] * fS[c];
-            mnew[c * N + ci.cell] = v;
+            mnew[ci.off + c * N + ci.cell] = v;
             if (fs.err) {
                 double d = 0.0;
 #pragma unroll
@@ -225,25 +231,27 @@ __global__ __launch_bounds__(NTS) void k_stage_final(const T* __restrict__ Mk, E
 }
 
 template <typename T, int NF>
-__global__ __launch_bounds__(NTS) void k_final(long ncell, const T* __restrict__ base, Final<T> fs, double inv_ms,
-                                               T* __restrict__ mnew, double* __restrict__ parts) {
+__global__ __launch_bounds__(NTS) void k_final(long ncell, int nb, const T* __restrict__ base, Final<T> fs,
+                                               double inv_ms, T* __restrict__ mnew, double* __restrict__ parts) {
     __shared__ double red[NTS];
     double emax = 0.0;
-    for (long cell = (long)blockIdx.x * NTS + threadIdx.x; cell < ncell; cell += (long)gridDim.x * NTS) {
+    for (long ic = (long)blockIdx.x * NTS + threadIdx.x; ic < ncell * nb; ic += (long)gridDim.x * NTS) {
+        const long b = ic / ncell, cell = ic - b * ncell;
+        const long o = b * 3 * ncell;
         T m0[3], f[NF][3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) m0[c] = base[c * ncell + cell];
+        for (int c = 0; c < 3; ++c) m0[c] = base[o + c * ncell + cell];
 #pragma unroll
         for (int k = 0; k < NF; ++k)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) f[k][c] = fs.f[k][c * ncell + cell];
+            for (int c = 0; c < 3; ++c) f[k][c] = fs.f[k][o + c * ncell + cell];
         double e2 = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             T v = m0[c];
 #pragma unroll
             for (int k = 0; k < NF; ++k) v += fs.cb[k] * f[k][c];
-            mnew[c * ncell + cell] = v;
+            mnew[o + c * ncell + cell] = v;
             if (fs.err) {
                 double d = 0.0;
 #pragma unroll
@@ -287,13 +295,15 @@ __global__ __launch_bounds__(NTS) void k_reduce_max(const double* __restrict__ p
 }
 
 template <typename T>
-__global__ __launch_bounds__(NTS) void k_renorm(long ncell, T* __restrict__ M, double Ms) {
-    for (long cell = (long)blockIdx.x * NTS + threadIdx.x; cell < ncell; cell += (long)gridDim.x * NTS) {
-        const double x = M[cell], y = M[ncell + cell], z = M[2 * ncell + cell];
+__global__ __launch_bounds__(NTS) void k_renorm(long ncell, int nb, T* __restrict__ M, double Ms) {
+    for (long ic = (long)blockIdx.x * NTS + threadIdx.x; ic < ncell * nb; ic += (long)gridDim.x * NTS) {
+        const long b = ic / ncell, cell = ic - b * ncell;
+        T* m = M + b * 3 * ncell;
+        const double x = m[cell], y = m[ncell + cell], z = m[2 * ncell + cell];
         const double s = Ms / sqrt(x * x + y * y + z * z);
-        M[cell] = (T)(x * s);
-        M[ncell + cell] = (T)(y * s);
-        M[2 * ncell + cell] = (T)(z * s);
+        m[cell] = (T)(x * s);
+        m[ncell + cell] = (T)(y * s);
+        m[2 * ncell + cell] = (T)(z * s);
     }
 }
 
@@ -356,11 +366,11 @@ static unsigned grid_for(long n) {
     return (unsigned)(b < 1 ? 1 : b);
 }
 
-CellGrid cell_grid(int nx, int ny, int nz) {
+CellGrid cell_grid(int nx, int ny, int nz, int nb) {
     int tx = 1;
     while (tx < nx && tx < NTS) tx <<= 1;
     const int ry = NTS / tx;
-    const long rows = (long)ny * nz;
+    const long rows = (long)ny * nz * nb;
     CellGrid g;
     g.block = dim3((unsigned)tx, (unsigned)ry, 1);
     g.grid = dim3((unsigned)((rows + ry - 1) / ry), (unsigned)((nx + tx - 1) / tx), 1);
@@ -416,7 +426,7 @@ hipError_t launch_epoly(hipStream_t s, long n, const EPoly<T>& ep) {
 
 template <typename T>
 hipError_t launch_extrap_rhs(hipStream_t s, const T* Mk, const Extrap<T>& ex, const Phys<T>& ph, T* F) {
-    const CellGrid cg = cell_grid(ph.nx, ph.ny, ph.nz);
+    const CellGrid cg = cell_grid(ph.nx, ph.ny, ph.nz, ph.nb);
     switch (ex.n) {
 #define EX(K) \
     case K: k_stage<T, K><<<cg.grid, cg.block, 0, s>>>(Mk, ex, ph, F); break;
@@ -430,7 +440,7 @@ hipError_t launch_extrap_rhs(hipStream_t s, const T* Mk, const Extrap<T>& ex, co
 template <typename T>
 hipError_t launch_stage_final(hipStream_t s, const T* Mk, const Extrap<T>& ex, const Phys<T>& ph, const T* M0,
                               const Final<T>& fs, double inv_ms, T* mnew, double* parts) {
-    const CellGrid cg = cell_grid(ph.nx, ph.ny, ph.nz);
+    const CellGrid cg = cell_grid(ph.nx, ph.ny, ph.nz, ph.nb);
     if (ex.n != 1) return hipErrorInvalidValue;
     switch (fs.n) {
 #define SF(K) \
@@ -443,11 +453,11 @@ hipError_t launch_stage_final(hipStream_t s, const T* Mk, const Extrap<T>& ex, c
 }
 
 template <typename T>
-hipError_t launch_final(hipStream_t s, long ncell, const T* base, const Final<T>& fs, double inv_ms, T* mnew,
+hipError_t launch_final(hipStream_t s, long ncell, int nb, const T* base, const Final<T>& fs, double inv_ms, T* mnew,
                         double* parts, int nparts) {
     switch (fs.n) {
 #define FN(K) \
-    case K: k_final<T, K><<<(unsigned)nparts, NTS, 0, s>>>(ncell, base, fs, inv_ms, mnew, parts); break;
+    case K: k_final<T, K><<<(unsigned)nparts, NTS, 0, s>>>(ncell, nb, base, fs, inv_ms, mnew, parts); break;
         FN(1) FN(2) FN(3) FN(4) FN(5) FN(6) FN(7) FN(8)
 #undef FN
         default: return hipErrorInvalidValue;
@@ -461,8 +471,8 @@ hipError_t launch_reduce_max(hipStream_t s, const double* parts, int nparts, dou
 }
 
 template <typename T>
-hipError_t launch_renorm(hipStream_t s, long ncell, T* M, double Ms) {
-    k_renorm<T><<<grid_for(ncell), NTS, 0, s>>>(ncell, M, Ms);
+hipError_t launch_renorm(hipStream_t s, long ncell, int nb, T* M, double Ms) {
+    k_renorm<T><<<grid_for(ncell * nb), NTS, 0, s>>>(ncell, nb, M, Ms);
     return hipGetLastError();
 }
 
@@ -489,8 +499,9 @@ hipError_t launch_cast(hipStream_t s, long n, const double* src, T* dst) {
     template hipError_t launch_extrap_rhs<T>(hipStream_t, const T*, const Extrap<T>&, const Phys<T>&, T*);        \
     template hipError_t launch_stage_final<T>(hipStream_t, const T*, const Extrap<T>&, const Phys<T>&, const T*,  \
                                               const Final<T>&, double, T*, double*);                             \
-    template hipError_t launch_final<T>(hipStream_t, long, const T*, const Final<T>&, double, T*, double*, int); \
-    template hipError_t launch_renorm<T>(hipStream_t, long, T*, double);                                         \
+    template hipError_t launch_final<T>(hipStream_t, long, int, const T*, const Final<T>&, double, T*, double*,  \
+                                        int);                                                                    \
+    template hipError_t launch_renorm<T>(hipStream_t, long, int, T*, double);                                    \
     template hipError_t launch_mean<T>(hipStream_t, long, const T*, double*, int);                               \
     template hipError_t launch_cast<T>(hipStream_t, long, const double*, T*);
 INST(float)

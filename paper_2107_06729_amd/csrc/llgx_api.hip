@@ -49,7 +49,9 @@ struct Ctx {
 
     // plan
     int nx = 1, ny = 1, nz = 1;
-    long ncell = 1;
+    long ncell = 1;             // cells per sample
+    int nb = 1;                 // samples sharing this mesh (batched launches)
+    void* hab = nullptr;        // per-sample applied fields [nb][3] (device, working precision)
     int Px = 1, Py = 1, Pz = 1, LX = 0, Kx = 1, SX = 16, Kyf = 1, Kzf = 1;
 
     // device workspace
@@ -209,6 +211,8 @@ static Phys<T> phys(const Ctx* c) {
     ph.nx = c->nx;
     ph.ny = c->ny;
     ph.nz = c->nz;
+    ph.nb = c->nb;
+    ph.hab = (const T*)c->hab;
     return ph;
 }
 
@@ -223,7 +227,7 @@ static llgx_status eval_exact(Ctx* c, const Combo<T>& in, T* mk_out, int mode, c
     const cx<T>* twP = table<T>(c, c->Px, false);
     {
         PROF(LLGX_K_XFWD);
-        HIPCHK(c, launch_xfwd<T>(s, c->LX, in, mk_out, c->nx, 3L * c->ny * c->nz, A, c->SX, twL, twP));
+        HIPCHK(c, launch_xfwd<T>(s, c->LX, in, mk_out, c->nx, 3L * c->ny * c->nz * c->nb, A, c->SX, twL, twP));
     }
     cx<T>* work = A;
     int nyrows = c->ny;
@@ -232,21 +236,23 @@ static llgx_status eval_exact(Ctx* c, const Combo<T>& in, T* mk_out, int mode, c
         const long sa = (long)c->nz * c->ny * c->SX, sb = (long)c->nz * c->Py * c->SX;
         PROF(LLGX_K_YFWD);
         HIPCHK(c, launch_colfft<T>(s, c->Py, false, A, sa, (long)c->ny * c->SX, c->SX, c->ny, B, sb,
-                                   (long)c->Py * c->SX, c->SX, c->Py, c->Kx, c->nz, 3, table<T>(c, c->Py, false)));
+                                   (long)c->Py * c->SX, c->SX, c->Py, c->Kx, c->nz, 3 * c->nb,
+                                   table<T>(c, c->Py, false)));
         work = B;
         nyrows = c->Py;
     }
     {
         PROF(LLGX_K_ZMUL);
         HIPCHK(c, launch_zmul<T>(s, c->Pz, work, c->SX, c->Kx, c->nz, nyrows, c->Py, c->Pz, (const T*)c->kfold,
-                                 c->Kyf, c->Kzf, table<T>(c, c->Pz, false)));
+                                 c->Kyf, c->Kzf, table<T>(c, c->Pz, false), c->nb));
     }
     if (c->Py > 1) {
         cx<T>* B = (cx<T>*)c->specB;
         const long sa = (long)c->nz * c->ny * c->SX, sb = (long)c->nz * c->Py * c->SX;
         PROF(LLGX_K_YINV);
         HIPCHK(c, launch_colfft<T>(s, c->Py, true, B, sb, (long)c->Py * c->SX, c->SX, c->Py, A, sa,
-                                   (long)c->ny * c->SX, c->SX, c->ny, c->Kx, c->nz, 3, table<T>(c, c->Py, false)));
+                                   (long)c->ny * c->SX, c->SX, c->ny, c->Kx, c->nz, 3 * c->nb,
+                                   table<T>(c, c->Py, false)));
     }
     {
         PROF(LLGX_K_XINV);
@@ -421,7 +427,7 @@ static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
                 ep.out[j] = (T*)c->E[j];
             }
             PROF(LLGX_K_EPOLY);
-            HIPCHK(c, launch_epoly<T>(c->stream, 3 * c->ncell, ep));
+            HIPCHK(c, launch_epoly<T>(c->stream, 3 * c->ncell * c->nb, ep));
         }
     }
     // Eq. (3) operands: stage derivatives used by the update or by the estimate
@@ -455,7 +461,7 @@ static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
         if (pl.extrap) {
             {
                 PROF(LLGX_K_COMBINE);
-                HIPCHK(c, launch_combine<T>(c->stream, 3 * c->ncell, cb, (T*)c->Mk));
+                HIPCHK(c, launch_combine<T>(c->stream, 3 * c->ncell * c->nb, cb, (T*)c->Mk));
             }
             Extrap<T> ex{};
             ex.n = 1;
@@ -478,11 +484,11 @@ static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
     }
     int nred = c->nparts;
     if (fused_final) {
-        nred = (int)cell_grid(c->nx, c->ny, c->nz).nblocks;
+        nred = (int)cell_grid(c->nx, c->ny, c->nz, c->nb).nblocks;
     } else {
         PROF(LLGX_K_FINAL);
-        HIPCHK(c, launch_final<T>(c->stream, c->ncell, (const T*)c->M, fs, 1.0 / c->p.Ms, (T*)c->Mnew, c->parts,
-                                  c->nparts));
+        HIPCHK(c, launch_final<T>(c->stream, c->ncell, c->nb, (const T*)c->M, fs, 1.0 / c->p.Ms, (T*)c->Mnew,
+                                  c->parts, c->nparts));
     }
     if (pl.want_err) {
         PROF(LLGX_K_OTHER);
@@ -595,7 +601,7 @@ static llgx_status do_step(Ctx* c, const llgx_stepper* s, llgx_step_info* info) 
     if (st) return st;
     if (s->renormalize) {
         PROF(LLGX_K_OTHER);
-        HIPCHK(c, launch_renorm<T>(c->stream, c->ncell, (T*)c->M, c->p.Ms));
+        HIPCHK(c, launch_renorm<T>(c->stream, c->ncell, c->nb, (T*)c->M, c->p.Ms));
     }
     c->h_next = s->adaptive ? h_next : h;
     c->n_rej += rejected;
@@ -668,7 +674,7 @@ static llgx_status do_run_fixed(Ctx* c, const llgx_stepper* s, int64_t nsteps, i
         c->n_extrap += pl.extrap ? tab->S - 1 : 0;
         st = commit<T>(c, pl, s->h);
         if (st) return st;
-        if (s->renormalize) HIPCHK(c, launch_renorm<T>(c->stream, c->ncell, (T*)c->M, c->p.Ms));
+        if (s->renormalize) HIPCHK(c, launch_renorm<T>(c->stream, c->ncell, c->nb, (T*)c->M, c->p.Ms));
         c->h_next = s->h;
         if (info) {
             info->t = c->t;
@@ -748,7 +754,7 @@ static void release(Ctx* c) {
     for (auto e : c->spare) (void)hipEventDestroy(e);
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
-    void* ptrs[] = {c->kfold, c->specA, c->specB, c->M, c->Mnew, c->Mk, c->parts, c->scal, c->octant};
+    void* ptrs[] = {c->kfold, c->specA, c->specB, c->M, c->Mnew, c->Mk, c->parts, c->scal, c->octant, c->hab};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (int i = 0; i < MAX_F; ++i)
@@ -791,25 +797,26 @@ void llgx_stepper_defaults(llgx_stepper* s) {
     s->e_max = 1e-5;
 }
 
-llgx_status llgx_create(const llgx_problem* p, int32_t precision, int32_t spectral, void* hip_stream,
-                        llgx_handle* out) {
-    g_create_error.clear();
-    if (!p || !out) {
-        g_create_error = "null argument";
-        return LLGX_E_ARG;
-    }
+}  // extern "C"
+
+namespace llgx {
+
+// Context for nb samples of one problem (differing only in the applied field,
+// ha_list[nb][3], or all equal to p->Ha when ha_list is null).
+static llgx_status create_ctx(const llgx_problem* p, int nb, const double* ha_list, int32_t precision,
+                              int32_t spectral, void* hip_stream, Ctx** out, std::string& err) {
     *out = nullptr;
     if (p->nx < 1 || p->ny < 1 || p->nz < 1 || !(p->dx > 0) || !(p->dy > 0) || !(p->dz > 0) || !(p->Ms > 0) ||
         !(p->gamma > 0) || p->A < 0 || p->alpha < 0) {
-        g_create_error = "invalid problem (sizes >= 1, cell > 0, Ms > 0, gamma > 0, A >= 0, alpha >= 0)";
+        err = "invalid problem (sizes >= 1, cell > 0, Ms > 0, gamma > 0, A >= 0, alpha >= 0)";
         return LLGX_E_ARG;
     }
     if (precision != LLGX_F32 && precision != LLGX_F64) {
-        g_create_error = "precision must be LLGX_F32 or LLGX_F64";
+        err = "precision must be LLGX_F32 or LLGX_F64";
         return LLGX_E_ARG;
     }
     if (spectral != LLGX_SPEC_NATIVE) {
-        g_create_error = "16-bit spectral storage is not available in this build";
+        err = "16-bit spectral storage is not available in this build";
         return LLGX_E_UNSUPPORTED;
     }
     Ctx* c = new Ctx();
@@ -821,12 +828,13 @@ llgx_status llgx_create(const llgx_problem* p, int32_t precision, int32_t spectr
     c->nx = p->nx;
     c->ny = p->ny;
     c->nz = p->nz;
+    c->nb = nb;
     c->ncell = (long)p->nx * p->ny * p->nz;
     c->Px = p->nx > 1 ? next_pow2(2L * p->nx - 1) : 1;
     c->Py = p->ny > 1 ? next_pow2(2L * p->ny - 1) : 1;
     c->Pz = p->nz > 1 ? next_pow2(2L * p->nz - 1) : 1;
     if (c->Px > MAX_LEN || c->Py > MAX_LEN || c->Pz > MAX_LEN / 2) {
-        g_create_error = "mesh too large: padded FFT length above 2048 (x, y) or 1024 (z)";
+        err = "mesh too large: padded FFT length above 2048 (x, y) or 1024 (z)";
         delete c;
         return LLGX_E_UNSUPPORTED;
     }
@@ -836,23 +844,43 @@ llgx_status llgx_create(const llgx_problem* p, int32_t precision, int32_t spectr
     c->Kyf = c->Py > 1 ? c->Py / 2 + 1 : 1;
     c->Kzf = c->Pz > 1 ? c->Pz / 2 + 1 : 1;
     const size_t cbytes = 2 * c->tsz;
-    const size_t vbytes = 3 * (size_t)c->ncell * c->tsz;
+    const size_t vbytes = 3 * (size_t)c->ncell * nb * c->tsz;
     llgx_status st = LLGX_OK;
     auto A = [&](void** ptr, size_t bytes) {
         if (st == LLGX_OK) st = dalloc(c, ptr, bytes);
     };
-    A(&c->specA, 3 * (size_t)c->nz * c->ny * c->SX * cbytes);
-    if (c->Py > 1) A(&c->specB, 3 * (size_t)c->nz * c->Py * c->SX * cbytes);
+    const size_t bytesA = 3 * (size_t)c->nz * c->ny * c->SX * cbytes * nb;
+    const size_t bytesB = 3 * (size_t)c->nz * c->Py * c->SX * cbytes * nb;
+    A(&c->specA, bytesA);
+    if (c->Py > 1) A(&c->specB, bytesB);
     A(&c->M, vbytes);
     A(&c->Mnew, vbytes);
     A(&c->Mk, vbytes);
     for (int i = 0; i < MAX_F; ++i) A(&c->F[i], vbytes);
     for (int i = 0; i < MAX_HIST; ++i) A(&c->G[i], vbytes);
     for (int i = 0; i < MAX_F - 1; ++i) A(&c->E[i], vbytes);
-    c->nparts = (int)std::min<long>(1024, std::max<long>(1, (c->ncell + 255) / 256));
-    c->nparts_alloc = std::max<long>(c->nparts, cell_grid(c->nx, c->ny, c->nz).nblocks);
+    c->nparts = (int)std::min<long>(1024, std::max<long>(1, (c->ncell * nb + 255) / 256));
+    c->nparts_alloc = std::max<long>(c->nparts, cell_grid(c->nx, c->ny, c->nz, nb).nblocks);
     A((void**)&c->parts, 3 * (size_t)c->nparts_alloc * sizeof(double));
     A((void**)&c->scal, 8 * sizeof(double));
+    if (ha_list) A(&c->hab, 3 * (size_t)nb * c->tsz);
+    if (st == LLGX_OK) {
+        // padding columns of the spectra are read (never used) by 16-byte packs: keep them zero
+        if (hipMemset(c->specA, 0, bytesA) != hipSuccess) st = c->fail(LLGX_E_HIP, "hipMemset failed");
+        if (st == LLGX_OK && c->specB && hipMemset(c->specB, 0, bytesB) != hipSuccess)
+            st = c->fail(LLGX_E_HIP, "hipMemset failed");
+    }
+    if (st == LLGX_OK && ha_list) {
+        std::vector<char> hb(3 * (size_t)nb * c->tsz);
+        for (int i = 0; i < 3 * nb; ++i) {
+            if (c->tsz == 4)
+                ((float*)hb.data())[i] = (float)ha_list[i];
+            else
+                ((double*)hb.data())[i] = ha_list[i];
+        }
+        if (hipMemcpy(c->hab, hb.data(), hb.size(), hipMemcpyHostToDevice) != hipSuccess)
+            st = c->fail(LLGX_E_HIP, "hipMemcpy of applied fields failed");
+    }
     if (st == LLGX_OK) {
         for (int L : {c->LX, c->Px, c->Py, c->Pz}) {
             if (st) break;
@@ -860,12 +888,271 @@ llgx_status llgx_create(const llgx_problem* p, int32_t precision, int32_t spectr
         }
     }
     if (st != LLGX_OK) {
-        g_create_error = c->err;
+        err = c->err;
         release(c);
         delete c;
         return st;
     }
+    *out = c;
+    return LLGX_OK;
+}
+
+// Independent samples grouped by problem (all fields but the applied one):
+// each group is one context whose launches cover all its samples.
+struct Batch {
+    std::vector<Ctx*> groups;
+    std::vector<std::pair<int, int>> where;  // sample -> (group, index in group)
+    hipStream_t stream = nullptr;
+    std::string err;
+    std::map<std::vector<GraphKey>, hipGraphExec_t> graphs;
+};
+
+static bool same_material(const llgx_problem& a, const llgx_problem& b) {
+    return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.dx == b.dx && a.dy == b.dy && a.dz == b.dz &&
+           a.Ms == b.Ms && a.A == b.A && a.K == b.K && a.easy[0] == b.easy[0] && a.easy[1] == b.easy[1] &&
+           a.easy[2] == b.easy[2] && a.alpha == b.alpha && a.gamma == b.gamma;
+}
+
+template <typename T>
+static llgx_status batch_run_fixed(Batch* bt, const llgx_stepper* s, int64_t nsteps, int use_graph) {
+    if (!s || s->adaptive) {
+        bt->err = "batched runs take a fixed step (adaptive = 0)";
+        return LLGX_E_ARG;
+    }
+    for (int64_t i = 0; i < nsteps; ++i) {
+        bool steady = use_graph && bt->stream != nullptr;
+        std::vector<Plan> plans(bt->groups.size());
+        std::vector<GraphKey> keys;
+        for (size_t g = 0; g < bt->groups.size(); ++g) {
+            Ctx* c = bt->groups[g];
+            const Tableau* tab;
+            int p;
+            llgx_status st = check_stepper(c, s, &tab, &p);
+            if (st) {
+                bt->err = c->err;
+                return st;
+            }
+            const bool ok = ((p < 0 && !tab->fsal) || (p >= 0 && (int)c->hist.size() == p) ||
+                             (p < 0 && tab->fsal && s->renormalize)) && !c->prof;
+            for (size_t j = 0; j < c->hist.size(); ++j) {
+                const double expect = -(double)(c->hist.size() - j) * s->h;
+                if (std::fabs((c->hist[j].t - c->t) - expect) > 1e-9 * s->h) steady = false;
+            }
+            steady = steady && ok;
+            Plan& pl = plans[g];
+            pl.tab = tab;
+            pl.p = p;
+            pl.extrap = p >= 0;
+            pl.stage1 = true;
+            pl.slot0 = free_slot(c);
+            pl.want_err = false;
+            pl.h = s->h;
+            GraphKey key{c->M, pl.slot0, {}, s->h};
+            for (auto& hh : c->hist) key.hist_slots.push_back(hh.slot);
+            keys.push_back(key);
+        }
+        if (!steady) {
+            for (Ctx* c : bt->groups) {
+                llgx_status st = do_step<T>(c, s, nullptr);
+                if (st) {
+                    bt->err = c->err;
+                    return st;
+                }
+            }
+            continue;
+        }
+        auto it = bt->graphs.find(keys);
+        if (it == bt->graphs.end()) {
+            hipGraph_t gr;
+            if (hipStreamBeginCapture(bt->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+                bt->err = "graph capture could not start";
+                return LLGX_E_HIP;
+            }
+            llgx_status st = LLGX_OK;
+            for (size_t g = 0; g < bt->groups.size() && st == LLGX_OK; ++g) {
+                st = enqueue_attempt<T>(bt->groups[g], plans[g]);
+                if (st) bt->err = bt->groups[g]->err;
+            }
+            hipError_t e2 = hipStreamEndCapture(bt->stream, &gr);
+            if (st) return st;
+            if (e2 != hipSuccess) {
+                bt->err = std::string("graph capture failed: ") + hipGetErrorString(e2);
+                return LLGX_E_HIP;
+            }
+            hipGraphExec_t ge;
+            if (hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0) != hipSuccess) {
+                (void)hipGraphDestroy(gr);
+                bt->err = "graph instantiation failed";
+                return LLGX_E_HIP;
+            }
+            (void)hipGraphDestroy(gr);
+            it = bt->graphs.emplace(keys, ge).first;
+        }
+        if (hipGraphLaunch(it->second, bt->stream) != hipSuccess) {
+            bt->err = "graph launch failed";
+            return LLGX_E_HIP;
+        }
+        for (size_t g = 0; g < bt->groups.size(); ++g) {
+            Ctx* c = bt->groups[g];
+            const Plan& pl = plans[g];
+            c->n_exact += 1 + (pl.extrap ? 0 : pl.tab->S - 1);
+            c->n_extrap += pl.extrap ? pl.tab->S - 1 : 0;
+            llgx_status st = commit<T>(c, pl, s->h);
+            if (st) return st;
+            if (s->renormalize && launch_renorm<T>(c->stream, c->ncell, c->nb, (T*)c->M, c->p.Ms) != hipSuccess) {
+                bt->err = "renormalisation launch failed";
+                return LLGX_E_HIP;
+            }
+            c->h_next = s->h;
+        }
+    }
+    return LLGX_OK;
+}
+
+}  // namespace llgx
+
+extern "C" {
+
+llgx_status llgx_create(const llgx_problem* p, int32_t precision, int32_t spectral, void* hip_stream,
+                        llgx_handle* out) {
+    g_create_error.clear();
+    if (!p || !out) {
+        g_create_error = "null argument";
+        return LLGX_E_ARG;
+    }
+    Ctx* c = nullptr;
+    llgx_status st = create_ctx(p, 1, nullptr, precision, spectral, hip_stream, &c, g_create_error);
     *out = (llgx_handle)c;
+    return st;
+}
+
+llgx_status llgx_batch_create(int32_t n, const llgx_problem* problems, int32_t precision, void* hip_stream,
+                              llgx_batch* out) {
+    g_create_error.clear();
+    if (!problems || !out || n < 1) {
+        g_create_error = "null argument or n < 1";
+        return LLGX_E_ARG;
+    }
+    *out = nullptr;
+    Batch* bt = new Batch();
+    bt->stream = (hipStream_t)hip_stream;
+    std::vector<std::vector<int>> members;
+    for (int i = 0; i < n; ++i) {
+        int g = -1;
+        for (size_t q = 0; q < members.size(); ++q)
+            if (same_material(problems[members[q][0]], problems[i])) g = (int)q;
+        if (g < 0) {
+            g = (int)members.size();
+            members.push_back({});
+        }
+        bt->where.push_back({g, (int)members[g].size()});
+        members[g].push_back(i);
+    }
+    for (auto& mem : members) {
+        std::vector<double> ha;
+        for (int i : mem)
+            for (int c = 0; c < 3; ++c) ha.push_back(problems[i].Ha[c]);
+        Ctx* c = nullptr;
+        llgx_status st = create_ctx(&problems[mem[0]], (int)mem.size(), ha.data(), precision, LLGX_SPEC_NATIVE,
+                                    hip_stream, &c, g_create_error);
+        if (st) {
+            for (Ctx* q : bt->groups) {
+                release(q);
+                delete q;
+            }
+            delete bt;
+            return st;
+        }
+        bt->groups.push_back(c);
+    }
+    *out = (llgx_batch)bt;
+    return LLGX_OK;
+}
+
+void llgx_batch_destroy(llgx_batch b) {
+    if (!b) return;
+    Batch* bt = (Batch*)b;
+    (void)hipStreamSynchronize(bt->stream);
+    for (auto& kv : bt->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (Ctx* c : bt->groups) {
+        release(c);
+        delete c;
+    }
+    delete bt;
+}
+
+const char* llgx_batch_last_error(llgx_batch b) {
+    if (!b) return g_create_error.c_str();
+    return ((Batch*)b)->err.c_str();
+}
+
+llgx_status llgx_batch_precompute_demag(llgx_batch b) {
+    if (!b) return LLGX_E_ARG;
+    Batch* bt = (Batch*)b;
+    for (Ctx* c : bt->groups) {
+        if (c->have_kernel) continue;
+        llgx_status st = precompute(c);
+        if (st) {
+            bt->err = c->err;
+            return st;
+        }
+    }
+    return LLGX_OK;
+}
+
+static llgx_status batch_copy(llgx_batch b, int32_t i, const void* src, void* dst_or_null, bool set) {
+    Batch* bt = (Batch*)b;
+    if (i < 0 || i >= (int)bt->where.size()) {
+        bt->err = "sample index out of range";
+        return LLGX_E_ARG;
+    }
+    Ctx* c = bt->groups[bt->where[i].first];
+    const size_t bytes = 3 * (size_t)c->ncell * c->tsz;
+    char* base = (char*)c->M + (size_t)bt->where[i].second * bytes;
+    hipError_t e;
+    if (set) {
+        e = hipMemcpyAsync(base, src, bytes, hipMemcpyDeviceToDevice, c->stream);
+        c->hist.clear();  // the group's Eq. (6) history no longer matches its state
+        c->fsal_valid = false;
+        c->have_m = true;
+    } else {
+        e = hipMemcpyAsync(dst_or_null, base, bytes, hipMemcpyDeviceToDevice, c->stream);
+    }
+    if (e != hipSuccess) {
+        bt->err = std::string("copy failed: ") + hipGetErrorString(e);
+        return LLGX_E_HIP;
+    }
+    return LLGX_OK;
+}
+
+llgx_status llgx_batch_set_m(llgx_batch b, int32_t i, const void* M_dev) {
+    if (!b || !M_dev) return LLGX_E_ARG;
+    return batch_copy(b, i, M_dev, nullptr, true);
+}
+
+llgx_status llgx_batch_get_m(llgx_batch b, int32_t i, void* M_dev) {
+    if (!b || !M_dev) return LLGX_E_ARG;
+    return batch_copy(b, i, nullptr, M_dev, false);
+}
+
+llgx_status llgx_batch_run_fixed(llgx_batch b, const llgx_stepper* s, int64_t nsteps, int32_t use_graph) {
+    if (!b) return LLGX_E_ARG;
+    Batch* bt = (Batch*)b;
+    if (bt->groups.empty()) return LLGX_E_STATE;
+    return bt->groups[0]->prec == LLGX_F32 ? batch_run_fixed<float>(bt, s, nsteps, use_graph)
+                                           : batch_run_fixed<double>(bt, s, nsteps, use_graph);
+}
+
+llgx_status llgx_batch_info(llgx_batch b, int32_t* ngroups, int64_t* total_cells, double* t) {
+    if (!b) return LLGX_E_ARG;
+    Batch* bt = (Batch*)b;
+    if (ngroups) *ngroups = (int32_t)bt->groups.size();
+    if (total_cells) {
+        int64_t n = 0;
+        for (Ctx* c : bt->groups) n += c->ncell * c->nb;
+        *total_cells = n;
+    }
+    if (t) *t = bt->groups.empty() ? 0.0 : bt->groups[0]->t;
     return LLGX_OK;
 }
 
@@ -921,7 +1208,7 @@ llgx_status llgx_set_m(llgx_handle h, const void* M_dev) {
     if (!h) return LLGX_E_ARG;
     Ctx* c = (Ctx*)h;
     if (!M_dev) return c->fail(LLGX_E_ARG, "null M");
-    HIPCHK(c, hipMemcpyAsync(c->M, M_dev, 3 * (size_t)c->ncell * c->tsz, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->M, M_dev, 3 * (size_t)c->ncell * c->nb * c->tsz, hipMemcpyDeviceToDevice, c->stream));
     c->have_m = true;
     c->hist.clear();
     c->fsal_valid = false;
@@ -933,7 +1220,7 @@ llgx_status llgx_get_m(llgx_handle h, void* M_dev) {
     Ctx* c = (Ctx*)h;
     if (!M_dev) return c->fail(LLGX_E_ARG, "null M");
     if (!c->have_m) return c->fail(LLGX_E_STATE, "magnetization not set");
-    HIPCHK(c, hipMemcpyAsync(M_dev, c->M, 3 * (size_t)c->ncell * c->tsz, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(M_dev, c->M, 3 * (size_t)c->ncell * c->nb * c->tsz, hipMemcpyDeviceToDevice, c->stream));
     return LLGX_OK;
 }
 

@@ -8,9 +8,11 @@
 
 namespace llgx {
 
+// M points at the sample's own [3][N] block; b is the sample index (applied field)
 template <typename T>
-__device__ __forceinline__ void heff_at(const T* __restrict__ M, long N, long cell, int x, int y, int z,
+__device__ __forceinline__ void heff_at(const T* __restrict__ M, long N, long cell, int x, int y, int z, int b,
                                         const Phys<T>& ph, const T hd[3], T m[3], T H[3]) {
+    const T* ha = ph.hab ? ph.hab + 3 * b : ph.ha;
     const long sy = ph.nx, sz = (long)ph.nx * ph.ny;
 #pragma unroll
     for (int c = 0; c < 3; ++c) m[c] = M[c * N + cell];
@@ -22,7 +24,7 @@ __device__ __forceinline__ void heff_at(const T* __restrict__ M, long N, long ce
         const T xm = x > 0 ? Mc[cell - 1] : mc, xp = x + 1 < ph.nx ? Mc[cell + 1] : mc;
         const T ym = y > 0 ? Mc[cell - sy] : mc, yp = y + 1 < ph.ny ? Mc[cell + sy] : mc;
         const T zm = z > 0 ? Mc[cell - sz] : mc, zp = z + 1 < ph.nz ? Mc[cell + sz] : mc;
-        H[c] = hd[c] + ph.ha[c] + ph.exx * ((xm + xp) - T(2) * mc) + ph.exy * ((ym + yp) - T(2) * mc) +
+        H[c] = hd[c] + ha[c] + ph.exx * ((xm + xp) - T(2) * mc) + ph.exy * ((ym + yp) - T(2) * mc) +
                ph.exz * ((zm + zp) - T(2) * mc);
     }
     const T mu = m[0] * ph.u[0] + m[1] * ph.u[1] + m[2] * ph.u[2];
