@@ -123,6 +123,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=200)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -285,6 +286,32 @@ def main():
             sa.close()
         extras["rkdp54_speedup_f32_p4_over_f64_full"] = (extras["rkdp54_f32_p4_sim_ns_per_h"]
                                                           / extras["rkdp54_f64_full_sim_ns_per_h"])
+
+        # ---- batched sweep: 64 samples over 4 meshes, RK4 h = 50 fs, FP32 ---
+        log("batch of 64 samples ...")
+        samples = workloads.batch_samples(64)
+        for tag, ex in (("p4", p), ("full", None)):
+            bt = llgx.Batch([q for q, _ in samples], "f32", stream=stream)
+            bt.precompute_demag()
+            with torch.cuda.stream(stream):
+                for i, (q, seed) in enumerate(samples):
+                    bt.set_m(i, torch.as_tensor(workloads.random_m(q["n"], q["Ms"], seed), dtype=torch.float32,
+                                                device=dev))
+            stb = llgx.make_stepper("RK4", extrap=ex, h=5e-14)
+            bt.run_fixed(stb, p + 20, use_graph=True)
+            torch.cuda.synchronize()
+            kb_ = args.batch_steps
+            t0 = time.perf_counter()
+            bt.run_fixed(stb, kb_, use_graph=True)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            inf = bt.info()
+            extras[f"batch64_{tag}_ms_per_step"] = 1e3 * wall / kb_
+            extras[f"batch64_{tag}_field_evals_per_s"] = 4 * 64 * kb_ / wall
+            extras[f"batch64_{tag}_sample_ns_per_h"] = 64 * 5e-14 * 1e9 * kb_ / wall * 3600.0
+            extras["batch64_groups"] = inf["groups"]
+            extras["batch64_cells"] = inf["cells"]
+            bt.close()
 
     cpu = None
     if not args.no_cpu:

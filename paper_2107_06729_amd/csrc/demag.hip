@@ -18,6 +18,7 @@
 
 #include "kernels.hpp"
 #include "physics.hpp"
+#include "spec_store.hpp"
 #include "tile_io.hpp"
 
 namespace llgx {
@@ -58,10 +59,11 @@ __device__ __forceinline__ T combo_at(const Combo<T>& c, long i) {
 // A real sequence of length P = 2 LX is packed as z[j] = x[2j] + i x[2j+1],
 // transformed with a length-LX complex FFT and split with
 //   X[k] = (Z[k] + Z*[LX-k])/2 - i e^{-2 pi i k/P} (Z[k] - Z*[LX-k])/2.
-template <typename T, int LX, int ROWS>
+template <typename T, typename S, int LX, int ROWS>
 __global__ __launch_bounds__(NT) void k_xfwd(Combo<T> in, T* __restrict__ mk_out, int nin, long nrows,
-                                             cx<T>* __restrict__ spec, int SX, const cx<T>* __restrict__ twL,
-                                             const cx<T>* __restrict__ twP) {
+                                             typename Spec<T, S>::elem* __restrict__ spec, int SX,
+                                             const cx<T>* __restrict__ twL, const cx<T>* __restrict__ twP,
+                                             T fscale) {
     using C = cx<T>;
     const long row0 = (long)blockIdx.x * ROWS;
     if constexpr (LX == 0) {
@@ -70,7 +72,7 @@ __global__ __launch_bounds__(NT) void k_xfwd(Combo<T> in, T* __restrict__ mk_out
             if (g < nrows) {
                 const T v = combo_at(in, g);
                 if (mk_out) mk_out[g] = v;
-                spec[g * SX] = C{v, T(0)};
+                spec[g * SX] = Spec<T, S>::put(C{v * fscale, T(0)});
             }
         }
         return;
@@ -130,7 +132,7 @@ __global__ __launch_bounds__(NT) void k_xfwd(Combo<T> in, T* __restrict__ mk_out
             const int e = threadIdx.x + m * NT;
             if (TOT % NT != 0 && e >= TOT) continue;
             const int r = e / LX, i = e - r * LX;
-            buf[r * CS + i] = v[m];
+            buf[r * CS + i] = C{v[m].x * fscale, v[m].y * fscale};
             if (mk_out && ok[m]) {
                 mk_out[off[m]] = v[m].x;
                 if (x0[m] + 1 < nin) mk_out[off[m] + 1] = v[m].y;
@@ -148,7 +150,7 @@ __global__ __launch_bounds__(NT) void k_xfwd(Combo<T> in, T* __restrict__ mk_out
             const C zc = cconj(buf[r * CS + ((LX - k) & (LX - 1))]);
             const C E{(zk.x + zc.x) * T(0.5), (zk.y + zc.y) * T(0.5)};
             const C O{(zk.y - zc.y) * T(0.5), (zc.x - zk.x) * T(0.5)};  // -i (zk - zc)/2
-            spec[g * SX + k] = cadd(E, cmul(O, twp[k]));
+            spec[g * SX + k] = Spec<T, S>::put(cadd(E, cmul(O, twp[k])));
         }
     }
 }
@@ -157,10 +159,11 @@ __global__ __launch_bounds__(NT) void k_xfwd(Combo<T> in, T* __restrict__ mk_out
 // inverse x pass: LX+1 complex -> real, keep x < nx; then per cell
 //   Z[k] = (X[k] + X*[LX-k]) + i e^{+2 pi i k/P} (X[k] - X*[LX-k]),
 //   z = IDFT_LX(Z), x[2j] = Re z[j], x[2j+1] = Im z[j].
-template <typename T, int LX, int ROWS, int MODE>
-__global__ __launch_bounds__(NT) void k_xinv(const cx<T>* __restrict__ spec, int SX, const T* __restrict__ M,
-                                             Phys<T> ph, XinvOut out, const cx<T>* __restrict__ twL,
-                                             const cx<T>* __restrict__ twP) {
+template <typename T, typename S, int LX, int ROWS, int MODE>
+__global__ __launch_bounds__(NT) void k_xinv(const typename Spec<T, S>::elem* __restrict__ spec, int SX,
+                                             const T* __restrict__ M, Phys<T> ph, XinvOut out,
+                                             const cx<T>* __restrict__ twL, const cx<T>* __restrict__ twP,
+                                             T hscale) {
     using C = cx<T>;
     constexpr int LXE = LX > 0 ? LX : 1;
     constexpr int CS = LXE + 1;
@@ -177,7 +180,7 @@ __global__ __launch_bounds__(NT) void k_xinv(const cx<T>* __restrict__ spec, int
         for (int lr = threadIdx.x; lr < 3 * ROWS; lr += NT) {
             const int r = lr / 3, c = lr - 3 * r;
             const long g = row0 + r;
-            if (g < nrow) buf[lr * CS] = spec[(c * nrow + g) * SX];
+            if (g < nrow) buf[lr * CS] = Spec<T, S>::get(spec[(c * nrow + g) * SX]);
         }
         __syncthreads();
     } else {
@@ -197,9 +200,9 @@ __global__ __launch_bounds__(NT) void k_xinv(const cx<T>* __restrict__ spec, int
             xb[m] = C{T(0), T(0)};
             wk[m] = twP[k];
             if ((TOT % NT == 0 || e < TOT) && g < nrow) {
-                const cx<T>* row = spec + (c * nrow + g) * SX;
-                xa[m] = row[k];
-                xb[m] = row[LX - k];
+                const typename Spec<T, S>::elem* row = spec + (c * nrow + g) * SX;
+                xa[m] = Spec<T, S>::get(row[k]);
+                xb[m] = Spec<T, S>::get(row[LX - k]);
             }
         }
 #pragma unroll
@@ -209,9 +212,9 @@ __global__ __launch_bounds__(NT) void k_xinv(const cx<T>* __restrict__ spec, int
             const int lr = e / LX, k = e - lr * LX;
             const C xk = xa[m];
             const C xc = cconj(xb[m]);
-            const C S = cadd(xk, xc);
+            const C sm = cadd(xk, xc);
             const C wd = cmulc(csub(xk, xc), wk[m]);
-            buf[lr * CS + k] = C{S.x - wd.y, S.y + wd.x};
+            buf[lr * CS + k] = C{sm.x - wd.y, sm.y + wd.x};
         }
         tw1.put(twl);
         __syncthreads();
@@ -226,7 +229,7 @@ __global__ __launch_bounds__(NT) void k_xinv(const cx<T>* __restrict__ spec, int
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const C v = buf[(3 * r + c) * CS + (LX > 0 ? (x >> 1) : 0)];
-            hd[c] = (x & 1) ? v.y : v.x;
+            hd[c] = ((x & 1) ? v.y : v.x) * hscale;
         }
         const long cell = g * nx + x;
         if constexpr (MODE == XINV_DEMAG) {
@@ -264,23 +267,25 @@ __global__ __launch_bounds__(NT) void k_xinv(const cx<T>* __restrict__ spec, int
 
 // ------------------------------------------------------------------------
 // strided column FFT: element (comp, outer, i, kx) at comp*cs + outer*os + i*is + kx
-template <typename T, int L, bool INV, int TK>
-__global__ __launch_bounds__(NT) void k_colfft(const cx<T>* __restrict__ src, long s_cs, long s_os, long s_is,
-                                               int n_in, cx<T>* __restrict__ dst, long d_cs, long d_os, long d_is,
-                                               int n_out, int Kx, const cx<T>* __restrict__ tw) {
+template <typename T, typename S, int L, bool INV, int TK>
+__global__ __launch_bounds__(NT) void k_colfft(const typename Spec<T, S>::elem* __restrict__ src, long s_cs,
+                                               long s_os, long s_is, int n_in,
+                                               typename Spec<T, S>::elem* __restrict__ dst, long d_cs, long d_os,
+                                               long d_is, int n_out, int Kx, const cx<T>* __restrict__ tw,
+                                               T scale) {
     using C = cx<T>;
     __shared__ C buf[L * TK];
     __shared__ C twl[L];
     const int kx0 = blockIdx.x * TK;
-    const cx<T>* sp = src + blockIdx.z * s_cs + blockIdx.y * s_os + kx0;
+    const auto* sp = src + blockIdx.z * s_cs + blockIdx.y * s_os + kx0;
     TwStage<T, L, NT> tws;
     tws.fetch(tw);
-    load_tile<T, L, TK, NT>(buf, sp, s_is, n_in, Kx - kx0);
+    load_tile_s<T, S, L, TK, NT>(buf, sp, s_is, n_in, Kx - kx0);
     tws.put(twl);
     __syncthreads();
     lds_fft<T, L, INV, Cols<TK, 1, TK, true>, NT>(buf, twl);
-    cx<T>* dp = dst + blockIdx.z * d_cs + blockIdx.y * d_os + kx0;
-    store_tile<T, L, TK, NT>(dp, d_is, buf, n_out, Kx - kx0);
+    auto* dp = dst + blockIdx.z * d_cs + blockIdx.y * d_os + kx0;
+    store_tile_s<T, S, L, TK, NT>(dp, d_is, buf, n_out, Kx - kx0, scale);
 }
 
 // ------------------------------------------------------------------------
@@ -290,19 +295,22 @@ __global__ __launch_bounds__(NT) void k_colfft(const cx<T>* __restrict__ src, lo
 // z inverse.  In place on rows z < nz of the [3][nz][nyrows][SX] buffer.
 // One workgroup takes the rows ky = q and ky = Py - q, which share the folded
 // kernel, so every folded value is read from memory once.
-template <typename T, int LZ, int TK>
-__global__ __launch_bounds__(NT) void k_zmul(cx<T>* __restrict__ buf, int SX, int Kx, int nz, int nyrows, int Py,
-                                             int Pz, const T* __restrict__ kfold, int Kyf, int Kzf,
-                                             const cx<T>* __restrict__ tw) {
+template <typename T, typename S, int LZ, int TK>
+__global__ __launch_bounds__(NT) void k_zmul(typename Spec<T, S>::elem* __restrict__ buf, int SX, int Kx, int nz,
+                                             int nyrows, int Py, int Pz, const T* __restrict__ kfold, int Kyf,
+                                             int Kzf, const cx<T>* __restrict__ tw, T kscale) {
     using C = cx<T>;
-    using P = typename Pack<T>::type;
-    constexpr int PN = Pack<T>::N;
+    using E = typename Spec<T, S>::elem;
+    constexpr int PN = pack_n<E, TK>();
+    using PU = PackU<E, PN>;
+    using RW = typename Raw<PN * (int)sizeof(E)>::type;
     constexpr int NC = 6 * TK;              // 2 rows x 3 components x TK columns
     constexpr int KZF = LZ / 2 + 1;         // folded kz extent (LZ = Pz)
     constexpr int PR = TK / PN, TOT = LZ * 6 * PR, PER = (TOT + NT - 1) / NT;
     constexpr int KTOT = KZF * TK * 6, KPER = (KTOT + NT - 1) / NT;
     static_assert(TK % PN == 0, "tile width");
     __shared__ C lb[LZ * NC];
+    (void)sizeof(PU);
     __shared__ T kl[KZF * 6 * TK];
     __shared__ C twl[LZ > 1 ? LZ : 1];
     const int kx0 = blockIdx.x * TK;
@@ -311,20 +319,20 @@ __global__ __launch_bounds__(NT) void k_zmul(cx<T>* __restrict__ buf, int SX, in
     const int ncol = Kx - kx0;
     const long cs = (long)nz * nyrows * SX, zs = (long)nyrows * SX;
     buf += (long)blockIdx.z * 3 * cs;  // sample
-    cx<T>* bp0 = buf + (long)q * SX + kx0;
-    cx<T>* bp1 = buf + (long)(Py - q) * SX + kx0;
+    E* bp0 = buf + (long)q * SX + kx0;
+    E* bp1 = buf + (long)(Py - q) * SX + kx0;
     TwStage<T, (LZ > 1 ? LZ : 1), NT> tws;
     if (LZ > 1) tws.fetch(tw);
     // staged loads: LDS row (z*2 + w)*3 + c holds component c of row z of ky row w
-    P r[PER];
+    PU r[PER];
 #pragma unroll
     for (int m = 0; m < PER; ++m) {
         const int e = threadIdx.x + m * NT;
         const int row = e / PR, j = e - row * PR;
         const int z = row / 6, wc = row - 6 * z, w = wc / 3, c = wc - 3 * w;
-        r[m] = Pack<T>::zero();
+        r[m].raw = {};
         if ((TOT % NT == 0 || e < TOT) && z < nz && w < nrow && j * PN < ncol)
-            r[m] = *(const P*)((w ? bp1 : bp0) + c * cs + z * zs + j * PN);
+            r[m].raw = *(const RW*)((w ? bp1 : bp0) + c * cs + z * zs + j * PN);
     }
     // folded kernel values of this column tile for kz <= Pz/2 (stored [kzf][comp][col])
     T kr[KPER];
@@ -334,12 +342,15 @@ __global__ __launch_bounds__(NT) void k_zmul(cx<T>* __restrict__ buf, int SX, in
         const int kzf = e / (6 * TK), rem = e - kzf * 6 * TK, comp = rem / TK, col = rem - comp * TK;
         kr[m] = T(0);
         if ((KTOT % NT == 0 || e < KTOT) && kzf < Kzf && col < ncol)
-            kr[m] = kfold[(((long)comp * Kzf + kzf) * Kyf + q) * SX + kx0 + col];
+            kr[m] = kscale * kfold[(((long)comp * Kzf + kzf) * Kyf + q) * SX + kx0 + col];
     }
 #pragma unroll
     for (int m = 0; m < PER; ++m) {
         const int e = threadIdx.x + m * NT;
-        if (TOT % NT == 0 || e < TOT) *(P*)(lb + e * PN) = r[m];
+        if (TOT % NT == 0 || e < TOT) {
+#pragma unroll
+            for (int qq = 0; qq < PN; ++qq) lb[e * PN + qq] = Spec<T, S>::get(r[m].e[qq]);
+        }
     }
 #pragma unroll
     for (int m = 0; m < KPER; ++m) {
@@ -369,7 +380,10 @@ __global__ __launch_bounds__(NT) void k_zmul(cx<T>* __restrict__ buf, int SX, in
 #pragma unroll
     for (int m = 0; m < PER; ++m) {
         const int e = threadIdx.x + m * NT;
-        if (TOT % NT == 0 || e < TOT) r[m] = *(const P*)(lb + e * PN);
+        if (TOT % NT == 0 || e < TOT) {
+#pragma unroll
+            for (int qq = 0; qq < PN; ++qq) r[m].e[qq] = Spec<T, S>::put(lb[e * PN + qq]);
+        }
     }
 #pragma unroll
     for (int m = 0; m < PER; ++m) {
@@ -377,7 +391,7 @@ __global__ __launch_bounds__(NT) void k_zmul(cx<T>* __restrict__ buf, int SX, in
         const int row = e / PR, j = e - row * PR;
         const int z = row / 6, wc = row - 6 * z, w = wc / 3, c = wc - 3 * w;
         if ((TOT % NT == 0 || e < TOT) && z < nz && w < nrow && j * PN < ncol)
-            *(P*)((w ? bp1 : bp0) + c * cs + z * zs + j * PN) = r[m];
+            *(RW*)((w ? bp1 : bp0) + c * cs + z * zs + j * PN) = r[m].raw;
     }
 }
 
@@ -593,21 +607,23 @@ __global__ __launch_bounds__(NT) void k_fold(const cx<double>* __restrict__ spec
 
 #define LLGX_POW2_CASES(M) M(2) M(4) M(8) M(16) M(32) M(64) M(128) M(256) M(512) M(1024) M(2048)
 
-template <typename T>
-hipError_t launch_xfwd(hipStream_t s, int LX, const Combo<T>& in, T* mk_out, int nin, long nrows, cx<T>* spec,
-                       int SX, const cx<T>* twL, const cx<T>* twP) {
-#define XF(L)                                                                                         \
-    case L: {                                                                                         \
-        constexpr int R = xfwd_rows<T>(L);                                                            \
-        k_xfwd<T, L, R><<<(unsigned)((nrows + R - 1) / R), NT, 0, s>>>(in, mk_out, nin, nrows, spec, SX, \
-                                                                       twL, twP);                     \
-        break;                                                                                        \
+template <typename T, typename S>
+hipError_t launch_xfwd(hipStream_t s, int LX, const Combo<T>& in, T* mk_out, int nin, long nrows, SpecPtr spec,
+                       int SX, const cx<T>* twL, const cx<T>* twP, T fscale) {
+    using E = typename Spec<T, S>::elem;
+    E* sp = (E*)spec;
+#define XF(L)                                                                                               \
+    case L: {                                                                                               \
+        constexpr int R = xfwd_rows<T>(L);                                                                  \
+        k_xfwd<T, S, L, R><<<(unsigned)((nrows + R - 1) / R), NT, 0, s>>>(in, mk_out, nin, nrows, sp, SX, twL, \
+                                                                          twP, fscale);                     \
+        break;                                                                                              \
     }
     switch (LX) {
         case 0: {
             constexpr int R = 256;
-            k_xfwd<T, 0, R><<<(unsigned)((nrows + R - 1) / R), NT, 0, s>>>(in, mk_out, nin, nrows, spec, SX, twL,
-                                                                           twP);
+            k_xfwd<T, S, 0, R><<<(unsigned)((nrows + R - 1) / R), NT, 0, s>>>(in, mk_out, nin, nrows, sp, SX, twL,
+                                                                              twP, fscale);
             break;
         }
         LLGX_POW2_CASES(XF)
@@ -618,25 +634,27 @@ hipError_t launch_xfwd(hipStream_t s, int LX, const Combo<T>& in, T* mk_out, int
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_xinv(hipStream_t s, int LX, int mode, const cx<T>* spec, int SX, const T* M, const Phys<T>& ph,
-                       const XinvOut& out, const cx<T>* twL, const cx<T>* twP) {
+template <typename T, typename S>
+hipError_t launch_xinv(hipStream_t s, int LX, int mode, SpecPtr spec, int SX, const T* M, const Phys<T>& ph,
+                       const XinvOut& out, const cx<T>* twL, const cx<T>* twP, T hscale) {
+    using E = typename Spec<T, S>::elem;
+    const E* sp = (const E*)spec;
     const long nrow = (long)ph.ny * ph.nz;
-#define XI_MODE(L, R)                                                                               \
-    {                                                                                               \
-        const dim3 nb((unsigned)((nrow + R - 1) / R), (unsigned)ph.nb, 1);                          \
-        if (mode == XINV_DEMAG)                                                                     \
-            k_xinv<T, L, R, XINV_DEMAG><<<nb, NT, 0, s>>>(spec, SX, M, ph, out, twL, twP);          \
-        else if (mode == XINV_HEFF)                                                                 \
-            k_xinv<T, L, R, XINV_HEFF><<<nb, NT, 0, s>>>(spec, SX, M, ph, out, twL, twP);           \
-        else                                                                                        \
-            k_xinv<T, L, R, XINV_RHS><<<nb, NT, 0, s>>>(spec, SX, M, ph, out, twL, twP);            \
+#define XI_MODE(L, R)                                                                                    \
+    {                                                                                                    \
+        const dim3 nb((unsigned)((nrow + R - 1) / R), (unsigned)ph.nb, 1);                               \
+        if (mode == XINV_DEMAG)                                                                          \
+            k_xinv<T, S, L, R, XINV_DEMAG><<<nb, NT, 0, s>>>(sp, SX, M, ph, out, twL, twP, hscale);      \
+        else if (mode == XINV_HEFF)                                                                      \
+            k_xinv<T, S, L, R, XINV_HEFF><<<nb, NT, 0, s>>>(sp, SX, M, ph, out, twL, twP, hscale);       \
+        else                                                                                             \
+            k_xinv<T, S, L, R, XINV_RHS><<<nb, NT, 0, s>>>(sp, SX, M, ph, out, twL, twP, hscale);        \
     }
-#define XI(L)                                   \
-    case L: {                                   \
-        constexpr int R = xinv_rows<T>(L);      \
-        XI_MODE(L, R)                           \
-        break;                                  \
+#define XI(L)                              \
+    case L: {                              \
+        constexpr int R = xinv_rows<T>(L); \
+        XI_MODE(L, R)                      \
+        break;                             \
     }
     switch (LX) {
         case 0: {
@@ -653,21 +671,24 @@ hipError_t launch_xinv(hipStream_t s, int LX, int mode, const cx<T>* spec, int S
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_colfft(hipStream_t s, int L, bool inv, const cx<T>* src, long s_cs, long s_os, long s_is, int n_in,
-                         cx<T>* dst, long d_cs, long d_os, long d_is, int n_out, int Kx, int nouter, int ncomp,
-                         const cx<T>* tw) {
-#define CF(LL)                                                                                              \
-    case LL: {                                                                                              \
-        constexpr int TK = col_tile<T>(LL);                                                                 \
-        dim3 g((unsigned)((Kx + TK - 1) / TK), (unsigned)nouter, (unsigned)ncomp);                          \
-        if (inv)                                                                                            \
-            k_colfft<T, LL, true, TK><<<g, NT, 0, s>>>(src, s_cs, s_os, s_is, n_in, dst, d_cs, d_os, d_is,  \
-                                                       n_out, Kx, tw);                                      \
-        else                                                                                                \
-            k_colfft<T, LL, false, TK><<<g, NT, 0, s>>>(src, s_cs, s_os, s_is, n_in, dst, d_cs, d_os, d_is, \
-                                                        n_out, Kx, tw);                                     \
-        break;                                                                                              \
+template <typename T, typename S>
+hipError_t launch_colfft(hipStream_t s, int L, bool inv, SpecPtr src, long s_cs, long s_os, long s_is, int n_in,
+                         SpecPtr dst, long d_cs, long d_os, long d_is, int n_out, int Kx, int nouter, int ncomp,
+                         const cx<T>* tw, T scale) {
+    using E = typename Spec<T, S>::elem;
+    const E* sp = (const E*)src;
+    E* dp = (E*)dst;
+#define CF(LL)                                                                                                   \
+    case LL: {                                                                                                   \
+        constexpr int TK = col_tile<T>(LL);                                                                      \
+        dim3 g((unsigned)((Kx + TK - 1) / TK), (unsigned)nouter, (unsigned)ncomp);                               \
+        if (inv)                                                                                                 \
+            k_colfft<T, S, LL, true, TK><<<g, NT, 0, s>>>(sp, s_cs, s_os, s_is, n_in, dp, d_cs, d_os, d_is, n_out, \
+                                                          Kx, tw, scale);                                        \
+        else                                                                                                     \
+            k_colfft<T, S, LL, false, TK><<<g, NT, 0, s>>>(sp, s_cs, s_os, s_is, n_in, dp, d_cs, d_os, d_is,     \
+                                                           n_out, Kx, tw, scale);                                \
+        break;                                                                                                   \
     }
     switch (L) {
         LLGX_POW2_CASES(CF)
@@ -678,21 +699,23 @@ hipError_t launch_colfft(hipStream_t s, int L, bool inv, const cx<T>* src, long 
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_zmul(hipStream_t s, int LZ, cx<T>* buf, int SX, int Kx, int nz, int nyrows, int Py, int Pz,
-                       const T* kfold, int Kyf, int Kzf, const cx<T>* tw, int nb) {
-#define ZM(LL)                                                                                             \
-    case LL: {                                                                                             \
-        constexpr int TK = zmul_tile<T>(LL);                                                               \
-        dim3 g((unsigned)((Kx + TK - 1) / TK), (unsigned)(Py / 2 + 1), (unsigned)nb);                      \
-        k_zmul<T, LL, TK><<<g, NT, 0, s>>>(buf, SX, Kx, nz, nyrows, Py, Pz, kfold, Kyf, Kzf, tw);           \
-        break;                                                                                             \
+template <typename T, typename S>
+hipError_t launch_zmul(hipStream_t s, int LZ, SpecPtr buf, int SX, int Kx, int nz, int nyrows, int Py, int Pz,
+                       const T* kfold, int Kyf, int Kzf, const cx<T>* tw, int nb, T kscale) {
+    using E = typename Spec<T, S>::elem;
+    E* bp = (E*)buf;
+#define ZM(LL)                                                                                                 \
+    case LL: {                                                                                                 \
+        constexpr int TK = zmul_tile<T>(LL);                                                                   \
+        dim3 g((unsigned)((Kx + TK - 1) / TK), (unsigned)(Py / 2 + 1), (unsigned)nb);                          \
+        k_zmul<T, S, LL, TK><<<g, NT, 0, s>>>(bp, SX, Kx, nz, nyrows, Py, Pz, kfold, Kyf, Kzf, tw, kscale);     \
+        break;                                                                                                 \
     }
     switch (LZ) {
         case 1: {
             constexpr int TK = 32;
             dim3 g((unsigned)((Kx + TK - 1) / TK), (unsigned)(Py / 2 + 1), (unsigned)nb);
-            k_zmul<T, 1, TK><<<g, NT, 0, s>>>(buf, SX, Kx, nz, nyrows, Py, Pz, kfold, Kyf, Kzf, tw);
+            k_zmul<T, S, 1, TK><<<g, NT, 0, s>>>(bp, SX, Kx, nz, nyrows, Py, Pz, kfold, Kyf, Kzf, tw, kscale);
             break;
         }
         ZM(2) ZM(4) ZM(8) ZM(16) ZM(32) ZM(64) ZM(128) ZM(256) ZM(512) ZM(1024)
@@ -725,19 +748,23 @@ hipError_t launch_fold(hipStream_t s, const cx<double>* spec, int SX, int Kx, in
     return hipGetLastError();
 }
 
-#define INST(T)                                                                                                    \
-    template hipError_t launch_xfwd<T>(hipStream_t, int, const Combo<T>&, T*, int, long, cx<T>*, int,             \
-                                       const cx<T>*, const cx<T>*);                                               \
-    template hipError_t launch_xinv<T>(hipStream_t, int, int, const cx<T>*, int, const T*, const Phys<T>&,        \
-                                       const XinvOut&, const cx<T>*, const cx<T>*);                               \
-    template hipError_t launch_colfft<T>(hipStream_t, int, bool, const cx<T>*, long, long, long, int, cx<T>*, long, \
-                                         long, long, int, int, int, int, const cx<T>*);                           \
-    template hipError_t launch_zmul<T>(hipStream_t, int, cx<T>*, int, int, int, int, int, int, const T*, int, int, \
-                                       const cx<T>*, int);                                                        \
-    template hipError_t launch_fold<T>(hipStream_t, const cx<double>*, int, int, int, int, int, int, double, int, \
-                                       T*, double*, int);
-INST(float)
-INST(double)
-#undef INST
+#define INST_TS(T, S)                                                                                         \
+    template hipError_t launch_xfwd<T, S>(hipStream_t, int, const Combo<T>&, T*, int, long, SpecPtr, int,          \
+                                          const cx<T>*, const cx<T>*, T);                                         \
+    template hipError_t launch_xinv<T, S>(hipStream_t, int, int, SpecPtr, int, const T*, const Phys<T>&,           \
+                                          const XinvOut&, const cx<T>*, const cx<T>*, T);                         \
+    template hipError_t launch_colfft<T, S>(hipStream_t, int, bool, SpecPtr, long, long, long, int, SpecPtr, long, \
+                                            long, long, int, int, int, int, const cx<T>*, T);                     \
+    template hipError_t launch_zmul<T, S>(hipStream_t, int, SpecPtr, int, int, int, int, int, int, const T*, int,  \
+                                          int, const cx<T>*, int, T);
+INST_TS(float, float)
+INST_TS(float, _Float16)
+INST_TS(float, __bf16)
+INST_TS(double, double)
+#undef INST_TS
+template hipError_t launch_fold<float>(hipStream_t, const cx<double>*, int, int, int, int, int, int, double, int,
+                                       float*, double*, int);
+template hipError_t launch_fold<double>(hipStream_t, const cx<double>*, int, int, int, int, int, int, double, int,
+                                        double*, double*, int);
 
 }  // namespace llgx

@@ -80,20 +80,25 @@ struct XinvOut {
     void* g;     // stored field G = H_d + N00 M of Eq. (6) (optional)
 };
 
-// Host-side launchers (demag.hip).  All lengths are powers of two.
-template <typename T>
-hipError_t launch_xfwd(hipStream_t s, int LX, const Combo<T>& in, T* mk_out, int nin, long nrows,
-                       cx<T>* spec, int SX, const cx<T>* twL, const cx<T>* twP);
-template <typename T>
-hipError_t launch_xinv(hipStream_t s, int LX, int mode, const cx<T>* spec, int SX, const T* M,
-                       const Phys<T>& ph, const XinvOut& out, const cx<T>* twL, const cx<T>* twP);
-template <typename T>
-hipError_t launch_colfft(hipStream_t s, int L, bool inv, const cx<T>* src, long s_cs, long s_os, long s_is,
-                         int n_in, cx<T>* dst, long d_cs, long d_os, long d_is, int n_out, int Kx,
-                         int nouter, int ncomp, const cx<T>* tw);
-template <typename T>
-hipError_t launch_zmul(hipStream_t s, int LZ, cx<T>* buf, int SX, int Kx, int nz, int nyrows, int Py, int Pz,
-                       const T* kfold, int Kyf, int Kzf, const cx<T>* tw, int nb);
+// Host-side launchers (demag.hip).  All lengths are powers of two.  Spectra
+// are passed untyped (SpecPtr) and stored as S: the working precision T, or
+// _Float16 / __bf16 pairs for T = float.  fscale, scale, kscale and hscale
+// multiply the x-pass input, the y-pass output, the k-space kernel and the
+// final field (all 1 for storage in the working precision).
+using SpecPtr = void*;
+template <typename T, typename S>
+hipError_t launch_xfwd(hipStream_t s, int LX, const Combo<T>& in, T* mk_out, int nin, long nrows, SpecPtr spec,
+                       int SX, const cx<T>* twL, const cx<T>* twP, T fscale);
+template <typename T, typename S>
+hipError_t launch_xinv(hipStream_t s, int LX, int mode, SpecPtr spec, int SX, const T* M, const Phys<T>& ph,
+                       const XinvOut& out, const cx<T>* twL, const cx<T>* twP, T hscale);
+template <typename T, typename S>
+hipError_t launch_colfft(hipStream_t s, int L, bool inv, SpecPtr src, long s_cs, long s_os, long s_is, int n_in,
+                         SpecPtr dst, long d_cs, long d_os, long d_is, int n_out, int Kx, int nouter, int ncomp,
+                         const cx<T>* tw, T scale);
+template <typename T, typename S>
+hipError_t launch_zmul(hipStream_t s, int LZ, SpecPtr buf, int SX, int Kx, int nz, int nyrows, int Py, int Pz,
+                       const T* kfold, int Kyf, int Kzf, const cx<T>* tw, int nb, T kscale);
 hipError_t launch_newell_octant(hipStream_t s, int nx, int ny, int nz, double dx, double dy, double dz,
                                 double* octant);
 hipError_t launch_scatter_tensor(hipStream_t s, const double* octant, int comp, int nx, int ny, int nz,

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -218,47 +219,66 @@ static Phys<T> phys(const Ctx* c) {
 
 // ---------------------------------------------------------------------------
 // one exact evaluation of Eq. (2) on the stage input `in` (Eq. (4)), ending
-// in the inverse x pass selected by `mode`
-template <typename T>
-static llgx_status eval_exact(Ctx* c, const Combo<T>& in, T* mk_out, int mode, const T* Mrhs, const XinvOut& out) {
+// in the inverse x pass selected by `mode`.  Spectra stored as S; with 16-bit
+// storage the transforms are scaled so that every stored spectrum is O(1):
+// the x pass takes M/(Ms Px), the y pass stores 1/Py of its output, the
+// kernel product carries Px Py (so it applies -N^/Pz), and the field is
+// multiplied by Ms when it is formed.  With S = T every scale is 1.
+template <typename T, typename S>
+static llgx_status eval_exact_s(Ctx* c, const Combo<T>& in, T* mk_out, int mode, const T* Mrhs, const XinvOut& out) {
     hipStream_t s = c->stream;
-    cx<T>* A = (cx<T>*)c->specA;
+    void* A = c->specA;
     const cx<T>* twL = table<T>(c, c->LX, false);
     const cx<T>* twP = table<T>(c, c->Px, false);
+    const bool native = std::is_same<T, S>::value;
+    const T fscale = native ? T(1) : (T)(1.0 / (c->p.Ms * c->Px));
+    const T yscale = native ? T(1) : (T)(1.0 / c->Py);
+    const T kscale = native ? T(1) : (T)((double)c->Px * c->Py);
+    const T hscale = native ? T(1) : (T)c->p.Ms;
     {
         PROF(LLGX_K_XFWD);
-        HIPCHK(c, launch_xfwd<T>(s, c->LX, in, mk_out, c->nx, 3L * c->ny * c->nz * c->nb, A, c->SX, twL, twP));
+        HIPCHK(c, (launch_xfwd<T, S>(s, c->LX, in, mk_out, c->nx, 3L * c->ny * c->nz * c->nb, A, c->SX, twL, twP,
+                                     fscale)));
     }
-    cx<T>* work = A;
+    void* work = A;
     int nyrows = c->ny;
     if (c->Py > 1) {
-        cx<T>* B = (cx<T>*)c->specB;
+        void* B = c->specB;
         const long sa = (long)c->nz * c->ny * c->SX, sb = (long)c->nz * c->Py * c->SX;
         PROF(LLGX_K_YFWD);
-        HIPCHK(c, launch_colfft<T>(s, c->Py, false, A, sa, (long)c->ny * c->SX, c->SX, c->ny, B, sb,
-                                   (long)c->Py * c->SX, c->SX, c->Py, c->Kx, c->nz, 3 * c->nb,
-                                   table<T>(c, c->Py, false)));
+        HIPCHK(c, (launch_colfft<T, S>(s, c->Py, false, A, sa, (long)c->ny * c->SX, c->SX, c->ny, B, sb,
+                                       (long)c->Py * c->SX, c->SX, c->Py, c->Kx, c->nz, 3 * c->nb,
+                                       table<T>(c, c->Py, false), yscale)));
         work = B;
         nyrows = c->Py;
     }
     {
         PROF(LLGX_K_ZMUL);
-        HIPCHK(c, launch_zmul<T>(s, c->Pz, work, c->SX, c->Kx, c->nz, nyrows, c->Py, c->Pz, (const T*)c->kfold,
-                                 c->Kyf, c->Kzf, table<T>(c, c->Pz, false), c->nb));
+        HIPCHK(c, (launch_zmul<T, S>(s, c->Pz, work, c->SX, c->Kx, c->nz, nyrows, c->Py, c->Pz, (const T*)c->kfold,
+                                     c->Kyf, c->Kzf, table<T>(c, c->Pz, false), c->nb, kscale)));
     }
     if (c->Py > 1) {
-        cx<T>* B = (cx<T>*)c->specB;
+        void* B = c->specB;
         const long sa = (long)c->nz * c->ny * c->SX, sb = (long)c->nz * c->Py * c->SX;
         PROF(LLGX_K_YINV);
-        HIPCHK(c, launch_colfft<T>(s, c->Py, true, B, sb, (long)c->Py * c->SX, c->SX, c->Py, A, sa,
-                                   (long)c->ny * c->SX, c->SX, c->ny, c->Kx, c->nz, 3 * c->nb,
-                                   table<T>(c, c->Py, false)));
+        HIPCHK(c, (launch_colfft<T, S>(s, c->Py, true, B, sb, (long)c->Py * c->SX, c->SX, c->Py, A, sa,
+                                       (long)c->ny * c->SX, c->SX, c->ny, c->Kx, c->nz, 3 * c->nb,
+                                       table<T>(c, c->Py, false), T(1))));
     }
     {
         PROF(LLGX_K_XINV);
-        HIPCHK(c, launch_xinv<T>(s, c->LX, mode, A, c->SX, Mrhs, phys<T>(c), out, twL, twP));
+        HIPCHK(c, (launch_xinv<T, S>(s, c->LX, mode, A, c->SX, Mrhs, phys<T>(c), out, twL, twP, hscale)));
     }
     return LLGX_OK;
+}
+
+template <typename T>
+static llgx_status eval_exact(Ctx* c, const Combo<T>& in, T* mk_out, int mode, const T* Mrhs, const XinvOut& out) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (c->spectral == LLGX_SPEC_BF16) return eval_exact_s<float, __bf16>(c, in, mk_out, mode, Mrhs, out);
+        if (c->spectral == LLGX_SPEC_F16) return eval_exact_s<float, _Float16>(c, in, mk_out, mode, Mrhs, out);
+    }
+    return eval_exact_s<T, T>(c, in, mk_out, mode, Mrhs, out);
 }
 
 template <typename T>
@@ -319,15 +339,17 @@ static llgx_status kernel_from_octant_or_real(Ctx* c, const std::vector<double>*
                                             (double*)real));
         }
         cx<double>* sp = (cx<double>*)spec;
-        HIPCHK(c, launch_xfwd<double>(s, c->LX, plain<double>(real), nullptr, c->Px, (long)c->Pz * c->Py, sp, c->SX,
-                                      table<double>(c, c->LX, true), table<double>(c, c->Px, true)));
+        HIPCHK(c, (launch_xfwd<double, double>(s, c->LX, plain<double>(real), nullptr, c->Px, (long)c->Pz * c->Py, sp,
+                                               c->SX, table<double>(c, c->LX, true), table<double>(c, c->Px, true),
+                                               1.0)));
         if (c->Py > 1)
-            HIPCHK(c, launch_colfft<double>(s, c->Py, false, sp, 0, (long)c->Py * c->SX, c->SX, c->Py, sp, 0,
-                                            (long)c->Py * c->SX, c->SX, c->Py, c->Kx, c->Pz, 1,
-                                            table<double>(c, c->Py, true)));
+            HIPCHK(c, (launch_colfft<double, double>(s, c->Py, false, sp, 0, (long)c->Py * c->SX, c->SX, c->Py, sp, 0,
+                                                     (long)c->Py * c->SX, c->SX, c->Py, c->Kx, c->Pz, 1,
+                                                     table<double>(c, c->Py, true), 1.0)));
         if (c->Pz > 1)
-            HIPCHK(c, launch_colfft<double>(s, c->Pz, false, sp, 0, c->SX, (long)c->Py * c->SX, c->Pz, sp, 0, c->SX,
-                                            (long)c->Py * c->SX, c->Pz, c->Kx, c->Py, 1, table<double>(c, c->Pz, true)));
+            HIPCHK(c, (launch_colfft<double, double>(s, c->Pz, false, sp, 0, c->SX, (long)c->Py * c->SX, c->Pz, sp, 0,
+                                                     c->SX, (long)c->Py * c->SX, c->Pz, c->Kx, c->Py, 1,
+                                                     table<double>(c, c->Pz, true), 1.0)));
         HIPCHK(c, launch_fold<T>(s, sp, c->SX, c->Kx, c->Py, c->Pz, c->Kyf, c->Kzf, scale, comp, (T*)c->kfold,
                                  c->parts, c->nparts));
     }
@@ -815,9 +837,13 @@ static llgx_status create_ctx(const llgx_problem* p, int nb, const double* ha_li
         err = "precision must be LLGX_F32 or LLGX_F64";
         return LLGX_E_ARG;
     }
-    if (spectral != LLGX_SPEC_NATIVE) {
-        err = "16-bit spectral storage is not available in this build";
-        return LLGX_E_UNSUPPORTED;
+    if (spectral != LLGX_SPEC_NATIVE && spectral != LLGX_SPEC_BF16 && spectral != LLGX_SPEC_F16) {
+        err = "spectral must be LLGX_SPEC_NATIVE, LLGX_SPEC_BF16 or LLGX_SPEC_F16";
+        return LLGX_E_ARG;
+    }
+    if (spectral != LLGX_SPEC_NATIVE && precision != LLGX_F32) {
+        err = "16-bit spectral storage requires LLGX_F32";
+        return LLGX_E_ARG;
     }
     Ctx* c = new Ctx();
     c->p = *p;
@@ -843,7 +869,7 @@ static llgx_status create_ctx(const llgx_problem* p, int nb, const double* ha_li
     c->SX = (c->Kx + 15) / 16 * 16;
     c->Kyf = c->Py > 1 ? c->Py / 2 + 1 : 1;
     c->Kzf = c->Pz > 1 ? c->Pz / 2 + 1 : 1;
-    const size_t cbytes = 2 * c->tsz;
+    const size_t cbytes = spectral == LLGX_SPEC_NATIVE ? 2 * c->tsz : 4;  // bytes per stored complex value
     const size_t vbytes = 3 * (size_t)c->ncell * nb * c->tsz;
     llgx_status st = LLGX_OK;
     auto A = [&](void** ptr, size_t bytes) {
