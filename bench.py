@@ -313,6 +313,55 @@ def main():
             extras["batch64_cells"] = inf["cells"]
             bt.close()
 
+    if not args.no_extras:
+        # ---- large film 512x512x64 (2 nm): spectral storage FP32 / BF16 / FP16 vs FP64 ----
+        log("large film 512x512x64 ...")
+        big = workloads.FILM_512x512x64
+        Mb = workloads.random_m(big["n"], big["Ms"], workloads.FILM_512x512x64_SEED)
+        ref = llgx.Sim(big, "f64", stream=stream)
+        ref.precompute_demag()
+        with torch.cuda.stream(stream):
+            Mb64 = torch.as_tensor(Mb, dtype=torch.float64, device=dev)
+            Href = ref.demag(Mb64)
+            torch.cuda.synchronize()
+            R = 10
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(R):
+                ref.demag(Mb64)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            extras["film512_f64_exact_evals_per_s"] = R / (e0.elapsed_time(e1) * 1e-3)
+        ref.close()
+        del Mb64
+        for tag, spec in (("f32", llgx.SPEC_NATIVE), ("bf16", llgx.SPEC_BF16), ("f16", llgx.SPEC_F16)):
+            sb = llgx.Sim(big, "f32", spectral=spec, stream=stream)
+            sb.precompute_demag()
+            with torch.cuda.stream(stream):
+                Mb32 = torch.as_tensor(Mb, dtype=torch.float32, device=dev)
+                H = sb.demag(Mb32)
+                torch.cuda.synchronize()
+                extras[f"film512_{tag}_field_err_over_Ms"] = float((H.double() - Href).abs().max().item() / big["Ms"])
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(R):
+                    sb.demag(Mb32)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                extras[f"film512_{tag}_exact_evals_per_s"] = R / (e0.elapsed_time(e1) * 1e-3)
+                sb.set_m(Mb32)
+            stb = llgx.make_stepper("RKDP54", extrap=4, h=2e-14)
+            sb.run_fixed(stb, 5, use_graph=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sb.run_fixed(stb, 10, use_graph=True)
+            torch.cuda.synchronize()
+            extras[f"film512_{tag}_rkdp54_p4_ms_per_step"] = 1e3 * (time.perf_counter() - t0) / 10
+            sb.close()
+            del Mb32, H
+        del Href
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
