@@ -29,10 +29,23 @@ sys.path.insert(0, ROOT)
 METRIC = "demag-field evals/s & simulated ns/h at 256x256x16, FP32 vs FP64, err<=1e-5"
 HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SOURCES = {
-    "xfwd": "demag.hip", "yfwd": "demag.hip", "zmul": "demag.hip", "yinv": "demag.hip", "xinv": "demag.hip",
-    "combine": "llg.hip", "extrap": "llg.hip", "final": "llg.hip", "epoly": "llg.hip",
-}
+# kernels of the FP32 step, by demangled-name pattern (rocprofv3 names)
+KIND_PATTERNS = (
+    ("xfwd", r"k_xfwd<float, float,"),
+    ("yfwd", r"k_colfft<float, float, \d+, false,"),
+    ("yinv", r"k_colfft<float, float, \d+, true,"),
+    ("zmul", r"k_zmul(_reg)?<float, float,"),
+    ("xinv", r"k_xinv<float, float,"),
+    ("combine", r"k_combine<float,"),
+    ("extrap", r"k_stage<float,"),
+    ("final", r"k_stage_final<float,"),
+    ("epoly", r"k_epoly<float,"),
+)
+# counter calibration: torch.neg over CALIB_BYTES of float32 reads and writes
+# exactly that many bytes
+CALIB_PATTERN = r"neg_kernel"
+CALIB_BYTES = 256 << 20
+STATS_MD = os.path.join(ROOT, "profiles", "rk4_p4_f32_256x256x16_kernel_stats.md")
 
 
 def log(msg):
@@ -71,9 +84,17 @@ def kernel_bytes(n, tsz, p, nnz_comb=1, nnz_final=4):
     }
 
 
-def source_hash(fname):
-    with open(os.path.join(ROOT, "paper_2107_06729_amd", "csrc", fname), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def source_hash():
+    """Hash of every kernel source and header (a change anywhere voids the
+    stored counter figures)."""
+    d = os.path.join(ROOT, "paper_2107_06729_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel):
@@ -84,9 +105,73 @@ def measured_traffic(kernel):
     except (OSError, ValueError):
         return None
     e = d.get("kernels", {}).get(kernel)
-    if not e or e.get("source_sha256_16") != source_hash(KERNEL_SOURCES[kernel]):
+    if not e or d.get("source_sha256_16") != source_hash():
         return None
     return e.get("bytes_per_launch")
+
+
+def _kind_of(name):
+    import re
+    for kind, pat in KIND_PATTERNS:
+        if re.search(pat, name):
+            return kind
+    return None
+
+
+def summarize(stats_dir, fetch_dir, write_dir, cmd_stats, cmd_fetch, cmd_write):
+    """Turn rocprofv3 output of this script into the committed summaries: the
+    kernel-time table (markdown) and the HBM traffic per launch of each step
+    kernel (JSON), FETCH_SIZE / WRITE_SIZE scaled by what the same counters
+    read for torch.neg over CALIB_BYTES."""
+    import csv
+    import re
+    rows = list(csv.DictReader(open(os.path.join(stats_dir, "run_kernel_stats.csv"))))
+
+    def short(n):
+        return re.sub(r"\(.*", "", n).replace("void ", "").replace("llgx::", "")
+
+    out = ["# rocprofv3 kernel statistics: RK4 + 4th-order extrapolation, FP32, 256x256x16 slab", "",
+           "Command (repo root on the GPU box):", "", "```", cmd_stats, "```", "",
+           "| kernel | step kind | calls | avg us | min us | max us | share % |",
+           "|---|---|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        out.append(f"| `{short(r['Name'])[:90]}` | {_kind_of(r['Name']) or ''} | {r['Calls']} | "
+                   f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                   f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    with open(STATS_MD, "w") as f:
+        f.write("\n".join(out) + "\n")
+
+    def counter(dirname, cname):
+        per = {}
+        for r in csv.DictReader(open(os.path.join(dirname, "run_counter_collection.csv"))):
+            if r["Counter_Name"] != cname:
+                continue
+            per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return per
+
+    fetch, write = counter(fetch_dir, "FETCH_SIZE"), counter(write_dir, "WRITE_SIZE")
+
+    def calib(per):
+        v = [x for n, xs in per.items() if re.search(CALIB_PATTERN, n) for x in xs]
+        return (CALIB_BYTES / 1024) / (sum(v) / len(v)) if v else None
+
+    fcal, wcal = calib(fetch), calib(write)
+    kernels = {}
+    for name in fetch:
+        kind = _kind_of(name)
+        if kind is None or name not in write:
+            continue
+        fk = sum(fetch[name]) / len(fetch[name])
+        wk = sum(write[name]) / len(write[name])
+        kernels[kind] = {"name": short(name), "dispatches": len(fetch[name]), "fetch_kib": fk, "write_kib": wk,
+                         "bytes_per_launch": 1024 * (fk * fcal + wk * wcal) if fcal and wcal else None}
+    traffic = {"source_sha256_16": source_hash(), "calibration": {
+        "kernel": "torch.neg of a float32 tensor", "bytes_each_way": CALIB_BYTES,
+        "fetch_factor": fcal, "write_factor": wcal},
+        "commands": {"fetch": cmd_fetch, "write": cmd_write}, "kernels": kernels}
+    with open(PROFILE_TRAFFIC, "w") as f:
+        json.dump(traffic, f, indent=1)
+    print(json.dumps(traffic, indent=1))
 
 
 def timed_steps(sim, stepper, k, torch, stream):
@@ -97,7 +182,7 @@ def timed_steps(sim, stepper, k, torch, stream):
     return time.perf_counter() - t0
 
 
-def cpu_baseline(prob, M0, h, p, steps=2):
+def cpu_baseline(prob, M0, h, p, steps=16):
     """The oracle as it stands (oracle.integrate.Integrator, single-threaded
     NumPy/SciPy), steady-state RK4 + p-order extrapolation steps on the same
     mesh.  The tensor is the oracle's own; the p history entries are zero
@@ -124,7 +209,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--summarize", nargs=6, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR", "CMD_STATS",
+                                                     "CMD_FETCH", "CMD_WRITE"),
+                    help="write the profiles/ summaries from rocprofv3 output of this script (no GPU)")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(*args.summarize)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: this build runs the hot path on a single MI355X "
@@ -211,6 +302,9 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         rec["copy_256MiB_gbs"] = 10 * 2 * csrc.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        for _ in range(3):
+            torch.neg(csrc, out=cdst)  # counter calibration (CALIB_BYTES each way)
+        torch.cuda.synchronize()
         del csrc, cdst
 
     extras = {}

@@ -191,6 +191,25 @@ llgx_status llgx_run(llgx_handle h, const llgx_stepper* s, double t_end, double 
 llgx_status llgx_profile(llgx_handle h, int32_t enable);
 llgx_status llgx_profile_read(llgx_handle h, double ms[LLGX_K_COUNT], int64_t launches[LLGX_K_COUNT]);
 
+/* ---- Checkpoint / resume ------------------------------------------------
+ * The whole stepping state of a handle -- t, the controller's next h, M, the
+ * Eq. (6) history (the stage-1 fields of the previous accepted iterations and
+ * their start times), the FSAL stage field when valid, the method and order
+ * the history belongs to, and the counters -- as one host byte image, so a
+ * run resumed from it continues exactly as the uninterrupted run (no new
+ * priming iterations, Sec. III).  The image holds arrays in the handle's
+ * working precision and fits only a handle of the same mesh, sample count
+ * and precision; the problem's material parameters are not part of it.
+ *
+ * llgx_save_state: with host_buf NULL, *used receives the size needed and
+ * nothing is copied; otherwise cap must be at least that size (LLGX_E_ARG if
+ * not).  Synchronises the handle's stream.  LLGX_E_STATE before llgx_set_m.
+ * llgx_load_state: len must equal the image size; a foreign, corrupt or
+ * mismatched image gives LLGX_E_ARG and leaves the handle unchanged.
+ * Synchronises.  The caller owns host_buf in both calls. */
+llgx_status llgx_save_state(llgx_handle h, void* host_buf, size_t cap, size_t* used);
+llgx_status llgx_load_state(llgx_handle h, const void* host_buf, size_t len);
+
 /* ---- Batches of independent samples -------------------------------------
  * n samples of possibly different meshes and applied fields (parameter and
  * field sweeps) stepped together.  Samples whose problems are equal except

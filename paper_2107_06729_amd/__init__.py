@@ -80,6 +80,8 @@ _sig = {
     "llgx_get_time": (_S, [_H, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "llgx_set_time": (_S, [_H, ctypes.c_double]),
     "llgx_counters": (_S, [_H, ctypes.POINTER(ctypes.c_int64)]),
+    "llgx_save_state": (_S, [_H, _P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+    "llgx_load_state": (_S, [_H, _P, ctypes.c_size_t]),
     "llgx_batch_create": (_S, [ctypes.c_int32, ctypes.POINTER(Problem), ctypes.c_int32, _P, ctypes.POINTER(_H)]),
     "llgx_batch_destroy": (None, [_H]),
     "llgx_batch_last_error": (ctypes.c_char_p, [_H]),
@@ -290,6 +292,20 @@ class Sim:
         out = (ctypes.c_int64 * 5)()
         _check(_lib.llgx_counters(self._h, out), self._h)
         return dict(zip(("exact", "extrap", "accepted", "rejected", "forced"), list(out)))
+
+    def save_state(self):
+        """Checkpoint of the stepping state as bytes (llgx_save_state)."""
+        need = ctypes.c_size_t()
+        _check(_lib.llgx_save_state(self._h, None, 0, ctypes.byref(need)), self._h)
+        buf = ctypes.create_string_buffer(need.value)
+        _check(_lib.llgx_save_state(self._h, buf, need.value, ctypes.byref(need)), self._h)
+        return buf.raw[:need.value]
+
+    def load_state(self, blob):
+        """Resume from bytes written by save_state (llgx_load_state)."""
+        blob = bytes(blob)
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(_lib.llgx_load_state(self._h, buf, len(blob)), self._h)
 
 
 def _bcheck(code, handle):

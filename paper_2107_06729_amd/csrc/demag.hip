@@ -18,6 +18,7 @@
 
 #include "kernels.hpp"
 #include "physics.hpp"
+#include "fft_reg.hpp"
 #include "spec_store.hpp"
 #include "tile_io.hpp"
 
@@ -396,6 +397,71 @@ __global__ __launch_bounds__(NT) void k_zmul(typename Spec<T, S>::elem* __restri
 }
 
 // ------------------------------------------------------------------------
+// Same pass for short z pencils (LZ <= 32 in FP32), one pencil triple per
+// thread in registers: thread (q, w, kx), kx fastest, owns the x, y and z
+// components of pencil (ky = q or Py - q, kx).  Forward DIF with the zero
+// upper half pruned leaves the spectrum in bit-reversed kz order; the kernel
+// product is applied there (each folded kz value loaded once for kz and
+// Pz - kz); the inverse DIT returns natural order and forms only z < Pz/2.
+template <typename T, typename S, int LZ>
+__global__ __launch_bounds__(NT) void k_zmul_reg(typename Spec<T, S>::elem* __restrict__ buf, int SX, int Kx, int nz,
+                                                 int nyrows, int Py, const T* __restrict__ kfold, int Kyf, int Kzf,
+                                                 T kscale) {
+    using C = cx<T>;
+    using E = typename Spec<T, S>::elem;
+    const long gid = (long)blockIdx.x * NT + threadIdx.x;
+    const long total = (long)(Py / 2 + 1) * 2 * Kx;
+    if (gid >= total) return;
+    const int kx = (int)(gid % Kx);
+    const long rest = gid / Kx;
+    const int w = (int)(rest & 1), q = (int)(rest >> 1);
+    if (w == 1 && (q == 0 || 2 * q == Py)) return;  // rows paired with themselves
+    const int ky = w ? Py - q : q;
+    const long cs = (long)nz * nyrows * SX, zs = (long)nyrows * SX;
+    E* p = buf + (long)blockIdx.y * 3 * cs + (long)ky * SX + kx;
+    C v[3][LZ];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int z = 0; z < LZ; ++z) {
+            v[c][z] = C{T(0), T(0)};
+            if (z < LZ / 2 && z < nz) v[c][z] = Spec<T, S>::get(p[c * cs + z * zs]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fft_dif<T, LZ, false, true>(v[c]);
+    const T sy = w ? T(-1) : T(1);
+    const long kcs = (long)Kzf * Kyf * SX, kzs = (long)Kyf * SX;
+    const T* kp = kfold + (long)q * SX + kx;
+#pragma unroll
+    for (int kzf = 0; kzf <= LZ / 2; ++kzf) {
+        const T* kk = kp + kzf * kzs;
+        const T nxx = kscale * kk[0], nyy = kscale * kk[kcs], nzz = kscale * kk[2 * kcs];
+        const T nxy0 = kscale * sy * kk[3 * kcs], nxz0 = kscale * kk[4 * kcs], nyz0 = kscale * sy * kk[5 * kcs];
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            if (side == 1 && (kzf == 0 || kzf == LZ / 2)) continue;
+            const int kz = side ? LZ - kzf : kzf;
+            const int i = bitrev(kz, LZ);
+            const T sz = side ? T(-1) : T(1);
+            const T nxy = nxy0, nxz = sz * nxz0, nyz = sz * nyz0;
+            const C mx = v[0][i], my = v[1][i], mz = v[2][i];
+            v[0][i] = C{nxx * mx.x + nxy * my.x + nxz * mz.x, nxx * mx.y + nxy * my.y + nxz * mz.y};
+            v[1][i] = C{nxy * mx.x + nyy * my.x + nyz * mz.x, nxy * mx.y + nyy * my.y + nyz * mz.y};
+            v[2][i] = C{nxz * mx.x + nyz * my.x + nzz * mz.x, nxz * mx.y + nyz * my.y + nzz * mz.y};
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fft_dit<T, LZ, true, LZ / 2>(v[c]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int z = 0; z < LZ / 2; ++z)
+            if (z < nz) p[c * cs + z * zs] = Spec<T, S>::put(v[c][z]);
+    }
+}
+
+// ------------------------------------------------------------------------
 // Newell tensor (ref. [24]) in double precision.
 // f and g are evaluated on |x|,|y|,|z|; g carries sign(x) sign(y).
 __device__ double newell_f(double x, double y, double z) {
@@ -701,9 +767,31 @@ hipError_t launch_colfft(hipStream_t s, int L, bool inv, SpecPtr src, long s_cs,
 
 template <typename T, typename S>
 hipError_t launch_zmul(hipStream_t s, int LZ, SpecPtr buf, int SX, int Kx, int nz, int nyrows, int Py, int Pz,
-                       const T* kfold, int Kyf, int Kzf, const cx<T>* tw, int nb, T kscale) {
+                       const T* kfold, int Kyf, int Kzf, const cx<T>* tw, int nb, T kscale, int variant) {
     using E = typename Spec<T, S>::elem;
     E* bp = (E*)buf;
+    if (variant == ZMUL_REG) {
+        if (!zmul_reg_ok<T>(LZ)) return hipErrorInvalidValue;
+        const long total = (long)(Py / 2 + 1) * 2 * Kx;
+        const dim3 g((unsigned)((total + NT - 1) / NT), (unsigned)nb, 1);
+        switch (LZ) {
+#define ZR(LL) \
+    case LL: k_zmul_reg<T, S, LL><<<g, NT, 0, s>>>(bp, SX, Kx, nz, nyrows, Py, kfold, Kyf, Kzf, kscale); break;
+            ZR(2) ZR(4) ZR(8)
+#undef ZR
+            case 16:
+                if constexpr (sizeof(T) == 4)
+                    k_zmul_reg<T, S, 16><<<g, NT, 0, s>>>(bp, SX, Kx, nz, nyrows, Py, kfold, Kyf, Kzf, kscale);
+                break;
+            case 32:
+                if constexpr (sizeof(T) == 4)
+                    k_zmul_reg<T, S, 32><<<g, NT, 0, s>>>(bp, SX, Kx, nz, nyrows, Py, kfold, Kyf, Kzf, kscale);
+                break;
+            default:
+                return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
 #define ZM(LL)                                                                                                 \
     case LL: {                                                                                                 \
         constexpr int TK = zmul_tile<T>(LL);                                                                   \
@@ -756,7 +844,7 @@ hipError_t launch_fold(hipStream_t s, const cx<double>* spec, int SX, int Kx, in
     template hipError_t launch_colfft<T, S>(hipStream_t, int, bool, SpecPtr, long, long, long, int, SpecPtr, long, \
                                             long, long, int, int, int, int, const cx<T>*, T);                     \
     template hipError_t launch_zmul<T, S>(hipStream_t, int, SpecPtr, int, int, int, int, int, int, const T*, int,  \
-                                          int, const cx<T>*, int, T);
+                                          int, const cx<T>*, int, T, int);
 INST_TS(float, float)
 INST_TS(float, _Float16)
 INST_TS(float, __bf16)

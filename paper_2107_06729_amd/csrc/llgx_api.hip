@@ -52,6 +52,7 @@ struct Ctx {
     int nx = 1, ny = 1, nz = 1;
     long ncell = 1;             // cells per sample
     int nb = 1;                 // samples sharing this mesh (batched launches)
+    int zvar = ZMUL_LDS;        // z-pass variant
     void* hab = nullptr;        // per-sample applied fields [nb][3] (device, working precision)
     int Px = 1, Py = 1, Pz = 1, LX = 0, Kx = 1, SX = 16, Kyf = 1, Kzf = 1;
 
@@ -135,7 +136,7 @@ static hipEvent_t take_event(Ctx* c) {
         return e;
     }
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 
@@ -255,7 +256,7 @@ static llgx_status eval_exact_s(Ctx* c, const Combo<T>& in, T* mk_out, int mode,
     {
         PROF(LLGX_K_ZMUL);
         HIPCHK(c, (launch_zmul<T, S>(s, c->Pz, work, c->SX, c->Kx, c->nz, nyrows, c->Py, c->Pz, (const T*)c->kfold,
-                                     c->Kyf, c->Kzf, table<T>(c, c->Pz, false), c->nb, kscale)));
+                                     c->Kyf, c->Kzf, table<T>(c, c->Pz, false), c->nb, kscale, c->zvar)));
     }
     if (c->Py > 1) {
         void* B = c->specB;
@@ -1333,6 +1334,109 @@ llgx_status llgx_set_time(llgx_handle h, double t) {
     c->t = t;
     c->hist.clear();
     c->fsal_valid = false;
+    return LLGX_OK;
+}
+
+// ---- checkpoint ---------------------------------------------------------
+// Host image: header, then M, then the history fields oldest first, then the
+// FSAL stage-1 field when it is valid.  All arrays in the working precision.
+struct CkptHeader {
+    char magic[8];
+    int32_t version, prec, nx, ny, nz, nb;
+    int32_t method, p, nhist, fsal_valid;
+    double t, h_next;
+    double hist_t[MAX_HIST];
+    int64_t counters[5];
+};
+static const char kCkptMagic[8] = {'L', 'L', 'G', 'X', 'C', 'K', 'P', '1'};
+
+static size_t ckpt_size(const Ctx* c) {
+    const size_t vec = 3 * (size_t)c->ncell * c->nb * c->tsz;
+    return sizeof(CkptHeader) + vec * (1 + c->hist.size() + (c->fsal_valid ? 1 : 0));
+}
+
+llgx_status llgx_save_state(llgx_handle h, void* host_buf, size_t cap, size_t* used) {
+    if (!h) return LLGX_E_ARG;
+    Ctx* c = (Ctx*)h;
+    if (!c->have_m) return c->fail(LLGX_E_STATE, "magnetization not set");
+    const size_t need = ckpt_size(c);
+    if (used) *used = need;
+    if (!host_buf) return LLGX_OK;
+    if (cap < need) return c->fail(LLGX_E_ARG, "checkpoint needs %zu bytes, buffer holds %zu", need, cap);
+    CkptHeader hd{};
+    memcpy(hd.magic, kCkptMagic, 8);
+    hd.version = 1;
+    hd.prec = c->prec;
+    hd.nx = c->nx;
+    hd.ny = c->ny;
+    hd.nz = c->nz;
+    hd.nb = c->nb;
+    hd.method = c->cur_method;
+    hd.p = c->cur_p;
+    hd.nhist = (int32_t)c->hist.size();
+    hd.fsal_valid = c->fsal_valid ? 1 : 0;
+    hd.t = c->t;
+    hd.h_next = c->h_next;
+    for (size_t i = 0; i < c->hist.size(); ++i) hd.hist_t[i] = c->hist[i].t;
+    hd.counters[0] = c->n_exact;
+    hd.counters[1] = c->n_extrap;
+    hd.counters[2] = c->n_acc;
+    hd.counters[3] = c->n_rej;
+    hd.counters[4] = c->n_forced;
+    char* out = (char*)host_buf;
+    memcpy(out, &hd, sizeof hd);
+    const size_t vec = 3 * (size_t)c->ncell * c->nb * c->tsz;
+    size_t off = sizeof hd;
+    HIPCHK(c, hipMemcpyAsync(out + off, c->M, vec, hipMemcpyDeviceToHost, c->stream));
+    off += vec;
+    for (const auto& e : c->hist) {
+        HIPCHK(c, hipMemcpyAsync(out + off, c->G[e.slot], vec, hipMemcpyDeviceToHost, c->stream));
+        off += vec;
+    }
+    if (c->fsal_valid) HIPCHK(c, hipMemcpyAsync(out + off, c->F[0], vec, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LLGX_OK;
+}
+
+llgx_status llgx_load_state(llgx_handle h, const void* host_buf, size_t len) {
+    if (!h) return LLGX_E_ARG;
+    Ctx* c = (Ctx*)h;
+    if (!host_buf || len < sizeof(CkptHeader)) return c->fail(LLGX_E_ARG, "checkpoint too short");
+    CkptHeader hd;
+    memcpy(&hd, host_buf, sizeof hd);
+    if (memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 1)
+        return c->fail(LLGX_E_ARG, "not a checkpoint of this library");
+    if (hd.prec != c->prec || hd.nx != c->nx || hd.ny != c->ny || hd.nz != c->nz || hd.nb != c->nb)
+        return c->fail(LLGX_E_ARG, "checkpoint of a %dx%dx%d x%d mesh in precision %d does not fit this handle",
+                       hd.nx, hd.ny, hd.nz, hd.nb, hd.prec);
+    if (hd.nhist < 0 || hd.nhist > MAX_HIST - 1 || (hd.fsal_valid != 0 && hd.fsal_valid != 1))
+        return c->fail(LLGX_E_ARG, "corrupt checkpoint header");
+    const size_t vec = 3 * (size_t)c->ncell * c->nb * c->tsz;
+    const size_t need = sizeof hd + vec * (1 + (size_t)hd.nhist + (size_t)hd.fsal_valid);
+    if (len != need) return c->fail(LLGX_E_ARG, "checkpoint length %zu, expected %zu", len, need);
+    const char* in = (const char*)host_buf;
+    size_t off = sizeof hd;
+    HIPCHK(c, hipMemcpyAsync(c->M, in + off, vec, hipMemcpyHostToDevice, c->stream));
+    off += vec;
+    c->hist.clear();
+    for (int i = 0; i < hd.nhist; ++i) {
+        HIPCHK(c, hipMemcpyAsync(c->G[i], in + off, vec, hipMemcpyHostToDevice, c->stream));
+        c->hist.push_back({hd.hist_t[i], i});
+        off += vec;
+    }
+    if (hd.fsal_valid) HIPCHK(c, hipMemcpyAsync(c->F[0], in + off, vec, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->fsal_valid = hd.fsal_valid != 0;
+    c->cur_method = hd.method;
+    c->cur_p = hd.p;
+    c->t = hd.t;
+    c->h_next = hd.h_next;
+    c->n_exact = hd.counters[0];
+    c->n_extrap = hd.counters[1];
+    c->n_acc = hd.counters[2];
+    c->n_rej = hd.counters[3];
+    c->n_forced = hd.counters[4];
+    c->have_m = true;
     return LLGX_OK;
 }
 
