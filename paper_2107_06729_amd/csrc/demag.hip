@@ -18,7 +18,7 @@
 
 #include "kernels.hpp"
 #include "physics.hpp"
-#include "fft_reg.hpp"
+#include "fft_col.hpp"
 #include "spec_store.hpp"
 #include "tile_io.hpp"
 
@@ -275,18 +275,27 @@ __global__ __launch_bounds__(NT) void k_colfft(const typename Spec<T, S>::elem* 
                                                long d_is, int n_out, int Kx, const cx<T>* __restrict__ tw,
                                                T scale) {
     using C = cx<T>;
-    __shared__ C buf[L * TK];
-    __shared__ C twl[L];
+    using F = ColFFT<T, S, L, INV, TK, 1, NT>;
+    using E = typename Spec<T, S>::elem;
     const int kx0 = blockIdx.x * TK;
-    const auto* sp = src + blockIdx.z * s_cs + blockIdx.y * s_os + kx0;
-    TwStage<T, L, NT> tws;
-    tws.fetch(tw);
-    load_tile_s<T, S, L, TK, NT>(buf, sp, s_is, n_in, Kx - kx0);
-    tws.put(twl);
-    __syncthreads();
-    lds_fft<T, L, INV, Cols<TK, 1, TK, true>, NT>(buf, twl);
-    auto* dp = dst + blockIdx.z * d_cs + blockIdx.y * d_os + kx0;
-    store_tile_s<T, S, L, TK, NT>(dp, d_is, buf, n_out, Kx - kx0, scale);
+    const Base1<const E> sp{src + blockIdx.z * s_cs + blockIdx.y * s_os + kx0};
+    const Base1<E> dp{dst + blockIdx.z * d_cs + blockIdx.y * d_os + kx0};
+    typename F::Regs rg;
+    if constexpr (F::NSTAGE == 1) {
+        F::load_first(rg, sp, s_is, n_in, Kx - kx0, 1);
+        F::single(rg, dp, d_is, n_out, Kx - kx0, 1, scale);
+    } else {
+        __shared__ C buf[F::LDS_ELEMS];
+        __shared__ C twl[L];
+        TwStage<T, L, NT> tws;
+        tws.fetch(tw);
+        F::load_first(rg, sp, s_is, n_in, Kx - kx0, 1);
+        tws.put(twl);
+        F::first_to_lds(rg, buf);
+        __syncthreads();
+        F::middle(buf, twl);
+        F::last_to_global(buf, twl, dp, d_is, n_out, Kx - kx0, 1, scale);
+    }
 }
 
 // ------------------------------------------------------------------------
@@ -295,169 +304,180 @@ __global__ __launch_bounds__(NT) void k_colfft(const typename Spec<T, S>::elem* 
 // (xy, yz) change sign for ky > Py/2, those odd in z (xz, yz) for kz > Pz/2),
 // z inverse.  In place on rows z < nz of the [3][nz][nyrows][SX] buffer.
 // One workgroup takes the rows ky = q and ky = Py - q, which share the folded
-// kernel, so every folded value is read from memory once.
-template <typename T, typename S, int LZ, int TK>
-__global__ __launch_bounds__(NT) void k_zmul(typename Spec<T, S>::elem* __restrict__ buf, int SX, int Kx, int nz,
-                                             int nyrows, int Py, int Pz, const T* __restrict__ kfold, int Kyf,
-                                             int Kzf, const cx<T>* __restrict__ tw, T kscale) {
-    using C = cx<T>;
-    using E = typename Spec<T, S>::elem;
-    constexpr int PN = pack_n<E, TK>();
-    using PU = PackU<E, PN>;
-    using RW = typename Raw<PN * (int)sizeof(E)>::type;
-    constexpr int NC = 6 * TK;              // 2 rows x 3 components x TK columns
-    constexpr int KZF = LZ / 2 + 1;         // folded kz extent (LZ = Pz)
-    constexpr int PR = TK / PN, TOT = LZ * 6 * PR, PER = (TOT + NT - 1) / NT;
-    constexpr int KTOT = KZF * TK * 6, KPER = (KTOT + NT - 1) / NT;
-    static_assert(TK % PN == 0, "tile width");
-    __shared__ C lb[LZ * NC];
-    (void)sizeof(PU);
-    __shared__ T kl[KZF * 6 * TK];
-    __shared__ C twl[LZ > 1 ? LZ : 1];
-    const int kx0 = blockIdx.x * TK;
-    const int q = blockIdx.y;                // 0 <= q <= Py/2
-    const int nrow = (2 * q == Py || q == 0) ? 1 : 2;
-    const int ncol = Kx - kx0;
-    const long cs = (long)nz * nyrows * SX, zs = (long)nyrows * SX;
-    buf += (long)blockIdx.z * 3 * cs;  // sample
-    E* bp0 = buf + (long)q * SX + kx0;
-    E* bp1 = buf + (long)(Py - q) * SX + kx0;
-    TwStage<T, (LZ > 1 ? LZ : 1), NT> tws;
-    if (LZ > 1) tws.fetch(tw);
-    // staged loads: LDS row (z*2 + w)*3 + c holds component c of row z of ky row w
-    PU r[PER];
+// kernel, so every folded value is read from memory once.  Tile groups
+// g = w * 3 + c: component c of row ky = (w ? Py - q : q).
+//
+// Folded kernel layout (kernel_index): blocks of KB = 16 / sizeof(T)
+// adjacent kx, each block holding all (kz, component) values of one ky, so a
+// workgroup reads its kernel values as contiguous 16-byte packs.
+template <typename T>
+__host__ __device__ __forceinline__ long kernel_index(int kyf, int kx, int kzf, int comp, int SX, int Kzf) {
+    constexpr int KB = 16 / (int)sizeof(T);
+    return ((((long)kyf * (SX / KB) + kx / KB) * Kzf + kzf) * 6 + comp) * KB + kx % KB;
+}
+
+template <typename E>
+struct ZBases {
+    E* row0;  // (ky = q, component 0, z = 0, kx0)
+    E* row1;  // (ky = Py - q, ...)
+    long cs;
+    __device__ __forceinline__ E* operator()(int g) const { return (g >= 3 ? row1 : row0) + (g % 3) * cs; }
+};
+
+// folded kernel values of columns kx0 .. kx0+TK-1 of row kyf into LDS
+// kl[(kzf * 6 + comp) * TK + col], times kscale; columns >= ncol read as zero
+template <typename T, int TK, int KZF>
+__device__ __forceinline__ void load_kernel_tile(T* kl, const T* __restrict__ kfold, int kyf, int kx0, int ncol,
+                                                 int SX, T kscale) {
+    constexpr int KB = 16 / (int)sizeof(T);
+    if constexpr (TK % KB == 0) {
+        using V = typename Pack<T>::type;  // 16 bytes = KB values
+        constexpr int NPK = (TK / KB) * KZF * 6, PER = (NPK + NT - 1) / NT;
+        V r[PER];
 #pragma unroll
-    for (int m = 0; m < PER; ++m) {
-        const int e = threadIdx.x + m * NT;
-        const int row = e / PR, j = e - row * PR;
-        const int z = row / 6, wc = row - 6 * z, w = wc / 3, c = wc - 3 * w;
-        r[m].raw = {};
-        if ((TOT % NT == 0 || e < TOT) && z < nz && w < nrow && j * PN < ncol)
-            r[m].raw = *(const RW*)((w ? bp1 : bp0) + c * cs + z * zs + j * PN);
-    }
-    // folded kernel values of this column tile for kz <= Pz/2 (stored [kzf][comp][col])
-    T kr[KPER];
-#pragma unroll
-    for (int m = 0; m < KPER; ++m) {
-        const int e = threadIdx.x + m * NT;
-        const int kzf = e / (6 * TK), rem = e - kzf * 6 * TK, comp = rem / TK, col = rem - comp * TK;
-        kr[m] = T(0);
-        if ((KTOT % NT == 0 || e < KTOT) && kzf < Kzf && col < ncol)
-            kr[m] = kscale * kfold[(((long)comp * Kzf + kzf) * Kyf + q) * SX + kx0 + col];
-    }
-#pragma unroll
-    for (int m = 0; m < PER; ++m) {
-        const int e = threadIdx.x + m * NT;
-        if (TOT % NT == 0 || e < TOT) {
-#pragma unroll
-            for (int qq = 0; qq < PN; ++qq) lb[e * PN + qq] = Spec<T, S>::get(r[m].e[qq]);
+        for (int m = 0; m < PER; ++m) {
+            const int e = threadIdx.x + m * NT;
+            const int b = e / (KZF * 6), rem = e - b * (KZF * 6);
+            r[m] = Pack<T>::zero();
+            if ((NPK % NT == 0 || e < NPK) && b * KB < ncol)
+                r[m] = *(const V*)(kfold + kernel_index<T>(kyf, kx0 + b * KB, rem / 6, rem % 6, SX, KZF));
         }
-    }
 #pragma unroll
-    for (int m = 0; m < KPER; ++m) {
-        const int e = threadIdx.x + m * NT;
-        if (KTOT % NT == 0 || e < KTOT) kl[e] = kr[m];
-    }
-    if (LZ > 1) tws.put(twl);
-    __syncthreads();
-    lds_fft<T, LZ, false, Cols<NC, 1, NC, true>, NT>(lb, twl);
-    for (int e = threadIdx.x; e < LZ * 2 * TK; e += NT) {
-        const int kz = e / (2 * TK), rem = e - kz * 2 * TK, w = rem / TK, col = rem - w * TK;
-        if (col >= ncol || w >= nrow) continue;
-        const int kzf = (2 * kz <= Pz) ? kz : Pz - kz;
-        const T sz = (2 * kz > Pz) ? T(-1) : T(1);
-        const T sy = w ? T(-1) : T(1);
-        const T* kp = kl + kzf * 6 * TK + col;
-        const T nxx = kp[0], nyy = kp[TK], nzz = kp[2 * TK];
-        const T nxy = sy * kp[3 * TK], nxz = sz * kp[4 * TK], nyz = sy * sz * kp[5 * TK];
-        C* p = lb + kz * NC + w * 3 * TK + col;
-        const C mx = p[0], my = p[TK], mz = p[2 * TK];
-        p[0] = C{nxx * mx.x + nxy * my.x + nxz * mz.x, nxx * mx.y + nxy * my.y + nxz * mz.y};
-        p[TK] = C{nxy * mx.x + nyy * my.x + nyz * mz.x, nxy * mx.y + nyy * my.y + nyz * mz.y};
-        p[2 * TK] = C{nxz * mx.x + nyz * my.x + nzz * mz.x, nxz * mx.y + nyz * my.y + nzz * mz.y};
-    }
-    __syncthreads();
-    lds_fft<T, LZ, true, Cols<NC, 1, NC, true>, NT>(lb, twl);
+        for (int m = 0; m < PER; ++m) {
+            const int e = threadIdx.x + m * NT;
+            if (NPK % NT == 0 || e < NPK) {
+                const int b = e / (KZF * 6), rem = e - b * (KZF * 6);
+                const T* v = (const T*)&r[m];
 #pragma unroll
-    for (int m = 0; m < PER; ++m) {
-        const int e = threadIdx.x + m * NT;
-        if (TOT % NT == 0 || e < TOT) {
-#pragma unroll
-            for (int qq = 0; qq < PN; ++qq) r[m].e[qq] = Spec<T, S>::put(lb[e * PN + qq]);
+                for (int i = 0; i < KB; ++i) kl[rem * TK + b * KB + i] = kscale * v[i];
+            }
         }
-    }
+    } else {
+        constexpr int NE = TK * KZF * 6, PER = (NE + NT - 1) / NT;
+        T r[PER];
 #pragma unroll
-    for (int m = 0; m < PER; ++m) {
-        const int e = threadIdx.x + m * NT;
-        const int row = e / PR, j = e - row * PR;
-        const int z = row / 6, wc = row - 6 * z, w = wc / 3, c = wc - 3 * w;
-        if ((TOT % NT == 0 || e < TOT) && z < nz && w < nrow && j * PN < ncol)
-            *(RW*)((w ? bp1 : bp0) + c * cs + z * zs + j * PN) = r[m].raw;
+        for (int m = 0; m < PER; ++m) {
+            const int e = threadIdx.x + m * NT;
+            const int col = e % TK, rem = e / TK;
+            r[m] = T(0);
+            if ((NE % NT == 0 || e < NE) && col < ncol)
+                r[m] = kfold[kernel_index<T>(kyf, kx0 + col, rem / 6, rem % 6, SX, KZF)];
+        }
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int e = threadIdx.x + m * NT;
+            if (NE % NT == 0 || e < NE) kl[e] = kscale * r[m];
+        }
     }
 }
 
-// ------------------------------------------------------------------------
-// Same pass for short z pencils (LZ <= 32 in FP32), one pencil triple per
-// thread in registers: thread (q, w, kx), kx fastest, owns the x, y and z
-// components of pencil (ky = q or Py - q, kx).  Forward DIF with the zero
-// upper half pruned leaves the spectrum in bit-reversed kz order; the kernel
-// product is applied there (each folded kz value loaded once for kz and
-// Pz - kz); the inverse DIT returns natural order and forms only z < Pz/2.
-template <typename T, typename S, int LZ>
-__global__ __launch_bounds__(NT) void k_zmul_reg(typename Spec<T, S>::elem* __restrict__ buf, int SX, int Kx, int nz,
-                                                 int nyrows, int Py, const T* __restrict__ kfold, int Kyf, int Kzf,
-                                                 T kscale) {
+// H = K M on LDS rows: row kz, groups (w, c), TK columns
+template <typename T, int LZ, int TK, int NTH>
+__device__ __forceinline__ void kspace_product(cx<T>* lb, const T* kl, int ng) {
+    using C = cx<T>;
+    constexpr int W = 6 * TK, NU = LZ * 2 * TK, PER = (NU + NTH - 1) / NTH;
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+        const int e = threadIdx.x + m * NTH;
+        const int col = e % TK, t = e / TK, w = t & 1, kz = t >> 1;
+        if ((NU % NTH == 0 || e < NU) && 3 * (w + 1) <= ng) {
+            const int kzf = (2 * kz <= LZ) ? kz : LZ - kz;
+            const T sz = (2 * kz > LZ) ? T(-1) : T(1);
+            const T sy = w ? T(-1) : T(1);
+            const T* kp = kl + kzf * 6 * TK + col;
+            const T nxx = kp[0], nyy = kp[TK], nzz = kp[2 * TK];
+            const T nxy = sy * kp[3 * TK], nxz = sz * kp[4 * TK], nyz = sy * sz * kp[5 * TK];
+            C* p = lb + kz * W + w * 3 * TK + col;
+            const C mx = p[0], my = p[TK], mz = p[2 * TK];
+            p[0] = C{nxx * mx.x + nxy * my.x + nxz * mz.x, nxx * mx.y + nxy * my.y + nxz * mz.y};
+            p[TK] = C{nxy * mx.x + nyy * my.x + nyz * mz.x, nxy * mx.y + nyy * my.y + nyz * mz.y};
+            p[2 * TK] = C{nxz * mx.x + nyz * my.x + nzz * mz.x, nxz * mx.y + nyz * my.y + nzz * mz.y};
+        }
+    }
+}
+
+template <typename T, typename S, int LZ, int TK>
+__global__ __launch_bounds__(NT) void k_zmul(typename Spec<T, S>::elem* __restrict__ buf, int SX, int Kx, int nz,
+                                             int nyrows, int Py, const T* __restrict__ kfold,
+                                             const cx<T>* __restrict__ tw, T kscale) {
     using C = cx<T>;
     using E = typename Spec<T, S>::elem;
-    const long gid = (long)blockIdx.x * NT + threadIdx.x;
-    const long total = (long)(Py / 2 + 1) * 2 * Kx;
-    if (gid >= total) return;
-    const int kx = (int)(gid % Kx);
-    const long rest = gid / Kx;
-    const int w = (int)(rest & 1), q = (int)(rest >> 1);
-    if (w == 1 && (q == 0 || 2 * q == Py)) return;  // rows paired with themselves
-    const int ky = w ? Py - q : q;
+    constexpr int L = LZ > 1 ? LZ : 2;  // LZ = 1 uses no transform
+    constexpr int KZF = LZ / 2 + 1;
+    using Ff = ColFFT<T, S, L, false, TK, 6, NT>;
+    using Fi = ColFFT<T, S, L, true, TK, 6, NT>;
+    __shared__ C lb[LZ * 6 * TK];
+    __shared__ T kl[KZF * 6 * TK];
+    __shared__ C twl[L];
+    const int kx0 = blockIdx.x * TK;
+    const int q = blockIdx.y;  // 0 <= q <= Py/2
+    const int ng = (2 * q == Py || q == 0) ? 3 : 6;
+    const int ncol = Kx - kx0;
     const long cs = (long)nz * nyrows * SX, zs = (long)nyrows * SX;
-    E* p = buf + (long)blockIdx.y * 3 * cs + (long)ky * SX + kx;
-    C v[3][LZ];
+    E* sb = buf + (long)blockIdx.z * 3 * cs;  // sample
+    const ZBases<E> bases{sb + (long)q * SX + kx0, sb + (long)(Py - q) * SX + kx0, cs};
+    if constexpr (LZ == 1) {
+        // no z transform: load the 6 x TK values, multiply, store
+        using PU = typename Ff::PU;
+        using RW = typename Ff::RW;
+        constexpr int PN = Ff::PN, NU = 6 * (TK / PN);
+        for (int u = threadIdx.x; u < NU; u += NT) {
+            const int p = u % (TK / PN), g = u / (TK / PN);
+            if (g < ng && p * PN < ncol) {
+                PU v;
+                v.raw = *(const RW*)(bases(g) + p * PN);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-#pragma unroll
-        for (int z = 0; z < LZ; ++z) {
-            v[c][z] = C{T(0), T(0)};
-            if (z < LZ / 2 && z < nz) v[c][z] = Spec<T, S>::get(p[c * cs + z * zs]);
+                for (int i = 0; i < PN; ++i) lb[g * TK + p * PN + i] = Spec<T, S>::get(v.e[i]);
+            }
         }
-    }
+        load_kernel_tile<T, TK, KZF>(kl, kfold, q, kx0, ncol, SX, kscale);
+        __syncthreads();
+        kspace_product<T, 1, TK, NT>(lb, kl, ng);
+        __syncthreads();
+        for (int u = threadIdx.x; u < NU; u += NT) {
+            const int p = u % (TK / PN), g = u / (TK / PN);
+            if (g < ng && p * PN < ncol) {
+                PU v;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) fft_dif<T, LZ, false, true>(v[c]);
-    const T sy = w ? T(-1) : T(1);
-    const long kcs = (long)Kzf * Kyf * SX, kzs = (long)Kyf * SX;
-    const T* kp = kfold + (long)q * SX + kx;
-#pragma unroll
-    for (int kzf = 0; kzf <= LZ / 2; ++kzf) {
-        const T* kk = kp + kzf * kzs;
-        const T nxx = kscale * kk[0], nyy = kscale * kk[kcs], nzz = kscale * kk[2 * kcs];
-        const T nxy0 = kscale * sy * kk[3 * kcs], nxz0 = kscale * kk[4 * kcs], nyz0 = kscale * sy * kk[5 * kcs];
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            if (side == 1 && (kzf == 0 || kzf == LZ / 2)) continue;
-            const int kz = side ? LZ - kzf : kzf;
-            const int i = bitrev(kz, LZ);
-            const T sz = side ? T(-1) : T(1);
-            const T nxy = nxy0, nxz = sz * nxz0, nyz = sz * nyz0;
-            const C mx = v[0][i], my = v[1][i], mz = v[2][i];
-            v[0][i] = C{nxx * mx.x + nxy * my.x + nxz * mz.x, nxx * mx.y + nxy * my.y + nxz * mz.y};
-            v[1][i] = C{nxy * mx.x + nyy * my.x + nyz * mz.x, nxy * mx.y + nyy * my.y + nyz * mz.y};
-            v[2][i] = C{nxz * mx.x + nyz * my.x + nzz * mz.x, nxz * mx.y + nyz * my.y + nzz * mz.y};
+                for (int i = 0; i < PN; ++i) v.e[i] = Spec<T, S>::put(lb[g * TK + p * PN + i]);
+                *(RW*)(bases(g) + p * PN) = v.raw;
+            }
         }
-    }
+    } else {
+        TwStage<T, LZ, NT> tws;
+        tws.fetch(tw);
+        typename Ff::Regs rg;
+        Ff::load_first(rg, bases, zs, nz, ncol, ng);
+        load_kernel_tile<T, TK, KZF>(kl, kfold, q, kx0, ncol, SX, kscale);
+        tws.put(twl);
+        Ff::first_to_lds(rg, lb);
+        __syncthreads();
+        if constexpr (Ff::NSTAGE > 1) {
+            Ff::middle(lb, twl);
+            Ff::last_in_lds(lb, twl);
+            __syncthreads();
+        }
+        kspace_product<T, LZ, TK, NT>(lb, kl, ng);
+        __syncthreads();
+        Fi::first_in_lds(lb);
+        if constexpr (Fi::NSTAGE > 1) {
+            Fi::middle(lb, twl);
+            Fi::last_to_global(lb, twl, bases, zs, nz, ncol, ng, T(1));
+        } else {
+            // single-stage lengths: rows z < nz from LDS
+            using PU = typename Ff::PU;
+            using RW = typename Ff::RW;
+            constexpr int PN = Ff::PN, NU = LZ * 6 * (TK / PN);
+            for (int u = threadIdx.x; u < NU; u += NT) {
+                const int p = u % (TK / PN), t = u / (TK / PN), g = t % 6, z = t / 6;
+                if (g < ng && p * PN < ncol && z < nz) {
+                    PU v;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) fft_dit<T, LZ, true, LZ / 2>(v[c]);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-#pragma unroll
-        for (int z = 0; z < LZ / 2; ++z)
-            if (z < nz) p[c * cs + z * zs] = Spec<T, S>::put(v[c][z]);
+                    for (int i = 0; i < PN; ++i) v.e[i] = Spec<T, S>::put(lb[z * 6 * TK + g * TK + p * PN + i]);
+                    *(RW*)(bases(g) + z * zs + p * PN) = v.raw;
+                }
+            }
+        }
     }
 }
 
@@ -656,7 +676,7 @@ __global__ __launch_bounds__(NT) void k_fold(const cx<double>* __restrict__ spec
         const long r = e / Kx;
         const int kyf = (int)(r % Kyf), kzf = (int)(r / Kyf);
         const cx<double> v = spec[((long)kzf * Py + kyf) * SX + kx];
-        kfold[(((long)comp * Kzf + kzf) * Kyf + kyf) * SX + kx] = (T)(v.x * scale);
+        kfold[kernel_index<T>(kyf, kx, kzf, comp, SX, Kzf)] = (T)(v.x * scale);
         mx = fmax(mx, fabs(v.y * scale));
     }
     red[threadIdx.x] = mx;
@@ -770,43 +790,19 @@ hipError_t launch_zmul(hipStream_t s, int LZ, SpecPtr buf, int SX, int Kx, int n
                        const T* kfold, int Kyf, int Kzf, const cx<T>* tw, int nb, T kscale, int variant) {
     using E = typename Spec<T, S>::elem;
     E* bp = (E*)buf;
-    if (variant == ZMUL_REG) {
-        if (!zmul_reg_ok<T>(LZ)) return hipErrorInvalidValue;
-        const long total = (long)(Py / 2 + 1) * 2 * Kx;
-        const dim3 g((unsigned)((total + NT - 1) / NT), (unsigned)nb, 1);
-        switch (LZ) {
-#define ZR(LL) \
-    case LL: k_zmul_reg<T, S, LL><<<g, NT, 0, s>>>(bp, SX, Kx, nz, nyrows, Py, kfold, Kyf, Kzf, kscale); break;
-            ZR(2) ZR(4) ZR(8)
-#undef ZR
-            case 16:
-                if constexpr (sizeof(T) == 4)
-                    k_zmul_reg<T, S, 16><<<g, NT, 0, s>>>(bp, SX, Kx, nz, nyrows, Py, kfold, Kyf, Kzf, kscale);
-                break;
-            case 32:
-                if constexpr (sizeof(T) == 4)
-                    k_zmul_reg<T, S, 32><<<g, NT, 0, s>>>(bp, SX, Kx, nz, nyrows, Py, kfold, Kyf, Kzf, kscale);
-                break;
-            default:
-                return hipErrorInvalidValue;
-        }
-        return hipGetLastError();
-    }
-#define ZM(LL)                                                                                                 \
-    case LL: {                                                                                                 \
-        constexpr int TK = zmul_tile<T>(LL);                                                                   \
-        dim3 g((unsigned)((Kx + TK - 1) / TK), (unsigned)(Py / 2 + 1), (unsigned)nb);                          \
-        k_zmul<T, S, LL, TK><<<g, NT, 0, s>>>(bp, SX, Kx, nz, nyrows, Py, Pz, kfold, Kyf, Kzf, tw, kscale);     \
-        break;                                                                                                 \
+    (void)Pz;
+    (void)Kyf;
+    (void)Kzf;
+    (void)variant;
+#define ZM(LL)                                                                                     \
+    case LL: {                                                                                     \
+        constexpr int TK = zmul_tile<T>(LL);                                                       \
+        dim3 g((unsigned)((Kx + TK - 1) / TK), (unsigned)(Py / 2 + 1), (unsigned)nb);              \
+        k_zmul<T, S, LL, TK><<<g, NT, 0, s>>>(bp, SX, Kx, nz, nyrows, Py, kfold, tw, kscale);        \
+        break;                                                                                     \
     }
     switch (LZ) {
-        case 1: {
-            constexpr int TK = 32;
-            dim3 g((unsigned)((Kx + TK - 1) / TK), (unsigned)(Py / 2 + 1), (unsigned)nb);
-            k_zmul<T, S, 1, TK><<<g, NT, 0, s>>>(bp, SX, Kx, nz, nyrows, Py, Pz, kfold, Kyf, Kzf, tw, kscale);
-            break;
-        }
-        ZM(2) ZM(4) ZM(8) ZM(16) ZM(32) ZM(64) ZM(128) ZM(256) ZM(512) ZM(1024)
+        ZM(1) ZM(2) ZM(4) ZM(8) ZM(16) ZM(32) ZM(64) ZM(128) ZM(256) ZM(512) ZM(1024)
         default:
             return hipErrorInvalidValue;
     }

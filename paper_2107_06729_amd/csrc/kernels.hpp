@@ -99,13 +99,6 @@ hipError_t launch_colfft(hipStream_t s, int L, bool inv, SpecPtr src, long s_cs,
 template <typename T, typename S>
 hipError_t launch_zmul(hipStream_t s, int LZ, SpecPtr buf, int SX, int Kx, int nz, int nyrows, int Py, int Pz,
                        const T* kfold, int Kyf, int Kzf, const cx<T>* tw, int nb, T kscale, int variant);
-// variant of the z pass: 0 LDS Stockham tiles; 1 one pencil triple per thread
-// in registers (LZ <= 32 in FP32, <= 8 in FP64; hipErrorInvalidValue otherwise)
-constexpr int ZMUL_LDS = 0, ZMUL_REG = 1;
-template <typename T>
-constexpr bool zmul_reg_ok(int LZ) {
-    return LZ >= 2 && LZ <= (sizeof(T) == 4 ? 32 : 8);
-}
 hipError_t launch_newell_octant(hipStream_t s, int nx, int ny, int nz, double dx, double dy, double dz,
                                 double* octant);
 hipError_t launch_scatter_tensor(hipStream_t s, const double* octant, int comp, int nx, int ny, int nz,

@@ -52,7 +52,7 @@ struct Ctx {
     int nx = 1, ny = 1, nz = 1;
     long ncell = 1;             // cells per sample
     int nb = 1;                 // samples sharing this mesh (batched launches)
-    int zvar = ZMUL_LDS;        // z-pass variant
+    int zvar = 0;               // z-pass variant
     void* hab = nullptr;        // per-sample applied fields [nb][3] (device, working precision)
     int Px = 1, Py = 1, Pz = 1, LX = 0, Kx = 1, SX = 16, Kyf = 1, Kzf = 1;
 
