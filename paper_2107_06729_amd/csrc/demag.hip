@@ -240,7 +240,7 @@ __global__ __launch_bounds__(NT) void k_xinv(const typename Spec<T, S>::elem* __
         } else {
             const int y = (int)(g % ph.ny), z = (int)(g / ph.ny);
             T m[3], H[3];
-            heff_at(M, N, cell, x, y, z, b, ph, hd, m, H);
+            heff_at(PtrField<T>{M}, N, cell, x, y, z, b, ph, hd, m, H);
             if constexpr (MODE == XINV_HEFF) {
                 T* Ho = (T*)out.h + vo;
 #pragma unroll

@@ -44,6 +44,15 @@ struct CellGrid {
 };
 CellGrid cell_grid(int nx, int ny, int nz, int nb);
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2): block b runs on XCD b % 8.  Give each XCD one contiguous run of row
+// groups, so the y and z neighbours a stencil reads were mostly fetched into
+// the same L2 by the same XCD.
+__device__ __forceinline__ int xcd_run(int b, int nblk) {
+    const int q = nblk >> 3, r = nblk & 7, x = b & 7, i = b >> 3;
+    return x * q + (x < r ? x : r) + i;
+}
+
 // Eq. (3): M = M0 + sum_k cb[k] f[k] (cb = h c_k) and, when err is set, the
 // per-cell estimate |sum_k ce[k] f[k]| (ce = h (c_k - c^_k)) over the union of
 // the stage derivatives either sum uses.
@@ -110,12 +119,18 @@ hipError_t launch_fold(hipStream_t s, const cx<double>* spec, int SX, int Kx, in
 // Stage kernels (llg.hip).
 template <typename T>
 hipError_t launch_combine(hipStream_t s, long n, const Combo<T>& c, T* out);
+// Sub-step F with M_k = mk.base + sum of mk.nf terms formed at every read
+// (mk.nf <= MAX_FUSED_TERMS; longer stage rows are combined beforehand) and
+// ex.n == 1.  Forming M_k inside the 7-point stencil re-reads every term at
+// the neighbours, which measured slower than one combine pass on gfx950
+// even for a single term, so stage inputs are always combined first.
+constexpr int MAX_FUSED_TERMS = 0;
 template <typename T>
-hipError_t launch_extrap_rhs(hipStream_t s, const T* Mk, const Extrap<T>& ex, const Phys<T>& ph, T* F);
+hipError_t launch_extrap_rhs(hipStream_t s, const Combo<T>& mk, const Extrap<T>& ex, const Phys<T>& ph, T* F);
 template <typename T>
 hipError_t launch_epoly(hipStream_t s, long n, const EPoly<T>& ep);
 template <typename T>
-hipError_t launch_stage_final(hipStream_t s, const T* Mk, const Extrap<T>& ex, const Phys<T>& ph, const T* M0,
+hipError_t launch_stage_final(hipStream_t s, const Combo<T>& mk, const Extrap<T>& ex, const Phys<T>& ph, const T* M0,
                               const Final<T>& fs, double inv_ms, T* mnew, double* parts);
 template <typename T>
 hipError_t launch_final(hipStream_t s, long ncell, int nb, const T* base, const Final<T>& fs, double inv_ms, T* mnew,

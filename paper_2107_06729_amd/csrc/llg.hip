@@ -131,7 +131,7 @@ template <typename T>
 __device__ __forceinline__ CellIdx cell_index(const Phys<T>& ph) {
     CellIdx c;
     c.x = blockIdx.y * blockDim.x + threadIdx.x;
-    const int row = blockIdx.x * blockDim.y + threadIdx.y;
+    const int row = xcd_run(blockIdx.x, gridDim.x) * blockDim.y + threadIdx.y;
     const int rows = ph.ny * ph.nz;
     c.ok = c.x < ph.nx && row < rows * ph.nb;
     c.b = row / rows;
@@ -143,36 +143,42 @@ __device__ __forceinline__ CellIdx cell_index(const Phys<T>& ph) {
     return c;
 }
 
-template <typename T, int NG>
-__device__ __forceinline__ void stage_rhs(const T* __restrict__ Mk, const Extrap<T>& ex, const Phys<T>& ph,
+template <typename T, int NC>
+__device__ __forceinline__ ComboField<T, NC> combo_field(const Combo<T>& c, long off) {
+    ComboField<T, NC> f;
+    f.base = c.base + off;
+#pragma unroll
+    for (int l = 0; l < NC; ++l) {
+        f.f[l] = c.f[l] + off;
+        f.coef[l] = c.coef[l];
+    }
+    return f;
+}
+
+// F at a sub-step: H_d = g - N00 M_k with g the Eq. (6) field of the stage's
+// time, H_eff and the LLG right-hand side; M_k = M0 + sum of NC terms
+template <typename T, int NC>
+__device__ __forceinline__ void stage_rhs(const Combo<T>& mk, const Extrap<T>& ex, const Phys<T>& ph,
                                           const CellIdx& ci, long N, T m[3], T f[3]) {
-    Mk += ci.off;
-    T g[NG][3];
+    const ComboField<T, NC> M = combo_field<T, NC>(mk, ci.off);
+    T g[3];
 #pragma unroll
-    for (int i = 0; i < NG; ++i)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) g[i][c] = ex.g[i][ci.off + c * N + ci.cell];
+    for (int c = 0; c < 3; ++c) g[c] = ex.g[0][ci.off + c * N + ci.cell];
     T hd[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        T acc = -ph.n00[c] * Mk[c * N + ci.cell];
-#pragma unroll
-        for (int i = 0; i < NG; ++i) acc += ex.w[i] * g[i][c];
-        hd[c] = acc;
-    }
+    for (int c = 0; c < 3; ++c) hd[c] = -ph.n00[c] * M(c * N + ci.cell) + ex.w[0] * g[c];
     T H[3];
-    heff_at(Mk, N, ci.cell, ci.x, ci.y, ci.z, ci.b, ph, hd, m, H);
+    heff_at(M, N, ci.cell, ci.x, ci.y, ci.z, ci.b, ph, hd, m, H);
     llg_at(m, H, ph, f);
 }
 
-template <typename T, int NG>
-__global__ __launch_bounds__(NTS) void k_stage(const T* __restrict__ Mk, Extrap<T> ex, Phys<T> ph,
-                                               T* __restrict__ F) {
+template <typename T, int NC>
+__global__ __launch_bounds__(NTS) void k_stage(Combo<T> mk, Extrap<T> ex, Phys<T> ph, T* __restrict__ F) {
     const long N = (long)ph.nx * ph.ny * ph.nz;
     const CellIdx ci = cell_index(ph);
     if (!ci.ok) return;
     T m[3], f[3];
-    stage_rhs<T, NG>(Mk, ex, ph, ci, N, m, f);
+    stage_rhs<T, NC>(mk, ex, ph, ci, N, m, f);
 #pragma unroll
     for (int c = 0; c < 3; ++c) F[ci.off + c * N + ci.cell] = f[c];
 }
@@ -180,10 +186,10 @@ __global__ __launch_bounds__(NTS) void k_stage(const T* __restrict__ Mk, Extrap<
 // last sub-step fused with Eq. (3): fs lists the stage derivatives used by
 // the update or the estimate; its final entry (index fs.n - 1) is this
 // stage's own F_S, which is taken from registers and never stored
-template <typename T, int NG, int NF>
-__global__ __launch_bounds__(NTS) void k_stage_final(const T* __restrict__ Mk, Extrap<T> ex, Phys<T> ph,
-                                                     const T* __restrict__ M0, Final<T> fs, double inv_ms,
-                                                     T* __restrict__ mnew, double* __restrict__ parts) {
+template <typename T, int NC, int NF>
+__global__ __launch_bounds__(NTS) void k_stage_final(Combo<T> mk, Extrap<T> ex, Phys<T> ph, const T* __restrict__ M0,
+                                                     Final<T> fs, double inv_ms, T* __restrict__ mnew,
+                                                     double* __restrict__ parts) {
     __shared__ double red[NTS];
     const long N = (long)ph.nx * ph.ny * ph.nz;
     const CellIdx ci = cell_index(ph);
@@ -191,7 +197,7 @@ __global__ __launch_bounds__(NTS) void k_stage_final(const T* __restrict__ Mk, E
     double emax = 0.0;
     if (ci.ok) {
         T m[3], fS[3];
-        stage_rhs<T, NG>(Mk, ex, ph, ci, N, m, fS);
+        stage_rhs<T, NC>(mk, ex, ph, ci, N, m, fS);
         T m0[3], f[NF > 1 ? NF - 1 : 1][3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) m0[c] = M0[ci.off + c * N + ci.cell];
@@ -425,31 +431,42 @@ hipError_t launch_epoly(hipStream_t s, long n, const EPoly<T>& ep) {
 }
 
 template <typename T>
-hipError_t launch_extrap_rhs(hipStream_t s, const T* Mk, const Extrap<T>& ex, const Phys<T>& ph, T* F) {
+hipError_t launch_extrap_rhs(hipStream_t s, const Combo<T>& mk, const Extrap<T>& ex, const Phys<T>& ph, T* F) {
     const CellGrid cg = cell_grid(ph.nx, ph.ny, ph.nz, ph.nb);
-    switch (ex.n) {
+    if (ex.n != 1) return hipErrorInvalidValue;
+    switch (mk.nf) {
 #define EX(K) \
-    case K: k_stage<T, K><<<cg.grid, cg.block, 0, s>>>(Mk, ex, ph, F); break;
-        EX(1) EX(2) EX(3) EX(4) EX(5) EX(6)
+    case K: k_stage<T, K><<<cg.grid, cg.block, 0, s>>>(mk, ex, ph, F); break;
+        EX(0)
 #undef EX
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_stage_final(hipStream_t s, const T* Mk, const Extrap<T>& ex, const Phys<T>& ph, const T* M0,
-                              const Final<T>& fs, double inv_ms, T* mnew, double* parts) {
-    const CellGrid cg = cell_grid(ph.nx, ph.ny, ph.nz, ph.nb);
-    if (ex.n != 1) return hipErrorInvalidValue;
+template <typename T, int NC>
+static hipError_t stage_final_nc(hipStream_t s, const CellGrid& cg, const Combo<T>& mk, const Extrap<T>& ex,
+                                 const Phys<T>& ph, const T* M0, const Final<T>& fs, double inv_ms, T* mnew,
+                                 double* parts) {
     switch (fs.n) {
-#define SF(K) \
-    case K: k_stage_final<T, 1, K><<<cg.grid, cg.block, 0, s>>>(Mk, ex, ph, M0, fs, inv_ms, mnew, parts); break;
+#define SF(K)                                                                                                   \
+    case K: k_stage_final<T, NC, K><<<cg.grid, cg.block, 0, s>>>(mk, ex, ph, M0, fs, inv_ms, mnew, parts); break;
         SF(1) SF(2) SF(3) SF(4) SF(5) SF(6) SF(7) SF(8)
 #undef SF
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_stage_final(hipStream_t s, const Combo<T>& mk, const Extrap<T>& ex, const Phys<T>& ph, const T* M0,
+                              const Final<T>& fs, double inv_ms, T* mnew, double* parts) {
+    const CellGrid cg = cell_grid(ph.nx, ph.ny, ph.nz, ph.nb);
+    if (ex.n != 1) return hipErrorInvalidValue;
+    switch (mk.nf) {
+        case 0: return stage_final_nc<T, 0>(s, cg, mk, ex, ph, M0, fs, inv_ms, mnew, parts);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename T>
@@ -496,8 +513,9 @@ hipError_t launch_cast(hipStream_t s, long n, const double* src, T* dst) {
 #define INST(T)                                                                                                  \
     template hipError_t launch_combine<T>(hipStream_t, long, const Combo<T>&, T*);                               \
     template hipError_t launch_epoly<T>(hipStream_t, long, const EPoly<T>&);                                     \
-    template hipError_t launch_extrap_rhs<T>(hipStream_t, const T*, const Extrap<T>&, const Phys<T>&, T*);        \
-    template hipError_t launch_stage_final<T>(hipStream_t, const T*, const Extrap<T>&, const Phys<T>&, const T*,  \
+    template hipError_t launch_extrap_rhs<T>(hipStream_t, const Combo<T>&, const Extrap<T>&, const Phys<T>&, T*); \
+    template hipError_t launch_stage_final<T>(hipStream_t, const Combo<T>&, const Extrap<T>&, const Phys<T>&,     \
+                                              const T*,                                                          \
                                               const Final<T>&, double, T*, double*);                             \
     template hipError_t launch_final<T>(hipStream_t, long, int, const T*, const Final<T>&, double, T*, double*,  \
                                         int);                                                                    \

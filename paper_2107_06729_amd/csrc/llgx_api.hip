@@ -482,9 +482,11 @@ static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
             cb.nf++;
         }
         if (pl.extrap) {
-            {
+            if (cb.nf > MAX_FUSED_TERMS) {
+                // long stage row: form M_k once instead of at every stencil read
                 PROF(LLGX_K_COMBINE);
                 HIPCHK(c, launch_combine<T>(c->stream, 3 * c->ncell * c->nb, cb, (T*)c->Mk));
+                cb = plain<T>(c->Mk);
             }
             Extrap<T> ex{};
             ex.n = 1;
@@ -493,11 +495,11 @@ static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
             ProfScope ps(c, k == tab->S - 1 ? LLGX_K_FINAL : LLGX_K_EXTRAP);
             if (k == tab->S - 1) {
                 add_final(k);  // own derivative, last entry
-                HIPCHK(c, launch_stage_final<T>(c->stream, (const T*)c->Mk, ex, phys<T>(c), (const T*)c->M, fs,
+                HIPCHK(c, launch_stage_final<T>(c->stream, cb, ex, phys<T>(c), (const T*)c->M, fs,
                                                 1.0 / c->p.Ms, (T*)c->Mnew, c->parts));
                 fused_final = true;
             } else {
-                HIPCHK(c, launch_extrap_rhs<T>(c->stream, (const T*)c->Mk, ex, phys<T>(c), (T*)c->F[k]));
+                HIPCHK(c, launch_extrap_rhs<T>(c->stream, cb, ex, phys<T>(c), (T*)c->F[k]));
             }
         } else {
             XinvOut out{nullptr, c->F[k], nullptr};

@@ -8,22 +8,44 @@
 
 namespace llgx {
 
-// M points at the sample's own [3][N] block; b is the sample index (applied field)
+// M at flat index i of the sample's [3][N] block: a plain array ...
 template <typename T>
-__device__ __forceinline__ void heff_at(const T* __restrict__ M, long N, long cell, int x, int y, int z, int b,
+struct PtrField {
+    const T* __restrict__ p;
+    __device__ __forceinline__ T operator()(long i) const { return p[i]; }
+};
+
+// ... or a stage input M_k = M0 + sum_l coef_l F_l (Eq. 4) formed where it is
+// read, so no M_k array is written and read back
+template <typename T, int NC>
+struct ComboField {
+    const T* __restrict__ base;
+    const T* __restrict__ f[NC > 0 ? NC : 1];
+    T coef[NC > 0 ? NC : 1];
+    __device__ __forceinline__ T operator()(long i) const {
+        T v = base[i];
+#pragma unroll
+        for (int l = 0; l < NC; ++l) v += coef[l] * f[l][i];
+        return v;
+    }
+};
+
+// M reads the sample's own [3][N] block; b is the sample index (applied field)
+template <typename T, typename Fld>
+__device__ __forceinline__ void heff_at(const Fld& M, long N, long cell, int x, int y, int z, int b,
                                         const Phys<T>& ph, const T hd[3], T m[3], T H[3]) {
     const T* ha = ph.hab ? ph.hab + 3 * b : ph.ha;
     const long sy = ph.nx, sz = (long)ph.nx * ph.ny;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) m[c] = M[c * N + cell];
+    for (int c = 0; c < 3; ++c) m[c] = M(c * N + cell);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const T* Mc = M + c * N;
+        const long o = c * N + cell;
         const T mc = m[c];
         // Neumann boundary: a missing neighbour is replaced by the cell itself
-        const T xm = x > 0 ? Mc[cell - 1] : mc, xp = x + 1 < ph.nx ? Mc[cell + 1] : mc;
-        const T ym = y > 0 ? Mc[cell - sy] : mc, yp = y + 1 < ph.ny ? Mc[cell + sy] : mc;
-        const T zm = z > 0 ? Mc[cell - sz] : mc, zp = z + 1 < ph.nz ? Mc[cell + sz] : mc;
+        const T xm = x > 0 ? M(o - 1) : mc, xp = x + 1 < ph.nx ? M(o + 1) : mc;
+        const T ym = y > 0 ? M(o - sy) : mc, yp = y + 1 < ph.ny ? M(o + sy) : mc;
+        const T zm = z > 0 ? M(o - sz) : mc, zp = z + 1 < ph.nz ? M(o + sz) : mc;
         H[c] = hd[c] + ha[c] + ph.exx * ((xm + xp) - T(2) * mc) + ph.exy * ((ym + yp) - T(2) * mc) +
                ph.exz * ((zm + zp) - T(2) * mc);
     }
