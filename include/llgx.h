@@ -191,6 +191,37 @@ llgx_status llgx_run(llgx_handle h, const llgx_stepper* s, double t_end, double 
 llgx_status llgx_profile(llgx_handle h, int32_t enable);
 llgx_status llgx_profile_read(llgx_handle h, double ms[LLGX_K_COUNT], int64_t launches[LLGX_K_COUNT]);
 
+/* ---- Launch variants and the autotuner ----------------------------------
+ * Each FFT pass of an exact evaluation (kinds LLGX_K_XFWD .. LLGX_K_XINV
+ * above, indices 0..4 of the arrays below) can be launched in a few variants
+ * -- tile widths and rows per workgroup -- that give bit-identical results
+ * and differ only in speed.  Variant 0 is the default.
+ *
+ * llgx_autotune: times every variant of every pass (reps back-to-back
+ * launches each, between HIP events on the handle's stream), keeps the
+ * fastest, and remembers the choice for the rest of the process under the
+ * key (precision, spectral storage, mesh, sample count), so handles created
+ * later with that key start with it.  us_out (may be NULL) receives the
+ * chosen variants' average microseconds per launch (0 for a pass the mesh
+ * does not need).  Needs llgx_precompute_demag and llgx_set_m (LLGX_E_STATE);
+ * uses only the spectral workspace and the stage scratch array, so the
+ * stepping state is unchanged.  Synchronises.
+ * llgx_time_passes: the same measurement for the current variants only.
+ * llgx_get_variants / llgx_set_variants: read or force the choice
+ * (LLGX_E_ARG for an index out of range).
+ * llgx_tune_export: the process-wide table as JSON lines
+ *   {"key": "f32/native/256x256x16/1", "variant": [v0..v4], "us": [t0..t4]}
+ * with the same size protocol as llgx_save_state (buf NULL: size only,
+ * including the terminating NUL).  llgx_tune_import: adds such lines to the
+ * table (LLGX_E_ARG on a malformed line or a variant out of range; nothing
+ * is added then).  Handles created afterwards pick the imported choices. */
+llgx_status llgx_autotune(llgx_handle h, int32_t reps, double us_out[5]);
+llgx_status llgx_time_passes(llgx_handle h, int32_t reps, double us_out[5]);
+llgx_status llgx_get_variants(llgx_handle h, int32_t v[5]);
+llgx_status llgx_set_variants(llgx_handle h, const int32_t v[5]);
+llgx_status llgx_tune_export(char* buf, size_t cap, size_t* used);
+llgx_status llgx_tune_import(const char* text);
+
 /* ---- Checkpoint / resume ------------------------------------------------
  * The whole stepping state of a handle -- t, the controller's next h, M, the
  * Eq. (6) history (the stage-1 fields of the previous accepted iterations and
@@ -228,6 +259,8 @@ llgx_status llgx_batch_precompute_demag(llgx_batch b);
 llgx_status llgx_batch_set_m(llgx_batch b, int32_t i, const void* M_dev);
 llgx_status llgx_batch_get_m(llgx_batch b, int32_t i, void* M_dev);
 llgx_status llgx_batch_run_fixed(llgx_batch b, const llgx_stepper* s, int64_t nsteps, int32_t use_graph);
+/* Autotune every mesh group of the batch (llgx_autotune on each). */
+llgx_status llgx_batch_autotune(llgx_batch b, int32_t reps);
 llgx_status llgx_batch_info(llgx_batch b, int32_t* ngroups, int64_t* total_cells, double* t);
 
 /* Time, proposed next step and counters of the handle. */

@@ -82,6 +82,13 @@ _sig = {
     "llgx_counters": (_S, [_H, ctypes.POINTER(ctypes.c_int64)]),
     "llgx_save_state": (_S, [_H, _P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
     "llgx_load_state": (_S, [_H, _P, ctypes.c_size_t]),
+    "llgx_autotune": (_S, [_H, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
+    "llgx_time_passes": (_S, [_H, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
+    "llgx_get_variants": (_S, [_H, ctypes.POINTER(ctypes.c_int32)]),
+    "llgx_set_variants": (_S, [_H, ctypes.POINTER(ctypes.c_int32)]),
+    "llgx_tune_export": (_S, [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+    "llgx_tune_import": (_S, [ctypes.c_char_p]),
+    "llgx_batch_autotune": (_S, [_H, ctypes.c_int32]),
     "llgx_batch_create": (_S, [ctypes.c_int32, ctypes.POINTER(Problem), ctypes.c_int32, _P, ctypes.POINTER(_H)]),
     "llgx_batch_destroy": (None, [_H]),
     "llgx_batch_last_error": (ctypes.c_char_p, [_H]),
@@ -301,11 +308,64 @@ class Sim:
         _check(_lib.llgx_save_state(self._h, buf, need.value, ctypes.byref(need)), self._h)
         return buf.raw[:need.value]
 
+    def autotune(self, reps=10):
+        """Time every launch variant of the five FFT passes and keep the
+        fastest (llgx_autotune); returns {pass: microseconds per launch}."""
+        us = (ctypes.c_double * 5)()
+        _check(_lib.llgx_autotune(self._h, int(reps), us), self._h)
+        return dict(zip(KERNELS[:5], list(us)))
+
+    def time_passes(self, reps=20):
+        """Average microseconds per launch of each FFT pass with the current
+        variants, reps back-to-back launches between HIP events."""
+        us = (ctypes.c_double * 5)()
+        _check(_lib.llgx_time_passes(self._h, int(reps), us), self._h)
+        return dict(zip(KERNELS[:5], list(us)))
+
+    def variants(self):
+        v = (ctypes.c_int32 * 5)()
+        _check(_lib.llgx_get_variants(self._h, v), self._h)
+        return list(v)
+
+    def set_variants(self, v):
+        arr = (ctypes.c_int32 * 5)(*[int(x) for x in v])
+        _check(_lib.llgx_set_variants(self._h, arr), self._h)
+
     def load_state(self, blob):
         """Resume from bytes written by save_state (llgx_load_state)."""
         blob = bytes(blob)
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(_lib.llgx_load_state(self._h, buf, len(blob)), self._h)
+
+
+def tune_export():
+    """The process-wide autotuner table as JSON lines (llgx_tune_export)."""
+    need = ctypes.c_size_t()
+    code = _lib.llgx_tune_export(None, 0, ctypes.byref(need))
+    if code != OK:
+        raise LlgxError(code, "llgx_tune_export")
+    buf = ctypes.create_string_buffer(need.value)
+    code = _lib.llgx_tune_export(buf, need.value, ctypes.byref(need))
+    if code != OK:
+        raise LlgxError(code, "llgx_tune_export")
+    return buf.value.decode()
+
+
+def tune_import(text):
+    """Add JSON lines written by tune_export to the table (llgx_tune_import)."""
+    code = _lib.llgx_tune_import(text.encode())
+    if code != OK:
+        raise LlgxError(code, "malformed tuning table")
+
+
+def save_tuning(path):
+    with open(path, "w") as f:
+        f.write(tune_export())
+
+
+def load_tuning(path):
+    with open(path) as f:
+        tune_import(f.read())
 
 
 def _bcheck(code, handle):
@@ -345,6 +405,9 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+    def autotune(self, reps=10):
+        _bcheck(_lib.llgx_batch_autotune(self._h, int(reps)), self._h)
 
     def precompute_demag(self):
         _bcheck(_lib.llgx_batch_precompute_demag(self._h), self._h)

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libllgx.so")
-SOURCES = ["demag.hip", "llg.hip", "llgx_api.hip"]
+SOURCES = ["pass_x.hip", "pass_col.hip", "pass_z.hip", "newell.hip", "llg.hip", "llgx_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -35,6 +35,9 @@ def torch_lib_dir():
 ARCH = "gfx950"
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    # contract a*b+c only inside one expression: every launch variant (and
+    # every template instantiation) of a kernel then rounds identically
+    "-ffp-contract=on",
     # no packed-FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,

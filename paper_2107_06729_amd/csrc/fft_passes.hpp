@@ -1,0 +1,487 @@
+// Kernels of the FFT passes of Eq. (2) (zero-padded FFT convolution, Sec. II)
+// for gfx950; instantiated by pass_x.hip, pass_col.hip and pass_z.hip.
+//
+// Data layout (complex elements, working precision T):
+//   spectrum buffers are [comp][z][y][kx] with row stride SX >= Kx, where
+//   Kx = Px/2 + 1 columns of the real-to-complex x transform (1 if Px = 1).
+// Pass chain of one evaluation (5 kernels; fewer when an axis has length 1):
+//   xfwd  : stage combination M_k = M0 + sum h b F (Eq. 4), real->complex x FFT
+//   colfft: y forward (rows y >= ny are the zero padding, never loaded)
+//   zmul  : z forward, H = -N^ M with the 6-component symmetric k-space
+//           kernel, z inverse (only z < nz rows are loaded and stored)
+//   colfft: y inverse (only y < ny rows stored)
+//   xinv  : complex->real x FFT (x < nx kept) fused with H_eff and the LLG
+//           right-hand side (Eq. 1), or writing H_d / H_eff alone.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels.hpp"
+#include "physics.hpp"
+#include "fft_col.hpp"
+#include "spec_store.hpp"
+#include "tile_io.hpp"
+
+namespace llgx {
+
+constexpr int NT = 256;
+
+// ------------------------------------------------------------------------
+// Tile choices (LDS budget per workgroup).  Every pass has launch variants
+// (tile widths or rows per workgroup) that compute bit-identical results;
+// variant 0 is the default and the autotuner picks among the others by
+// timing them on the problem's own shapes.
+template <typename T>
+constexpr int col_tile(int L, int v) {
+    const int t = sizeof(T) == 4 ? (L <= 512 ? 16 : 8) : (L <= 512 ? 8 : 4);
+    return v == 1 ? (t > 1 ? t / 2 : 1) : t;
+}
+template <typename T>
+constexpr int zmul_tile(int L, int v) {
+    const int t = sizeof(T) == 4 ? (L <= 64 ? 16 : L == 128 ? 8 : L == 256 ? 4 : 2)
+                                 : (L <= 64 ? 8 : L == 128 ? 4 : L == 256 ? 2 : 1);
+    // variant 2 doubles the tile while its spectrum stays within 48 KiB of LDS
+    const bool fits = (long)(L > 1 ? L : 1) * 6 * 2 * t * 2 * (long)sizeof(T) <= 48 * 1024;
+    return v == 1 ? (t > 1 ? t / 2 : 1) : (v == 2 && fits) ? 2 * t : t;
+}
+template <typename T>
+constexpr int xfwd_rows(int LX, int v) {
+    int r = (sizeof(T) == 4 ? 2048 : 1024) / (LX > 0 ? LX : 1);
+    r = r < 1 ? 1 : (r > 16 ? 16 : r);
+    return v == 1 ? (r > 1 ? r / 2 : 1) : r;
+}
+template <typename T>
+constexpr int xinv_rows(int LX, int v) {
+    int r = (sizeof(T) == 4 ? 1024 : 512) / (LX > 0 ? LX : 1);
+    r = r < 1 ? 1 : (r > 8 ? 8 : r);
+    return v == 1 ? (r > 1 ? r / 2 : 1) : r;
+}
+
+#define LLGX_POW2_CASES(M) M(2) M(4) M(8) M(16) M(32) M(64) M(128) M(256) M(512) M(1024) M(2048)
+
+template <typename T>
+__device__ __forceinline__ T combo_at(const Combo<T>& c, long i) {
+    T v = c.base[i];
+    for (int l = 0; l < c.nf; ++l) v += c.coef[l] * c.f[l][i];
+    return v;
+}
+
+// ------------------------------------------------------------------------
+// forward x pass: real rows of length nin (zero padded to 2 LX) -> LX+1 complex
+// A real sequence of length P = 2 LX is packed as z[j] = x[2j] + i x[2j+1],
+// transformed with a length-LX complex FFT and split with
+//   X[k] = (Z[k] + Z*[LX-k])/2 - i e^{-2 pi i k/P} (Z[k] - Z*[LX-k])/2.
+template <typename T, typename S, int LX, int ROWS>
+__global__ __launch_bounds__(NT) void k_xfwd(Combo<T> in, T* __restrict__ mk_out, int nin, long nrows,
+                                             typename Spec<T, S>::elem* __restrict__ spec, int SX,
+                                             const cx<T>* __restrict__ twL, const cx<T>* __restrict__ twP,
+                                             T fscale) {
+    using C = cx<T>;
+    const long row0 = (long)blockIdx.x * ROWS;
+    if constexpr (LX == 0) {
+        for (int r = threadIdx.x; r < ROWS; r += NT) {
+            const long g = row0 + r;
+            if (g < nrows) {
+                const T v = combo_at(in, g);
+                if (mk_out) mk_out[g] = v;
+                spec[g * SX] = Spec<T, S>::put(C{v * fscale, T(0)});
+            }
+        }
+        return;
+    } else {
+        constexpr int CS = LX + 1;
+        constexpr int TOT = ROWS * LX, PER = (TOT + NT - 1) / NT;
+        __shared__ C buf[ROWS * CS];
+        __shared__ C twl[LX];
+        __shared__ C twp[LX + 1];
+        TwStage<T, LX, NT> tw1;
+        TwStage<T, LX + 1, NT> tw2;
+        tw1.fetch(twL);
+        tw2.fetch(twP);
+        // element pair (x[2i], x[2i+1]) of row g; staged: all loads of one
+        // operand are issued before they are used
+        C v[PER];
+        long off[PER];
+        int x0[PER];
+        bool ok[PER];
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int e = threadIdx.x + m * NT;
+            const int r = e / LX, i = e - r * LX;
+            const long g = row0 + r;
+            x0[m] = 2 * i;
+            off[m] = g * nin + 2 * i;
+            ok[m] = (TOT % NT == 0 || e < TOT) && g < nrows && 2 * i < nin;
+        }
+        const bool pairs = (nin & 1) == 0;  // rows start 8/16-byte aligned: load both reals at once
+        auto load2 = [&](const T* __restrict__ p, int m) -> C {
+            C w{T(0), T(0)};
+            if (ok[m]) {
+                if (pairs) {
+                    w = *(const C*)(p + off[m]);
+                } else {
+                    w.x = p[off[m]];
+                    if (x0[m] + 1 < nin) w.y = p[off[m] + 1];
+                }
+            }
+            return w;
+        };
+#pragma unroll
+        for (int m = 0; m < PER; ++m) v[m] = load2(in.base, m);
+        for (int l = 0; l < in.nf; ++l) {
+            C w[PER];
+#pragma unroll
+            for (int m = 0; m < PER; ++m) w[m] = load2(in.f[l], m);
+            const T cf = in.coef[l];
+#pragma unroll
+            for (int m = 0; m < PER; ++m) {
+                v[m].x += cf * w[m].x;
+                v[m].y += cf * w[m].y;
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int e = threadIdx.x + m * NT;
+            if (TOT % NT != 0 && e >= TOT) continue;
+            const int r = e / LX, i = e - r * LX;
+            buf[r * CS + i] = C{v[m].x * fscale, v[m].y * fscale};
+            if (mk_out && ok[m]) {
+                mk_out[off[m]] = v[m].x;
+                if (x0[m] + 1 < nin) mk_out[off[m] + 1] = v[m].y;
+            }
+        }
+        tw1.put(twl);
+        tw2.put(twp);
+        __syncthreads();
+        lds_fft<T, LX, false, Cols<ROWS, CS, 1, false>, NT>(buf, twl);
+        for (int e = threadIdx.x; e < ROWS * (LX + 1); e += NT) {
+            const int r = e / (LX + 1), k = e - r * (LX + 1);
+            const long g = row0 + r;
+            if (g >= nrows) continue;
+            const C zk = buf[r * CS + (k & (LX - 1))];
+            const C zc = cconj(buf[r * CS + ((LX - k) & (LX - 1))]);
+            const C E{(zk.x + zc.x) * T(0.5), (zk.y + zc.y) * T(0.5)};
+            const C O{(zk.y - zc.y) * T(0.5), (zc.x - zk.x) * T(0.5)};  // -i (zk - zc)/2
+            spec[g * SX + k] = Spec<T, S>::put(cadd(E, cmul(O, twp[k])));
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// inverse x pass: LX+1 complex -> real, keep x < nx; then per cell
+//   Z[k] = (X[k] + X*[LX-k]) + i e^{+2 pi i k/P} (X[k] - X*[LX-k]),
+//   z = IDFT_LX(Z), x[2j] = Re z[j], x[2j+1] = Im z[j].
+template <typename T, typename S, int LX, int ROWS, int MODE>
+__global__ __launch_bounds__(NT) void k_xinv(const typename Spec<T, S>::elem* __restrict__ spec, int SX,
+                                             const T* __restrict__ M, Phys<T> ph, XinvOut out,
+                                             const cx<T>* __restrict__ twL, const cx<T>* __restrict__ twP,
+                                             T hscale) {
+    using C = cx<T>;
+    constexpr int LXE = LX > 0 ? LX : 1;
+    constexpr int CS = LXE + 1;
+    __shared__ C buf[3 * ROWS * CS];
+    __shared__ C twl[LXE];
+    const long nrow = (long)ph.ny * ph.nz;
+    const long N = nrow * ph.nx;
+    const long row0 = (long)blockIdx.x * ROWS;
+    const int b = blockIdx.y;  // sample
+    spec += (long)b * 3 * nrow * SX;
+    if (M) M += (long)b * 3 * N;
+    const long vo = (long)b * 3 * N;
+    if constexpr (LX == 0) {
+        for (int lr = threadIdx.x; lr < 3 * ROWS; lr += NT) {
+            const int r = lr / 3, c = lr - 3 * r;
+            const long g = row0 + r;
+            if (g < nrow) buf[lr * CS] = Spec<T, S>::get(spec[(c * nrow + g) * SX]);
+        }
+        __syncthreads();
+    } else {
+        constexpr int TOT = 3 * ROWS * LX, PER = (TOT + NT - 1) / NT;
+        TwStage<T, LX, NT> tw1;
+        tw1.fetch(twL);
+        // post-twiddles of this thread's k (fetched with the spectrum)
+        C wk[PER];
+        C xa[PER], xb[PER];
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int e = threadIdx.x + m * NT;
+            const int lr = e / LX, k = e - lr * LX;
+            const int r = lr / 3, c = lr - 3 * r;
+            const long g = row0 + r;
+            xa[m] = C{T(0), T(0)};
+            xb[m] = C{T(0), T(0)};
+            wk[m] = twP[k];
+            if ((TOT % NT == 0 || e < TOT) && g < nrow) {
+                const typename Spec<T, S>::elem* row = spec + (c * nrow + g) * SX;
+                xa[m] = Spec<T, S>::get(row[k]);
+                xb[m] = Spec<T, S>::get(row[LX - k]);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int e = threadIdx.x + m * NT;
+            if (TOT % NT != 0 && e >= TOT) continue;
+            const int lr = e / LX, k = e - lr * LX;
+            const C xk = xa[m];
+            const C xc = cconj(xb[m]);
+            const C sm = cadd(xk, xc);
+            const C wd = cmulc(csub(xk, xc), wk[m]);
+            buf[lr * CS + k] = C{sm.x - wd.y, sm.y + wd.x};
+        }
+        tw1.put(twl);
+        __syncthreads();
+        lds_fft<T, LX, true, Cols<3 * ROWS, CS, 1, false>, NT>(buf, twl);
+    }
+    const int nx = ph.nx;
+    for (int e = threadIdx.x; e < ROWS * nx; e += NT) {
+        const int r = e / nx, x = e - r * nx;
+        const long g = row0 + r;
+        if (g >= nrow) continue;
+        T hd[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const C v = buf[(3 * r + c) * CS + (LX > 0 ? (x >> 1) : 0)];
+            hd[c] = ((x & 1) ? v.y : v.x) * hscale;
+        }
+        const long cell = g * nx + x;
+        if constexpr (MODE == XINV_DEMAG) {
+            T* H = (T*)out.h + vo;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) H[c * N + cell] = hd[c];
+        } else {
+            const int y = (int)(g % ph.ny), z = (int)(g / ph.ny);
+            T m[3], H[3];
+            heff_at(PtrField<T>{M}, N, cell, x, y, z, b, ph, hd, m, H);
+            if constexpr (MODE == XINV_HEFF) {
+                T* Ho = (T*)out.h + vo;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) Ho[c * N + cell] = H[c];
+            } else {
+                T F[3];
+                llg_at(m, H, ph, F);
+                T* Fo = (T*)out.f + vo;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) Fo[c * N + cell] = F[c];
+                if (out.g) {
+                    T* G = (T*)out.g + vo;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) G[c * N + cell] = hd[c] + ph.n00[c] * m[c];
+                }
+                if (out.h) {
+                    T* Ho = (T*)out.h + vo;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) Ho[c * N + cell] = hd[c];
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// strided column FFT: element (comp, outer, i, kx) at comp*cs + outer*os + i*is + kx
+template <typename T, typename S, int L, bool INV, int TK>
+__global__ __launch_bounds__(NT) void k_colfft(const typename Spec<T, S>::elem* __restrict__ src, long s_cs,
+                                               long s_os, long s_is, int n_in,
+                                               typename Spec<T, S>::elem* __restrict__ dst, long d_cs, long d_os,
+                                               long d_is, int n_out, int Kx, const cx<T>* __restrict__ tw,
+                                               T scale) {
+    using C = cx<T>;
+    using F = ColFFT<T, S, L, INV, TK, 1, NT>;
+    using E = typename Spec<T, S>::elem;
+    const int kx0 = blockIdx.x * TK;
+    const Base1<const E> sp{src + blockIdx.z * s_cs + blockIdx.y * s_os + kx0};
+    const Base1<E> dp{dst + blockIdx.z * d_cs + blockIdx.y * d_os + kx0};
+    typename F::Regs rg;
+    if constexpr (F::NSTAGE == 1) {
+        F::load_first(rg, sp, s_is, n_in, Kx - kx0, 1);
+        F::single(rg, dp, d_is, n_out, Kx - kx0, 1, scale);
+    } else {
+        __shared__ C buf[F::LDS_ELEMS];
+        __shared__ C twl[L];
+        TwStage<T, L, NT> tws;
+        tws.fetch(tw);
+        F::load_first(rg, sp, s_is, n_in, Kx - kx0, 1);
+        tws.put(twl);
+        F::first_to_lds(rg, buf);
+        __syncthreads();
+        F::middle(buf, twl);
+        F::last_to_global(buf, twl, dp, d_is, n_out, Kx - kx0, 1, scale);
+    }
+}
+
+// ------------------------------------------------------------------------
+// z forward, k-space product H^ = K^ M^ (K^ = -N^/(Px Py Pz), real and
+// symmetric, stored for |ky| <= Py/2, |kz| <= Pz/2; the components odd in y
+// (xy, yz) change sign for ky > Py/2, those odd in z (xz, yz) for kz > Pz/2),
+// z inverse.  In place on rows z < nz of the [3][nz][nyrows][SX] buffer.
+// One workgroup takes the rows ky = q and ky = Py - q, which share the folded
+// kernel, so every folded value is read from memory once.  Tile groups
+// g = w * 3 + c: component c of row ky = (w ? Py - q : q).
+//
+template <typename E>
+struct ZBases {
+    E* row0;  // (ky = q, component 0, z = 0, kx0)
+    E* row1;  // (ky = Py - q, ...)
+    long cs;
+    __device__ __forceinline__ E* operator()(int g) const { return (g >= 3 ? row1 : row0) + (g % 3) * cs; }
+};
+
+// folded kernel values of columns kx0 .. kx0+TK-1 of row kyf into LDS
+// kl[(kzf * 6 + comp) * TK + col], times kscale; columns >= ncol read as zero
+template <typename T, int TK, int KZF>
+__device__ __forceinline__ void load_kernel_tile(T* kl, const T* __restrict__ kfold, int kyf, int kx0, int ncol,
+                                                 int SX, T kscale) {
+    constexpr int KB = 16 / (int)sizeof(T);
+    if constexpr (TK % KB == 0) {
+        using V = typename Pack<T>::type;  // 16 bytes = KB values
+        constexpr int NPK = (TK / KB) * KZF * 6, PER = (NPK + NT - 1) / NT;
+        V r[PER];
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int e = threadIdx.x + m * NT;
+            const int b = e / (KZF * 6), rem = e - b * (KZF * 6);
+            r[m] = Pack<T>::zero();
+            if ((NPK % NT == 0 || e < NPK) && b * KB < ncol)
+                r[m] = *(const V*)(kfold + kernel_index<T>(kyf, kx0 + b * KB, rem / 6, rem % 6, SX, KZF));
+        }
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int e = threadIdx.x + m * NT;
+            if (NPK % NT == 0 || e < NPK) {
+                const int b = e / (KZF * 6), rem = e - b * (KZF * 6);
+                const T* v = (const T*)&r[m];
+#pragma unroll
+                for (int i = 0; i < KB; ++i) kl[rem * TK + b * KB + i] = kscale * v[i];
+            }
+        }
+    } else {
+        constexpr int NE = TK * KZF * 6, PER = (NE + NT - 1) / NT;
+        T r[PER];
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int e = threadIdx.x + m * NT;
+            const int col = e % TK, rem = e / TK;
+            r[m] = T(0);
+            if ((NE % NT == 0 || e < NE) && col < ncol)
+                r[m] = kfold[kernel_index<T>(kyf, kx0 + col, rem / 6, rem % 6, SX, KZF)];
+        }
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int e = threadIdx.x + m * NT;
+            if (NE % NT == 0 || e < NE) kl[e] = kscale * r[m];
+        }
+    }
+}
+
+// H = K M on LDS rows: row kz, groups (w, c), TK columns
+template <typename T, int LZ, int TK, int NTH>
+__device__ __forceinline__ void kspace_product(cx<T>* lb, const T* kl, int ng) {
+    using C = cx<T>;
+    constexpr int W = 6 * TK, NU = LZ * 2 * TK, PER = (NU + NTH - 1) / NTH;
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+        const int e = threadIdx.x + m * NTH;
+        const int col = e % TK, t = e / TK, w = t & 1, kz = t >> 1;
+        if ((NU % NTH == 0 || e < NU) && 3 * (w + 1) <= ng) {
+            const int kzf = (2 * kz <= LZ) ? kz : LZ - kz;
+            const T sz = (2 * kz > LZ) ? T(-1) : T(1);
+            const T sy = w ? T(-1) : T(1);
+            const T* kp = kl + kzf * 6 * TK + col;
+            const T nxx = kp[0], nyy = kp[TK], nzz = kp[2 * TK];
+            const T nxy = sy * kp[3 * TK], nxz = sz * kp[4 * TK], nyz = sy * sz * kp[5 * TK];
+            C* p = lb + kz * W + w * 3 * TK + col;
+            const C mx = p[0], my = p[TK], mz = p[2 * TK];
+            p[0] = C{nxx * mx.x + nxy * my.x + nxz * mz.x, nxx * mx.y + nxy * my.y + nxz * mz.y};
+            p[TK] = C{nxy * mx.x + nyy * my.x + nyz * mz.x, nxy * mx.y + nyy * my.y + nyz * mz.y};
+            p[2 * TK] = C{nxz * mx.x + nyz * my.x + nzz * mz.x, nxz * mx.y + nyz * my.y + nzz * mz.y};
+        }
+    }
+}
+
+template <typename T, typename S, int LZ, int TK>
+__global__ __launch_bounds__(NT) void k_zmul(typename Spec<T, S>::elem* __restrict__ buf, int SX, int Kx, int nz,
+                                             int nyrows, int Py, const T* __restrict__ kfold,
+                                             const cx<T>* __restrict__ tw, T kscale) {
+    using C = cx<T>;
+    using E = typename Spec<T, S>::elem;
+    constexpr int L = LZ > 1 ? LZ : 2;  // LZ = 1 uses no transform
+    constexpr int KZF = LZ / 2 + 1;
+    using Ff = ColFFT<T, S, L, false, TK, 6, NT>;
+    using Fi = ColFFT<T, S, L, true, TK, 6, NT>;
+    __shared__ C lb[LZ * 6 * TK];
+    __shared__ T kl[KZF * 6 * TK];
+    __shared__ C twl[L];
+    const int kx0 = blockIdx.x * TK;
+    const int q = blockIdx.y;  // 0 <= q <= Py/2
+    const int ng = (2 * q == Py || q == 0) ? 3 : 6;
+    const int ncol = Kx - kx0;
+    const long cs = (long)nz * nyrows * SX, zs = (long)nyrows * SX;
+    E* sb = buf + (long)blockIdx.z * 3 * cs;  // sample
+    const ZBases<E> bases{sb + (long)q * SX + kx0, sb + (long)(Py - q) * SX + kx0, cs};
+    if constexpr (LZ == 1) {
+        // no z transform: load the 6 x TK values, multiply, store
+        using PU = typename Ff::PU;
+        using RW = typename Ff::RW;
+        constexpr int PN = Ff::PN, NU = 6 * (TK / PN);
+        for (int u = threadIdx.x; u < NU; u += NT) {
+            const int p = u % (TK / PN), g = u / (TK / PN);
+            if (g < ng && p * PN < ncol) {
+                PU v;
+                v.raw = *(const RW*)(bases(g) + p * PN);
+#pragma unroll
+                for (int i = 0; i < PN; ++i) lb[g * TK + p * PN + i] = Spec<T, S>::get(v.e[i]);
+            }
+        }
+        load_kernel_tile<T, TK, KZF>(kl, kfold, q, kx0, ncol, SX, kscale);
+        __syncthreads();
+        kspace_product<T, 1, TK, NT>(lb, kl, ng);
+        __syncthreads();
+        for (int u = threadIdx.x; u < NU; u += NT) {
+            const int p = u % (TK / PN), g = u / (TK / PN);
+            if (g < ng && p * PN < ncol) {
+                PU v;
+#pragma unroll
+                for (int i = 0; i < PN; ++i) v.e[i] = Spec<T, S>::put(lb[g * TK + p * PN + i]);
+                *(RW*)(bases(g) + p * PN) = v.raw;
+            }
+        }
+    } else {
+        TwStage<T, LZ, NT> tws;
+        tws.fetch(tw);
+        typename Ff::Regs rg;
+        Ff::load_first(rg, bases, zs, nz, ncol, ng);
+        load_kernel_tile<T, TK, KZF>(kl, kfold, q, kx0, ncol, SX, kscale);
+        tws.put(twl);
+        Ff::first_to_lds(rg, lb);
+        __syncthreads();
+        if constexpr (Ff::NSTAGE > 1) {
+            Ff::middle(lb, twl);
+            Ff::last_in_lds(lb, twl);
+            __syncthreads();
+        }
+        kspace_product<T, LZ, TK, NT>(lb, kl, ng);
+        __syncthreads();
+        Fi::first_in_lds(lb);
+        if constexpr (Fi::NSTAGE > 1) {
+            Fi::middle(lb, twl);
+            Fi::last_to_global(lb, twl, bases, zs, nz, ncol, ng, T(1));
+        } else {
+            // single-stage lengths: rows z < nz from LDS
+            using PU = typename Ff::PU;
+            using RW = typename Ff::RW;
+            constexpr int PN = Ff::PN, NU = LZ * 6 * (TK / PN);
+            for (int u = threadIdx.x; u < NU; u += NT) {
+                const int p = u % (TK / PN), t = u / (TK / PN), g = t % 6, z = t / 6;
+                if (g < ng && p * PN < ncol && z < nz) {
+                    PU v;
+#pragma unroll
+                    for (int i = 0; i < PN; ++i) v.e[i] = Spec<T, S>::put(lb[z * 6 * TK + g * TK + p * PN + i]);
+                    *(RW*)(bases(g) + z * zs + p * PN) = v.raw;
+                }
+            }
+        }
+    }
+}
+
+}  // namespace llgx

@@ -97,14 +97,14 @@ struct XinvOut {
 using SpecPtr = void*;
 template <typename T, typename S>
 hipError_t launch_xfwd(hipStream_t s, int LX, const Combo<T>& in, T* mk_out, int nin, long nrows, SpecPtr spec,
-                       int SX, const cx<T>* twL, const cx<T>* twP, T fscale);
+                       int SX, const cx<T>* twL, const cx<T>* twP, T fscale, int variant);
 template <typename T, typename S>
 hipError_t launch_xinv(hipStream_t s, int LX, int mode, SpecPtr spec, int SX, const T* M, const Phys<T>& ph,
-                       const XinvOut& out, const cx<T>* twL, const cx<T>* twP, T hscale);
+                       const XinvOut& out, const cx<T>* twL, const cx<T>* twP, T hscale, int variant);
 template <typename T, typename S>
 hipError_t launch_colfft(hipStream_t s, int L, bool inv, SpecPtr src, long s_cs, long s_os, long s_is, int n_in,
                          SpecPtr dst, long d_cs, long d_os, long d_is, int n_out, int Kx, int nouter, int ncomp,
-                         const cx<T>* tw, T scale);
+                         const cx<T>* tw, T scale, int variant);
 template <typename T, typename S>
 hipError_t launch_zmul(hipStream_t s, int LZ, SpecPtr buf, int SX, int Kx, int nz, int nyrows, int Py, int Pz,
                        const T* kfold, int Kyf, int Kzf, const cx<T>* tw, int nb, T kscale, int variant);
@@ -115,6 +115,18 @@ hipError_t launch_scatter_tensor(hipStream_t s, const double* octant, int comp, 
 template <typename T>
 hipError_t launch_fold(hipStream_t s, const cx<double>* spec, int SX, int Kx, int Py, int Pz, int Kyf, int Kzf,
                        double scale, int comp, T* kfold, double* imag_max_parts, int nparts);
+
+// Folded k-space kernel layout: blocks of KB = 16 / sizeof(T) adjacent kx,
+// each block holding all (kz, component) values of one ky, so the z pass
+// reads a tile's kernel values as contiguous 16-byte packs.
+template <typename T>
+__host__ __device__ __forceinline__ long kernel_index(int kyf, int kx, int kzf, int comp, int SX, int Kzf) {
+    constexpr int KB = 16 / (int)sizeof(T);
+    return ((((long)kyf * (SX / KB) + kx / KB) * Kzf + kzf) * 6 + comp) * KB + kx % KB;
+}
+
+// Launch variants per FFT pass (bit-identical results, different tiles).
+constexpr int NVAR_XFWD = 2, NVAR_COL = 2, NVAR_ZMUL = 3, NVAR_XINV = 2;
 
 // Stage kernels (llg.hip).
 template <typename T>

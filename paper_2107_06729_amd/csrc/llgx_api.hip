@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <type_traits>
 #include <string>
 #include <vector>
@@ -52,7 +53,7 @@ struct Ctx {
     int nx = 1, ny = 1, nz = 1;
     long ncell = 1;             // cells per sample
     int nb = 1;                 // samples sharing this mesh (batched launches)
-    int zvar = 0;               // z-pass variant
+    int var[5] = {0, 0, 0, 0, 0};  // launch variant per FFT pass (LLGX_K_XFWD .. LLGX_K_XINV)
     void* hab = nullptr;        // per-sample applied fields [nb][3] (device, working precision)
     int Px = 1, Py = 1, Pz = 1, LX = 0, Kx = 1, SX = 16, Kyf = 1, Kzf = 1;
 
@@ -218,6 +219,14 @@ static Phys<T> phys(const Ctx* c) {
     return ph;
 }
 
+template <typename T>
+static Combo<T> plain(const void* base) {
+    Combo<T> cb{};
+    cb.base = (const T*)base;
+    cb.nf = 0;
+    return cb;
+}
+
 // ---------------------------------------------------------------------------
 // one exact evaluation of Eq. (2) on the stage input `in` (Eq. (4)), ending
 // in the inverse x pass selected by `mode`.  Spectra stored as S; with 16-bit
@@ -225,52 +234,107 @@ static Phys<T> phys(const Ctx* c) {
 // the x pass takes M/(Ms Px), the y pass stores 1/Py of its output, the
 // kernel product carries Px Py (so it applies -N^/Pz), and the field is
 // multiplied by Ms when it is formed.  With S = T every scale is 1.
+template <typename T>
+struct EvalArgs {
+    Combo<T> in;
+    T* mk_out;
+    int mode;
+    const T* Mrhs;
+    XinvOut out;
+};
+
+static bool pass_exists(const Ctx* c, int kind) {
+    return !((kind == LLGX_K_YFWD || kind == LLGX_K_YINV) && c->Py == 1);
+}
+
+// launch one pass (kind LLGX_K_XFWD .. LLGX_K_XINV) with the handle's variant
 template <typename T, typename S>
-static llgx_status eval_exact_s(Ctx* c, const Combo<T>& in, T* mk_out, int mode, const T* Mrhs, const XinvOut& out) {
+static llgx_status run_pass(Ctx* c, int kind, const EvalArgs<T>& a) {
     hipStream_t s = c->stream;
     void* A = c->specA;
+    void* B = c->specB;
     const cx<T>* twL = table<T>(c, c->LX, false);
     const cx<T>* twP = table<T>(c, c->Px, false);
     const bool native = std::is_same<T, S>::value;
-    const T fscale = native ? T(1) : (T)(1.0 / (c->p.Ms * c->Px));
-    const T yscale = native ? T(1) : (T)(1.0 / c->Py);
-    const T kscale = native ? T(1) : (T)((double)c->Px * c->Py);
-    const T hscale = native ? T(1) : (T)c->p.Ms;
-    {
-        PROF(LLGX_K_XFWD);
-        HIPCHK(c, (launch_xfwd<T, S>(s, c->LX, in, mk_out, c->nx, 3L * c->ny * c->nz * c->nb, A, c->SX, twL, twP,
-                                     fscale)));
-    }
-    void* work = A;
-    int nyrows = c->ny;
-    if (c->Py > 1) {
-        void* B = c->specB;
-        const long sa = (long)c->nz * c->ny * c->SX, sb = (long)c->nz * c->Py * c->SX;
-        PROF(LLGX_K_YFWD);
-        HIPCHK(c, (launch_colfft<T, S>(s, c->Py, false, A, sa, (long)c->ny * c->SX, c->SX, c->ny, B, sb,
-                                       (long)c->Py * c->SX, c->SX, c->Py, c->Kx, c->nz, 3 * c->nb,
-                                       table<T>(c, c->Py, false), yscale)));
-        work = B;
-        nyrows = c->Py;
-    }
-    {
-        PROF(LLGX_K_ZMUL);
-        HIPCHK(c, (launch_zmul<T, S>(s, c->Pz, work, c->SX, c->Kx, c->nz, nyrows, c->Py, c->Pz, (const T*)c->kfold,
-                                     c->Kyf, c->Kzf, table<T>(c, c->Pz, false), c->nb, kscale, c->zvar)));
-    }
-    if (c->Py > 1) {
-        void* B = c->specB;
-        const long sa = (long)c->nz * c->ny * c->SX, sb = (long)c->nz * c->Py * c->SX;
-        PROF(LLGX_K_YINV);
-        HIPCHK(c, (launch_colfft<T, S>(s, c->Py, true, B, sb, (long)c->Py * c->SX, c->SX, c->Py, A, sa,
-                                       (long)c->ny * c->SX, c->SX, c->ny, c->Kx, c->nz, 3 * c->nb,
-                                       table<T>(c, c->Py, false), T(1))));
-    }
-    {
-        PROF(LLGX_K_XINV);
-        HIPCHK(c, (launch_xinv<T, S>(s, c->LX, mode, A, c->SX, Mrhs, phys<T>(c), out, twL, twP, hscale)));
+    const long sa = (long)c->nz * c->ny * c->SX, sb = (long)c->nz * c->Py * c->SX;
+    switch (kind) {
+        case LLGX_K_XFWD: {
+            const T fscale = native ? T(1) : (T)(1.0 / (c->p.Ms * c->Px));
+            HIPCHK(c, (launch_xfwd<T, S>(s, c->LX, a.in, a.mk_out, c->nx, 3L * c->ny * c->nz * c->nb, A, c->SX, twL,
+                                         twP, fscale, c->var[kind])));
+            break;
+        }
+        case LLGX_K_YFWD: {
+            const T yscale = native ? T(1) : (T)(1.0 / c->Py);
+            HIPCHK(c, (launch_colfft<T, S>(s, c->Py, false, A, sa, (long)c->ny * c->SX, c->SX, c->ny, B, sb,
+                                           (long)c->Py * c->SX, c->SX, c->Py, c->Kx, c->nz, 3 * c->nb,
+                                           table<T>(c, c->Py, false), yscale, c->var[kind])));
+            break;
+        }
+        case LLGX_K_ZMUL: {
+            const T kscale = native ? T(1) : (T)((double)c->Px * c->Py);
+            void* work = c->Py > 1 ? B : A;
+            const int nyrows = c->Py > 1 ? c->Py : c->ny;
+            HIPCHK(c, (launch_zmul<T, S>(s, c->Pz, work, c->SX, c->Kx, c->nz, nyrows, c->Py, c->Pz,
+                                         (const T*)c->kfold, c->Kyf, c->Kzf, table<T>(c, c->Pz, false), c->nb,
+                                         kscale, c->var[kind])));
+            break;
+        }
+        case LLGX_K_YINV:
+            HIPCHK(c, (launch_colfft<T, S>(s, c->Py, true, B, sb, (long)c->Py * c->SX, c->SX, c->Py, A, sa,
+                                           (long)c->ny * c->SX, c->SX, c->ny, c->Kx, c->nz, 3 * c->nb,
+                                           table<T>(c, c->Py, false), T(1), c->var[kind])));
+            break;
+        case LLGX_K_XINV: {
+            const T hscale = native ? T(1) : (T)c->p.Ms;
+            HIPCHK(c, (launch_xinv<T, S>(s, c->LX, a.mode, A, c->SX, a.Mrhs, phys<T>(c), a.out, twL, twP, hscale,
+                                         c->var[kind])));
+            break;
+        }
+        default:
+            return c->fail(LLGX_E_ARG, "unknown pass %d", kind);
     }
     return LLGX_OK;
+}
+
+template <typename T, typename S>
+static llgx_status eval_exact_s(Ctx* c, const Combo<T>& in, T* mk_out, int mode, const T* Mrhs, const XinvOut& out) {
+    const EvalArgs<T> a{in, mk_out, mode, Mrhs, out};
+    for (int kind = LLGX_K_XFWD; kind <= LLGX_K_XINV; ++kind) {
+        if (!pass_exists(c, kind)) continue;
+        PROF(kind);
+        llgx_status st = run_pass<T, S>(c, kind, a);
+        if (st) return st;
+    }
+    return LLGX_OK;
+}
+
+// Average duration of `reps` back-to-back launches of one pass with
+// variant v, between two HIP events on the handle's stream.  Works on the
+// spectral workspace and the stage-input scratch array only (x pass from M,
+// inverse x pass into M_k), so the stepping state is left as it was.
+template <typename T, typename S>
+static llgx_status time_pass(Ctx* c, int kind, int v, int reps, double* us) {
+    const EvalArgs<T> a{plain<T>(c->M), nullptr, XINV_RHS, (const T*)c->M, XinvOut{nullptr, c->Mk, nullptr}};
+    const int saved = c->var[kind];
+    c->var[kind] = v;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    llgx_status st = LLGX_OK;
+    if (hipEventCreateWithFlags(&e0, hipEventDisableSystemFence) != hipSuccess ||
+        hipEventCreateWithFlags(&e1, hipEventDisableSystemFence) != hipSuccess)
+        st = c->fail(LLGX_E_HIP, "hipEventCreate failed");
+    for (int w = 0; w < 2 && st == LLGX_OK; ++w) st = run_pass<T, S>(c, kind, a);
+    if (st == LLGX_OK && hipEventRecord(e0, c->stream) != hipSuccess) st = c->fail(LLGX_E_HIP, "hipEventRecord failed");
+    for (int r = 0; r < reps && st == LLGX_OK; ++r) st = run_pass<T, S>(c, kind, a);
+    if (st == LLGX_OK && hipEventRecord(e1, c->stream) != hipSuccess) st = c->fail(LLGX_E_HIP, "hipEventRecord failed");
+    float ms = 0.f;
+    if (st == LLGX_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        st = c->fail(LLGX_E_HIP, "event timing failed");
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    c->var[kind] = saved;
+    if (st == LLGX_OK) *us = 1e3 * (double)ms / reps;
+    return st;
 }
 
 template <typename T>
@@ -280,14 +344,6 @@ static llgx_status eval_exact(Ctx* c, const Combo<T>& in, T* mk_out, int mode, c
         if (c->spectral == LLGX_SPEC_F16) return eval_exact_s<float, _Float16>(c, in, mk_out, mode, Mrhs, out);
     }
     return eval_exact_s<T, T>(c, in, mk_out, mode, Mrhs, out);
-}
-
-template <typename T>
-static Combo<T> plain(const void* base) {
-    Combo<T> cb{};
-    cb.base = (const T*)base;
-    cb.nf = 0;
-    return cb;
 }
 
 // ---------------------------------------------------------------------------
@@ -342,15 +398,15 @@ static llgx_status kernel_from_octant_or_real(Ctx* c, const std::vector<double>*
         cx<double>* sp = (cx<double>*)spec;
         HIPCHK(c, (launch_xfwd<double, double>(s, c->LX, plain<double>(real), nullptr, c->Px, (long)c->Pz * c->Py, sp,
                                                c->SX, table<double>(c, c->LX, true), table<double>(c, c->Px, true),
-                                               1.0)));
+                                               1.0, 0)));
         if (c->Py > 1)
             HIPCHK(c, (launch_colfft<double, double>(s, c->Py, false, sp, 0, (long)c->Py * c->SX, c->SX, c->Py, sp, 0,
                                                      (long)c->Py * c->SX, c->SX, c->Py, c->Kx, c->Pz, 1,
-                                                     table<double>(c, c->Py, true), 1.0)));
+                                                     table<double>(c, c->Py, true), 1.0, 0)));
         if (c->Pz > 1)
             HIPCHK(c, (launch_colfft<double, double>(s, c->Pz, false, sp, 0, c->SX, (long)c->Py * c->SX, c->Pz, sp, 0,
                                                      c->SX, (long)c->Py * c->SX, c->Pz, c->Kx, c->Py, 1,
-                                                     table<double>(c, c->Pz, true), 1.0)));
+                                                     table<double>(c, c->Pz, true), 1.0, 0)));
         HIPCHK(c, launch_fold<T>(s, sp, c->SX, c->Kx, c->Py, c->Pz, c->Kyf, c->Kzf, scale, comp, (T*)c->kfold,
                                  c->parts, c->nparts));
     }
@@ -828,6 +884,80 @@ namespace llgx {
 
 // Context for nb samples of one problem (differing only in the applied field,
 // ha_list[nb][3], or all equal to p->Ha when ha_list is null).
+// ---- autotuner ----------------------------------------------------------
+// Each FFT pass has launch variants (tile widths, rows per workgroup) with
+// bit-identical results.  llgx_autotune times every variant of every pass on
+// the handle's own shapes and keeps the fastest; the choice is remembered per
+// (precision, spectral storage, mesh, samples) for the rest of the process
+// and can be exported / imported as JSON lines.
+static const int kNumVar[5] = {NVAR_XFWD, NVAR_COL, NVAR_ZMUL, NVAR_COL, NVAR_XINV};
+
+struct TuneEntry {
+    int var[5];
+    double us[5];
+};
+static std::mutex g_tune_mu;
+static std::map<std::string, TuneEntry> g_tune;
+
+static std::string tune_key(const Ctx* c) {
+    char b[160];
+    snprintf(b, sizeof b, "%s/%s/%dx%dx%d/%d", c->prec == LLGX_F32 ? "f32" : "f64",
+             c->spectral == LLGX_SPEC_BF16 ? "bf16" : c->spectral == LLGX_SPEC_F16 ? "f16" : "native", c->nx, c->ny,
+             c->nz, c->nb);
+    return b;
+}
+
+static void drop_graphs(Ctx* c) {
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+}
+
+static void apply_tuned(Ctx* c) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(c));
+    if (it == g_tune.end()) return;
+    for (int k = 0; k < 5; ++k) c->var[k] = it->second.var[k];
+    drop_graphs(c);
+}
+
+static llgx_status time_pass_any(Ctx* c, int kind, int v, int reps, double* us) {
+    if (c->prec == LLGX_F64) return time_pass<double, double>(c, kind, v, reps, us);
+    if (c->spectral == LLGX_SPEC_BF16) return time_pass<float, __bf16>(c, kind, v, reps, us);
+    if (c->spectral == LLGX_SPEC_F16) return time_pass<float, _Float16>(c, kind, v, reps, us);
+    return time_pass<float, float>(c, kind, v, reps, us);
+}
+
+static llgx_status tune_ctx(Ctx* c, int reps, double us_out[5]) {
+    if (reps < 1) return c->fail(LLGX_E_ARG, "reps must be >= 1");
+    if (!c->have_kernel) return c->fail(LLGX_E_STATE, "demag kernel not computed (llgx_precompute_demag)");
+    if (!c->have_m) return c->fail(LLGX_E_STATE, "magnetization not set (llgx_set_m)");
+    TuneEntry te{};
+    for (int k = 0; k < 5; ++k) {
+        te.var[k] = 0;
+        te.us[k] = 0.0;
+        if (!pass_exists(c, k)) continue;
+        double best = 0.0;
+        for (int v = 0; v < kNumVar[k]; ++v) {
+            double us = 0.0;
+            llgx_status st = time_pass_any(c, k, v, reps, &us);
+            if (st) return st;
+            if (v == 0 || us < best) {
+                best = us;
+                te.var[k] = v;
+            }
+        }
+        te.us[k] = best;
+    }
+    for (int k = 0; k < 5; ++k) {
+        c->var[k] = te.var[k];
+        if (us_out) us_out[k] = te.us[k];
+    }
+    drop_graphs(c);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[tune_key(c)] = te;
+    return LLGX_OK;
+}
+
 static llgx_status create_ctx(const llgx_problem* p, int nb, const double* ha_list, int32_t precision,
                               int32_t spectral, void* hip_stream, Ctx** out, std::string& err) {
     *out = nullptr;
@@ -922,6 +1052,7 @@ static llgx_status create_ctx(const llgx_problem* p, int nb, const double* ha_li
         delete c;
         return st;
     }
+    apply_tuned(c);
     *out = c;
     return LLGX_OK;
 }
@@ -1172,6 +1303,21 @@ llgx_status llgx_batch_run_fixed(llgx_batch b, const llgx_stepper* s, int64_t ns
                                            : batch_run_fixed<double>(bt, s, nsteps, use_graph);
 }
 
+llgx_status llgx_batch_autotune(llgx_batch b, int32_t reps) {
+    if (!b) return LLGX_E_ARG;
+    Batch* bt = (Batch*)b;
+    for (Ctx* g : bt->groups) {
+        llgx_status st = tune_ctx(g, reps, nullptr);
+        if (st) {
+            bt->err = g->err;
+            return st;
+        }
+    }
+    for (auto& kv : bt->graphs) (void)hipGraphExecDestroy(kv.second);
+    bt->graphs.clear();
+    return LLGX_OK;
+}
+
 llgx_status llgx_batch_info(llgx_batch b, int32_t* ngroups, int64_t* total_cells, double* t) {
     if (!b) return LLGX_E_ARG;
     Batch* bt = (Batch*)b;
@@ -1336,6 +1482,97 @@ llgx_status llgx_set_time(llgx_handle h, double t) {
     c->t = t;
     c->hist.clear();
     c->fsal_valid = false;
+    return LLGX_OK;
+}
+
+llgx_status llgx_autotune(llgx_handle h, int32_t reps, double us_out[5]) {
+    if (!h) return LLGX_E_ARG;
+    return tune_ctx((Ctx*)h, reps, us_out);
+}
+
+llgx_status llgx_time_passes(llgx_handle h, int32_t reps, double us_out[5]) {
+    if (!h || !us_out) return LLGX_E_ARG;
+    Ctx* c = (Ctx*)h;
+    if (reps < 1) return c->fail(LLGX_E_ARG, "reps must be >= 1");
+    if (!c->have_kernel) return c->fail(LLGX_E_STATE, "demag kernel not computed (llgx_precompute_demag)");
+    if (!c->have_m) return c->fail(LLGX_E_STATE, "magnetization not set (llgx_set_m)");
+    for (int k = 0; k < 5; ++k) {
+        us_out[k] = 0.0;
+        if (!pass_exists(c, k)) continue;
+        llgx_status st = time_pass_any(c, k, c->var[k], reps, &us_out[k]);
+        if (st) return st;
+    }
+    return LLGX_OK;
+}
+
+llgx_status llgx_get_variants(llgx_handle h, int32_t v[5]) {
+    if (!h || !v) return LLGX_E_ARG;
+    Ctx* c = (Ctx*)h;
+    for (int k = 0; k < 5; ++k) v[k] = c->var[k];
+    return LLGX_OK;
+}
+
+llgx_status llgx_set_variants(llgx_handle h, const int32_t v[5]) {
+    if (!h || !v) return LLGX_E_ARG;
+    Ctx* c = (Ctx*)h;
+    for (int k = 0; k < 5; ++k)
+        if (v[k] < 0 || v[k] >= kNumVar[k]) return c->fail(LLGX_E_ARG, "variant %d of pass %d out of range", v[k], k);
+    for (int k = 0; k < 5; ++k) c->var[k] = v[k];
+    drop_graphs(c);
+    return LLGX_OK;
+}
+
+llgx_status llgx_tune_export(char* buf, size_t cap, size_t* used) {
+    std::string out;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (const auto& kv : g_tune) {
+            char line[512];
+            const TuneEntry& e = kv.second;
+            snprintf(line, sizeof line,
+                     "{\"key\": \"%s\", \"variant\": [%d, %d, %d, %d, %d], \"us\": [%.3f, %.3f, %.3f, %.3f, %.3f]}\n",
+                     kv.first.c_str(), e.var[0], e.var[1], e.var[2], e.var[3], e.var[4], e.us[0], e.us[1], e.us[2],
+                     e.us[3], e.us[4]);
+            out += line;
+        }
+    }
+    if (used) *used = out.size() + 1;
+    if (!buf) return LLGX_OK;
+    if (cap < out.size() + 1) return LLGX_E_ARG;
+    memcpy(buf, out.c_str(), out.size() + 1);
+    return LLGX_OK;
+}
+
+llgx_status llgx_tune_import(const char* text) {
+    if (!text) return LLGX_E_ARG;
+    std::map<std::string, TuneEntry> add;
+    const char* p = text;
+    while (*p) {
+        const char* eol = strchr(p, '\n');
+        std::string line(p, eol ? (size_t)(eol - p) : strlen(p));
+        p = eol ? eol + 1 : p + line.size();
+        if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
+        char key[160] = {0};
+        TuneEntry e{};
+        const size_t kp = line.find("\"key\"");
+        const size_t vp = line.find("\"variant\"");
+        if (kp == std::string::npos || vp == std::string::npos) return LLGX_E_ARG;
+        if (sscanf(line.c_str() + kp, "\"key\" : \"%159[^\"]\"", key) != 1 &&
+            sscanf(line.c_str() + kp, "\"key\": \"%159[^\"]\"", key) != 1)
+            return LLGX_E_ARG;
+        if (sscanf(line.c_str() + vp, "\"variant\": [%d, %d, %d, %d, %d]", &e.var[0], &e.var[1], &e.var[2],
+                   &e.var[3], &e.var[4]) != 5)
+            return LLGX_E_ARG;
+        for (int k = 0; k < 5; ++k)
+            if (e.var[k] < 0 || e.var[k] >= kNumVar[k]) return LLGX_E_ARG;
+        const size_t up = line.find("\"us\"");
+        if (up != std::string::npos)
+            (void)sscanf(line.c_str() + up, "\"us\": [%lf, %lf, %lf, %lf, %lf]", &e.us[0], &e.us[1], &e.us[2],
+                         &e.us[3], &e.us[4]);
+        add[key] = e;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& kv : add) g_tune[kv.first] = kv.second;
     return LLGX_OK;
 }
 
