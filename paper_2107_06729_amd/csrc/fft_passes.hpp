@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "kernels.hpp"
 #include "physics.hpp"
@@ -327,51 +328,60 @@ struct ZBases {
     __device__ __forceinline__ E* operator()(int g) const { return (g >= 3 ? row1 : row0) + (g % 3) * cs; }
 };
 
-// folded kernel values of columns kx0 .. kx0+TK-1 of row kyf into LDS
-// kl[(kzf * 6 + comp) * TK + col], times kscale; columns >= ncol read as zero
+// folded kernel values of columns kx0 .. kx0+TK-1 of row kyf, loaded into
+// registers by load() and written to LDS kl[(kzf * 6 + comp) * TK + col],
+// times kscale, by put(); columns >= ncol read as zero
+template <typename T, int TK, int KZF>
+struct KernelTile {
+    static constexpr int KB = 16 / (int)sizeof(T);
+    static constexpr bool PACKED = TK % KB == 0;
+    using V = typename Pack<T>::type;  // 16 bytes = KB values
+    static constexpr int NPK = (TK / KB) * KZF * 6;  // packs (PACKED)
+    static constexpr int NE = TK * KZF * 6;          // values (not PACKED)
+    static constexpr int PER = PACKED ? (NPK + NT - 1) / NT : (NE + NT - 1) / NT;
+    typename std::conditional<PACKED, V, T>::type r[PER];
+
+    __device__ __forceinline__ void load(const T* __restrict__ kfold, int kyf, int kx0, int ncol, int SX) {
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int e = threadIdx.x + m * NT;
+            if constexpr (PACKED) {
+                const int b = e / (KZF * 6), rem = e - b * (KZF * 6);
+                r[m] = Pack<T>::zero();
+                if ((NPK % NT == 0 || e < NPK) && b * KB < ncol)
+                    r[m] = *(const V*)(kfold + kernel_index<T>(kyf, kx0 + b * KB, rem / 6, rem % 6, SX, KZF));
+            } else {
+                const int col = e % TK, rem = e / TK;
+                r[m] = T(0);
+                if ((NE % NT == 0 || e < NE) && col < ncol)
+                    r[m] = kfold[kernel_index<T>(kyf, kx0 + col, rem / 6, rem % 6, SX, KZF)];
+            }
+        }
+    }
+    __device__ __forceinline__ void put(T* kl, T kscale) const {
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int e = threadIdx.x + m * NT;
+            if constexpr (PACKED) {
+                if (NPK % NT == 0 || e < NPK) {
+                    const int b = e / (KZF * 6), rem = e - b * (KZF * 6);
+                    const T* v = (const T*)&r[m];
+#pragma unroll
+                    for (int i = 0; i < KB; ++i) kl[rem * TK + b * KB + i] = kscale * v[i];
+                }
+            } else {
+                if (NE % NT == 0 || e < NE) kl[e] = kscale * r[m];
+            }
+        }
+    }
+};
+
 template <typename T, int TK, int KZF>
 __device__ __forceinline__ void load_kernel_tile(T* kl, const T* __restrict__ kfold, int kyf, int kx0, int ncol,
                                                  int SX, T kscale) {
-    constexpr int KB = 16 / (int)sizeof(T);
-    if constexpr (TK % KB == 0) {
-        using V = typename Pack<T>::type;  // 16 bytes = KB values
-        constexpr int NPK = (TK / KB) * KZF * 6, PER = (NPK + NT - 1) / NT;
-        V r[PER];
-#pragma unroll
-        for (int m = 0; m < PER; ++m) {
-            const int e = threadIdx.x + m * NT;
-            const int b = e / (KZF * 6), rem = e - b * (KZF * 6);
-            r[m] = Pack<T>::zero();
-            if ((NPK % NT == 0 || e < NPK) && b * KB < ncol)
-                r[m] = *(const V*)(kfold + kernel_index<T>(kyf, kx0 + b * KB, rem / 6, rem % 6, SX, KZF));
-        }
-#pragma unroll
-        for (int m = 0; m < PER; ++m) {
-            const int e = threadIdx.x + m * NT;
-            if (NPK % NT == 0 || e < NPK) {
-                const int b = e / (KZF * 6), rem = e - b * (KZF * 6);
-                const T* v = (const T*)&r[m];
-#pragma unroll
-                for (int i = 0; i < KB; ++i) kl[rem * TK + b * KB + i] = kscale * v[i];
-            }
-        }
-    } else {
-        constexpr int NE = TK * KZF * 6, PER = (NE + NT - 1) / NT;
-        T r[PER];
-#pragma unroll
-        for (int m = 0; m < PER; ++m) {
-            const int e = threadIdx.x + m * NT;
-            const int col = e % TK, rem = e / TK;
-            r[m] = T(0);
-            if ((NE % NT == 0 || e < NE) && col < ncol)
-                r[m] = kfold[kernel_index<T>(kyf, kx0 + col, rem / 6, rem % 6, SX, KZF)];
-        }
-#pragma unroll
-        for (int m = 0; m < PER; ++m) {
-            const int e = threadIdx.x + m * NT;
-            if (NE % NT == 0 || e < NE) kl[e] = kscale * r[m];
-        }
-    }
+    KernelTile<T, TK, KZF> kt;
+    kt.load(kfold, kyf, kx0, ncol, SX);
+    kt.put(kl, kscale);
 }
 
 // H = K M on LDS rows: row kz, groups (w, c), TK columns
