@@ -264,6 +264,12 @@ __global__ __launch_bounds__(NT) void k_xinv(const typename Spec<T, S>::elem* __
                 T* Fo = (T*)out.f + vo;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) Fo[c * N + cell] = F[c];
+                if (out.mnext) {
+                    T* Mn = (T*)out.mnext + vo;
+                    const T cn = (T)out.cnext;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) Mn[c * N + cell] = m[c] + cn * F[c];
+                }
                 if (out.g) {
                     T* G = (T*)out.g + vo;
 #pragma unroll

@@ -84,9 +84,12 @@ struct Phys {
 enum XinvMode { XINV_DEMAG = 0, XINV_HEFF = 1, XINV_RHS = 2 };
 
 struct XinvOut {
-    void* h;     // demag field (XINV_DEMAG) or H_eff (XINV_HEFF), may be null in XINV_RHS
-    void* f;     // dM/dt (XINV_RHS)
-    void* g;     // stored field G = H_d + N00 M of Eq. (6) (optional)
+    void* h;       // demag field (XINV_DEMAG) or H_eff (XINV_HEFF), may be null in XINV_RHS
+    void* f;       // dM/dt (XINV_RHS)
+    void* g;       // stored field G = H_d + N00 M of Eq. (6) (optional)
+    void* mnext;   // XINV_RHS, optional: next stage input M + cnext F (Eq. 4, a stage
+                   // row whose only entry is the stage just formed)
+    double cnext;
 };
 
 // Host-side launchers (demag.hip).  All lengths are powers of two.  Spectra
@@ -131,6 +134,16 @@ constexpr int NVAR_XFWD = 2, NVAR_COL = 2, NVAR_ZMUL = 3, NVAR_XINV = 2;
 // Stage kernels (llg.hip).
 template <typename T>
 hipError_t launch_combine(hipStream_t s, long n, const Combo<T>& c, T* out);
+// Optional second output of a sub-step kernel: the next stage input
+// mnext = m0 + cnext F of Eq. (4) when that stage's row holds only the stage
+// just formed (as in RK4), so no combine pass is needed for it.
+template <typename T>
+struct NextStage {
+    const T* m0;
+    T* mnext;
+    T cnext;
+};
+
 // Sub-step F with M_k = mk.base + sum of mk.nf terms formed at every read
 // (mk.nf <= MAX_FUSED_TERMS; longer stage rows are combined beforehand) and
 // ex.n == 1.  Forming M_k inside the 7-point stencil re-reads every term at
@@ -138,7 +151,8 @@ hipError_t launch_combine(hipStream_t s, long n, const Combo<T>& c, T* out);
 // even for a single term, so stage inputs are always combined first.
 constexpr int MAX_FUSED_TERMS = 0;
 template <typename T>
-hipError_t launch_extrap_rhs(hipStream_t s, const Combo<T>& mk, const Extrap<T>& ex, const Phys<T>& ph, T* F);
+hipError_t launch_extrap_rhs(hipStream_t s, const Combo<T>& mk, const Extrap<T>& ex, const Phys<T>& ph, T* F,
+                             const NextStage<T>& nx);
 template <typename T>
 hipError_t launch_epoly(hipStream_t s, long n, const EPoly<T>& ep);
 template <typename T>

@@ -173,7 +173,8 @@ __device__ __forceinline__ void stage_rhs(const Combo<T>& mk, const Extrap<T>& e
 }
 
 template <typename T, int NC>
-__global__ __launch_bounds__(NTS) void k_stage(Combo<T> mk, Extrap<T> ex, Phys<T> ph, T* __restrict__ F) {
+__global__ __launch_bounds__(NTS) void k_stage(Combo<T> mk, Extrap<T> ex, Phys<T> ph, T* __restrict__ F,
+                                               NextStage<T> nx) {
     const long N = (long)ph.nx * ph.ny * ph.nz;
     const CellIdx ci = cell_index(ph);
     if (!ci.ok) return;
@@ -181,6 +182,13 @@ __global__ __launch_bounds__(NTS) void k_stage(Combo<T> mk, Extrap<T> ex, Phys<T
     stage_rhs<T, NC>(mk, ex, ph, ci, N, m, f);
 #pragma unroll
     for (int c = 0; c < 3; ++c) F[ci.off + c * N + ci.cell] = f[c];
+    if (nx.mnext) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const long i = ci.off + c * N + ci.cell;
+            nx.mnext[i] = nx.m0[i] + nx.cnext * f[c];
+        }
+    }
 }
 
 // last sub-step fused with Eq. (3): fs lists the stage derivatives used by
@@ -431,12 +439,13 @@ hipError_t launch_epoly(hipStream_t s, long n, const EPoly<T>& ep) {
 }
 
 template <typename T>
-hipError_t launch_extrap_rhs(hipStream_t s, const Combo<T>& mk, const Extrap<T>& ex, const Phys<T>& ph, T* F) {
+hipError_t launch_extrap_rhs(hipStream_t s, const Combo<T>& mk, const Extrap<T>& ex, const Phys<T>& ph, T* F,
+                             const NextStage<T>& nx) {
     const CellGrid cg = cell_grid(ph.nx, ph.ny, ph.nz, ph.nb);
     if (ex.n != 1) return hipErrorInvalidValue;
     switch (mk.nf) {
 #define EX(K) \
-    case K: k_stage<T, K><<<cg.grid, cg.block, 0, s>>>(mk, ex, ph, F); break;
+    case K: k_stage<T, K><<<cg.grid, cg.block, 0, s>>>(mk, ex, ph, F, nx); break;
         EX(0)
 #undef EX
         default: return hipErrorInvalidValue;
@@ -513,7 +522,8 @@ hipError_t launch_cast(hipStream_t s, long n, const double* src, T* dst) {
 #define INST(T)                                                                                                  \
     template hipError_t launch_combine<T>(hipStream_t, long, const Combo<T>&, T*);                               \
     template hipError_t launch_epoly<T>(hipStream_t, long, const EPoly<T>&);                                     \
-    template hipError_t launch_extrap_rhs<T>(hipStream_t, const Combo<T>&, const Extrap<T>&, const Phys<T>&, T*); \
+    template hipError_t launch_extrap_rhs<T>(hipStream_t, const Combo<T>&, const Extrap<T>&, const Phys<T>&, T*,   \
+                                             const NextStage<T>&);                                               \
     template hipError_t launch_stage_final<T>(hipStream_t, const Combo<T>&, const Extrap<T>&, const Phys<T>&,     \
                                               const T*,                                                          \
                                               const Final<T>&, double, T*, double*);                             \

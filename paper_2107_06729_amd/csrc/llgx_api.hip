@@ -66,6 +66,7 @@ struct Ctx {
     void* M = nullptr;
     void* Mnew = nullptr;
     void* Mk = nullptr;
+    void* Mk2 = nullptr;        // second stage-input buffer (chained stages ping-pong)
     void* F[MAX_F] = {};
     void* G[MAX_HIST] = {};
     void* E[MAX_F] = {};        // Eq. (6) fields at the distinct sub-step times of a step
@@ -467,8 +468,24 @@ template <typename T>
 static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
     const Tableau* tab = pl.tab;
     const double h = pl.h;
+    // Stage j reads M_j = M0 + h sum_l a_jl F_l (Eq. 4).  When row j holds only
+    // a_j,j-1 (RK4), the kernel that forms F_{j-1} also writes M_j, into one of
+    // two buffers taken in turn (the stencil of stage j-1 still reads M_{j-1}).
+    auto chained = [&](int j) {
+        if (!pl.extrap || j < 1 || j >= tab->S || tab->a[j][j - 1] == 0.0) return false;
+        for (int l = 0; l + 1 < j; ++l)
+            if (tab->a[j][l] != 0.0) return false;
+        return true;
+    };
+    auto mkbuf = [&](int j) { return (j & 1) ? c->Mk : c->Mk2; };
+    std::vector<bool> formed(tab->S, false);
     if (pl.stage1) {
-        XinvOut out{nullptr, c->F[0], pl.p >= 0 ? c->G[pl.slot0] : nullptr};
+        XinvOut out{nullptr, c->F[0], pl.p >= 0 ? c->G[pl.slot0] : nullptr, nullptr, 0.0};
+        if (chained(1)) {
+            out.mnext = mkbuf(1);
+            out.cnext = h * tab->a[1][0];
+            formed[1] = true;
+        }
         llgx_status st = eval_exact<T>(c, plain<T>(c->M), nullptr, XINV_RHS, (const T*)c->M, out);
         if (st) return st;
     }
@@ -538,11 +555,13 @@ static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
             cb.nf++;
         }
         if (pl.extrap) {
-            if (cb.nf > MAX_FUSED_TERMS) {
-                // long stage row: form M_k once instead of at every stencil read
+            if (formed[k]) {
+                cb = plain<T>(mkbuf(k));
+            } else if (cb.nf > MAX_FUSED_TERMS) {
+                // form M_k once instead of at every stencil read
                 PROF(LLGX_K_COMBINE);
-                HIPCHK(c, launch_combine<T>(c->stream, 3 * c->ncell * c->nb, cb, (T*)c->Mk));
-                cb = plain<T>(c->Mk);
+                HIPCHK(c, launch_combine<T>(c->stream, 3 * c->ncell * c->nb, cb, (T*)mkbuf(k)));
+                cb = plain<T>(mkbuf(k));
             }
             Extrap<T> ex{};
             ex.n = 1;
@@ -555,7 +574,12 @@ static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
                                                 1.0 / c->p.Ms, (T*)c->Mnew, c->parts));
                 fused_final = true;
             } else {
-                HIPCHK(c, launch_extrap_rhs<T>(c->stream, cb, ex, phys<T>(c), (T*)c->F[k]));
+                NextStage<T> nx{nullptr, nullptr, T(0)};
+                if (chained(k + 1)) {
+                    nx = NextStage<T>{(const T*)c->M, (T*)mkbuf(k + 1), (T)(h * tab->a[k + 1][k])};
+                    formed[k + 1] = true;
+                }
+                HIPCHK(c, launch_extrap_rhs<T>(c->stream, cb, ex, phys<T>(c), (T*)c->F[k], nx));
             }
         } else {
             XinvOut out{nullptr, c->F[k], nullptr};
@@ -835,7 +859,7 @@ static void release(Ctx* c) {
     for (auto e : c->spare) (void)hipEventDestroy(e);
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
-    void* ptrs[] = {c->kfold, c->specA, c->specB, c->M, c->Mnew, c->Mk, c->parts, c->scal, c->octant, c->hab};
+    void* ptrs[] = {c->kfold, c->specA, c->specB, c->M, c->Mnew, c->Mk, c->Mk2, c->parts, c->scal, c->octant, c->hab};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (int i = 0; i < MAX_F; ++i)
@@ -1015,6 +1039,7 @@ static llgx_status create_ctx(const llgx_problem* p, int nb, const double* ha_li
     A(&c->M, vbytes);
     A(&c->Mnew, vbytes);
     A(&c->Mk, vbytes);
+    A(&c->Mk2, vbytes);
     for (int i = 0; i < MAX_F; ++i) A(&c->F[i], vbytes);
     for (int i = 0; i < MAX_HIST; ++i) A(&c->G[i], vbytes);
     for (int i = 0; i < MAX_F - 1; ++i) A(&c->E[i], vbytes);
