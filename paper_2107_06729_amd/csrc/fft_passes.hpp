@@ -36,7 +36,7 @@ constexpr int NT = 256;
 template <typename T>
 constexpr int col_tile(int L, int v) {
     const int t = sizeof(T) == 4 ? (L <= 512 ? 16 : 8) : (L <= 512 ? 8 : 4);
-    return v == 1 ? (t > 1 ? t / 2 : 1) : t;
+    return v == 1 ? (t > 1 ? t / 2 : 1) : v == 2 ? (t > 3 ? t / 4 : 1) : t;
 }
 template <typename T>
 constexpr int zmul_tile(int L, int v) {
@@ -50,13 +50,16 @@ template <typename T>
 constexpr int xfwd_rows(int LX, int v) {
     int r = (sizeof(T) == 4 ? 2048 : 1024) / (LX > 0 ? LX : 1);
     r = r < 1 ? 1 : (r > 16 ? 16 : r);
-    return v == 1 ? (r > 1 ? r / 2 : 1) : r;
+    // variant 2 doubles the rows while the tile stays within 48 KiB of LDS
+    const bool fits = 2L * r * (LX + 1) * 2 * (long)sizeof(T) <= 48 * 1024;
+    return v == 1 ? (r > 1 ? r / 2 : 1) : (v == 2 && fits) ? 2 * r : r;
 }
 template <typename T>
 constexpr int xinv_rows(int LX, int v) {
     int r = (sizeof(T) == 4 ? 1024 : 512) / (LX > 0 ? LX : 1);
     r = r < 1 ? 1 : (r > 8 ? 8 : r);
-    return v == 1 ? (r > 1 ? r / 2 : 1) : r;
+    const bool fits = 2L * 3 * r * (LX + 1) * 2 * (long)sizeof(T) <= 48 * 1024;
+    return v == 1 ? (r > 1 ? r / 2 : 1) : (v == 2 && fits) ? 2 * r : r;
 }
 
 #define LLGX_POW2_CASES(M) M(2) M(4) M(8) M(16) M(32) M(64) M(128) M(256) M(512) M(1024) M(2048)

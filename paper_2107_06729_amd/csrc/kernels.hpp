@@ -129,7 +129,7 @@ __host__ __device__ __forceinline__ long kernel_index(int kyf, int kx, int kzf, 
 }
 
 // Launch variants per FFT pass (bit-identical results, different tiles).
-constexpr int NVAR_XFWD = 2, NVAR_COL = 2, NVAR_ZMUL = 3, NVAR_XINV = 2;
+constexpr int NVAR_XFWD = 3, NVAR_COL = 3, NVAR_ZMUL = 3, NVAR_XINV = 3;
 
 // Stage kernels (llg.hip).
 template <typename T>

@@ -27,8 +27,11 @@ hipError_t launch_colfft(hipStream_t s, int L, bool inv, SpecPtr src, long s_cs,
         if (variant == 0) {                             \
             constexpr int TK = col_tile<T>(LL, 0);      \
             CF_T(LL, TK)                                \
-        } else {                                        \
+        } else if (variant == 1) {                      \
             constexpr int TK = col_tile<T>(LL, 1);      \
+            CF_T(LL, TK)                                \
+        } else {                                        \
+            constexpr int TK = col_tile<T>(LL, 2);      \
             CF_T(LL, TK)                                \
         }                                               \
         break;                                          \

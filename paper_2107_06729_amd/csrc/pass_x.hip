@@ -18,8 +18,10 @@ hipError_t launch_xfwd(hipStream_t s, int LX, const Combo<T>& in, T* mk_out, int
     case L: {                                      \
         if (variant == 0)                          \
             XF_R(L, (xfwd_rows<T>(L, 0)));         \
-        else                                       \
+        else if (variant == 1)                     \
             XF_R(L, (xfwd_rows<T>(L, 1)));         \
+        else                                       \
+            XF_R(L, (xfwd_rows<T>(L, 2)));         \
         break;                                     \
     }
     switch (LX) {
@@ -57,8 +59,11 @@ hipError_t launch_xinv(hipStream_t s, int LX, int mode, SpecPtr spec, int SX, co
         if (variant == 0) {                            \
             constexpr int R = xinv_rows<T>(L, 0);      \
             XI_MODE(L, R)                              \
-        } else {                                       \
+        } else if (variant == 1) {                     \
             constexpr int R = xinv_rows<T>(L, 1);      \
+            XI_MODE(L, R)                              \
+        } else {                                       \
+            constexpr int R = xinv_rows<T>(L, 2);      \
             XI_MODE(L, R)                              \
         }                                              \
         break;                                         \

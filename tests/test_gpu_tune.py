@@ -12,7 +12,7 @@ from tests.gpu_util import film, log, sim, to_dev, to_host
 pytestmark = pytest.mark.gpu
 
 N, CELL = (40, 36, 6), (5e-9, 5e-9, 3e-9)
-NVAR = (2, 2, 3, 2, 2)
+NVAR = (3, 3, 3, 3, 3)
 
 
 @pytest.mark.parametrize("prec,spectral", [("f32", "native"), ("f64", "native"), ("f32", "bf16"), ("f32", "f16")])
@@ -77,14 +77,14 @@ def test_tune_table_roundtrip():
     text = llgx.tune_export()
     key = "f64/native/20x16x4/1"
     assert key in text
-    forced = '{"key": "f64/native/20x16x4/1", "variant": [1, 1, 2, 0, 1], "us": [1, 1, 1, 1, 1]}\n'
+    forced = '{"key": "f64/native/20x16x4/1", "variant": [1, 2, 2, 0, 1], "us": [1, 1, 1, 1, 1]}\n'
     llgx.tune_import(forced)
-    assert sim(p, "f64").variants() == [1, 1, 2, 0, 1]
+    assert sim(p, "f64").variants() == [1, 2, 2, 0, 1]
     with pytest.raises(llgx.LlgxError):
         llgx.tune_import('{"key": "f64/native/20x16x4/1", "variant": [9, 0, 0, 0, 0]}')
     with pytest.raises(llgx.LlgxError):
         llgx.tune_import('{"variant": [0, 0, 0, 0, 0]}')
-    assert sim(p, "f64").variants() == [1, 1, 2, 0, 1]
+    assert sim(p, "f64").variants() == [1, 2, 2, 0, 1]
     llgx.tune_import(text)
     s.close()
 
