@@ -57,6 +57,12 @@ typedef int32_t llgx_status;
 #define LLGX_HEUN 4   /* adaptive Heun, 2nd propagated, 1st estimate          */
 #define LLGX_RK23 5   /* Bogacki-Shampine, 3rd propagated, 2nd estimate, FSAL */
 #define LLGX_RKF56 6  /* Fehlberg, 5th propagated, 6th estimate, 8 stages     */
+#define LLGX_ABM2 7   /* Adams-Bashforth-Moulton 2nd order PECE (ref. [32]):
+                         variable-step AB2 predictor, trapezoidal corrector,
+                         Milne error estimate; per step one Eq. (6) field at
+                         the predicted state and one exact Eq. (2) at the
+                         corrected state (the next step's start node).
+                         Single handles only (not batches).                 */
 
 #define LLGX_EXTRAP_FULL (-1)    /* exact Eq. (2) at every stage              */
 #define LLGX_EXTRAP_MATCHED (-2) /* Eq. (6) with p = the propagated order n    */
@@ -225,8 +231,10 @@ llgx_status llgx_tune_import(const char* text);
 /* ---- Checkpoint / resume ------------------------------------------------
  * The whole stepping state of a handle -- t, the controller's next h, M, the
  * Eq. (6) history (the stage-1 fields of the previous accepted iterations and
- * their start times), the FSAL stage field when valid, the method and order
- * the history belongs to, and the counters -- as one host byte image, so a
+ * their start times), the FSAL stage field when valid, the ABM2 start
+ * derivative, its stored field and the previous derivative and step, the
+ * method and order the history belongs to, and the counters -- as one host
+ * byte image, so a
  * run resumed from it continues exactly as the uninterrupted run (no new
  * priming iterations, Sec. III).  The image holds arrays in the handle's
  * working precision and fits only a handle of the same mesh, sample count

@@ -35,6 +35,24 @@ Readings of the paper taken here (the GPU library takes the same ones):
 * ``renormalize`` (off by default): rescale every cell to |M| = Ms after each
   accepted iteration.
 
+ABM2 (the 2nd-order Adams-Bashforth-Moulton predictor-corrector of Sec. II,
+ref. [32]), in PECE form with the readings taken here:
+
+* predictor, variable-step AB2 with r = h_n / h_{n-1}:
+  M_p = M_n + h_n ((1 + r/2) F_n - (r/2) F_{n-1}); the first step after a
+  start (no F_{n-1}) uses M_p = M_n + h F_n, i.e. Heun's method;
+* E: F_p = F(t_n + h, M_p) -- with extrapolation this is the Eq. (6) field at
+  t_n + h (nodes: the current and p previous iteration starts);
+* corrector, trapezoidal (AM2): M_{n+1} = M_n + (h/2)(F_n + F_p);
+* E: F_{n+1} = F(t_{n+1}, M_{n+1}) with exact Eq. (2): the one exact
+  evaluation per iteration, whose stored field G and time are the next
+  iteration's start node; it is evaluated after acceptance (and after
+  renormalisation), so a rejected attempt costs one evaluation;
+* error (Milne): the corrector's local error, -h^3/12 times the third time
+  derivative of M, is estimated as r/(3(r+1)) |M_{n+1} - M_p| per cell, max
+  over cells, / Ms; Heun's estimate |M_{n+1} - M_p| on the starting step;
+  Eq. (5) exponent 1/3 (q = 2).
+
 Pins (tests/test_oracle_integrate.py, test_oracle_extrap.py): convergence
 order of every tableau on the closed-form damped precession; extrapolation
 exact on polynomials of degree <= p for either sign reading; the single-cell
@@ -96,6 +114,26 @@ def controller_step(h, c, h_min=H_MIN, h_max=H_MAX):
     return min(max(h * c, h_min), h_max)
 
 
+def ab2_predict(M0, F0, Fprev, h, h_prev):
+    """Variable-step AB2 predictor (Heun's Euler predictor without F_{n-1})."""
+    if Fprev is None:
+        return M0 + h * F0
+    r = h / h_prev
+    return M0 + h * ((1.0 + 0.5 * r) * F0 - (0.5 * r) * Fprev)
+
+
+def am2_correct(M0, F0, Fp, h):
+    """Trapezoidal (AM2) corrector."""
+    return M0 + (0.5 * h) * (F0 + Fp)
+
+
+def milne_factor(r):
+    """Local error of the AM2 corrector over (corrector - AB2 predictor) for
+    the step ratio r = h_n / h_{n-1}, on solutions with constant third
+    derivative."""
+    return r / (3.0 * (r + 1.0))
+
+
 class Integrator:
     """State (t, M, h, history) and one-iteration stepping for a problem dict.
 
@@ -107,19 +145,27 @@ class Integrator:
                  h_min=H_MIN, h_max=H_MAX, c_min=C_MIN, c_max=C_MAX, e_max=E_MAX,
                  renormalize=False, exponent="min", Nfull=None, demag_fn=None):
         self.pa = _fields.problem_arrays(problem)
-        self.tab = TABLEAUX[method]
-        if extrap == "matched":
-            extrap = self.tab.order
+        self.multistep = method == "ABM2"
+        if self.multistep:
+            self.tab = None
+            if extrap == "matched":
+                extrap = 2
+            self.adaptive = True if adaptive is None else bool(adaptive)
+            self.q = 2
+        else:
+            self.tab = TABLEAUX[method]
+            if extrap == "matched":
+                extrap = self.tab.order
+            self.adaptive = self.tab.adaptive if adaptive is None else bool(adaptive)
+            if self.adaptive and not self.tab.adaptive:
+                raise ValueError("method has no embedded estimate")
+            if exponent == "min":
+                self.q = min(self.tab.order, self.tab.order_hat) if self.tab.adaptive else self.tab.order
+            else:
+                self.q = self.tab.order
         self.p = extrap
-        self.adaptive = self.tab.adaptive if adaptive is None else bool(adaptive)
-        if self.adaptive and not self.tab.adaptive:
-            raise ValueError("method has no embedded estimate")
         self.h_min, self.h_max, self.c_min, self.c_max, self.e_max = h_min, h_max, c_min, c_max, e_max
         self.renormalize = renormalize
-        if exponent == "min":
-            self.q = min(self.tab.order, self.tab.order_hat) if self.tab.adaptive else self.tab.order
-        else:
-            self.q = self.tab.order
         n = self.pa["n"]
         if Nfull is None:
             from . import newell
@@ -135,10 +181,14 @@ class Integrator:
         self.hist = []        # previous accepted (t_i, G_i), oldest first, at most p
         self.fsal_F = None
         self.stats = dict(exact=0, extrap=0, accepted=0, rejected=0, forced=0)
-        self.a = [[float(v) for v in row] for row in self.tab.a]
-        self.b = [float(v) for v in self.tab.b]
-        self.c = [float(v) for v in self.tab.c]
-        self.db = None if self.tab.bhat is None else [float(x - y) for x, y in zip(self.tab.b, self.tab.bhat)]
+        # ABM2 state: F_n and its stored field G_n at (t, M), F_{n-1} and h_{n-1}
+        self.abm_F = self.abm_G = self.abm_Fprev = None
+        self.abm_hprev = None
+        if not self.multistep:
+            self.a = [[float(v) for v in row] for row in self.tab.a]
+            self.b = [float(v) for v in self.tab.b]
+            self.c = [float(v) for v in self.tab.c]
+            self.db = None if self.tab.bhat is None else [float(x - y) for x, y in zip(self.tab.b, self.tab.bhat)]
 
     # --- field evaluations -------------------------------------------------
     def demag(self, M):
@@ -156,11 +206,15 @@ class Integrator:
         self.M = np.array(M, dtype=np.float64)
         self.hist = []
         self.fsal_F = None
+        self.abm_F = self.abm_G = self.abm_Fprev = None
+        self.abm_hprev = None
 
     # --- one accepted iteration -------------------------------------------
     def step(self, h=None):
         if h is not None:
             self.h = float(h)
+        if self.multistep:
+            return self._step_abm()
         tab, p = self.tab, self.p
         M0, t0 = self.M, self.t
         use_extrap = p is not None and len(self.hist) == p
@@ -233,6 +287,68 @@ class Integrator:
         self.M = Mnew
         self.t = t0 + h
         self.h = h_next
+        self.stats["accepted"] += 1
+        self.stats["rejected"] += rejected
+        self.stats["forced"] += int(forced)
+        return dict(t=self.t, h_used=h, h_next=h_next, err=err, rejected=rejected, forced=forced)
+
+    def _exact_start(self, M):
+        Hd = self.demag(M)
+        self.stats["exact"] += 1
+        F = self.rhs(M, Hd)
+        G = stored_field(Hd, M, self.N00) if self.p is not None else None
+        return F, G
+
+    def _step_abm(self):
+        p = self.p
+        M0, t0 = self.M, self.t
+        if self.abm_F is None:
+            self.abm_F, self.abm_G = self._exact_start(M0)
+        F0, G0 = self.abm_F, self.abm_G
+        use_extrap = p is not None and len(self.hist) == p
+        h = self.h
+        if self.adaptive:
+            h = min(max(h, self.h_min), self.h_max)
+        rejected = 0
+        forced = False
+        while True:
+            Mp = ab2_predict(M0, F0, self.abm_Fprev, h, self.abm_hprev)
+            if use_extrap:
+                nodes = [ti - t0 for ti, _ in self.hist] + [0.0]
+                Gs = [g for _, g in self.hist] + [G0]
+                Hd = extrapolated_field(nodes, Gs, h, Mp, self.N00)
+                self.stats["extrap"] += 1
+            else:
+                Hd = self.demag(Mp)
+                self.stats["exact"] += 1
+            Fp = self.rhs(Mp, Hd)
+            Mc = am2_correct(M0, F0, Fp, h)
+            D = Mc - Mp
+            fac = 1.0 if self.abm_Fprev is None else milne_factor(h / self.abm_hprev)
+            err = fac * float(np.max(np.sqrt(np.sum(D * D, axis=0)))) / self.pa["Ms"]
+            if self.adaptive:
+                c = controller_factor(err, self.e_max, self.q, self.c_min, self.c_max)
+                if err > self.e_max:
+                    if h > self.h_min:
+                        rejected += 1
+                        h = controller_step(h, c, self.h_min, self.h_max)
+                        continue
+                    forced = True
+                h_next = controller_step(h, c, self.h_min, self.h_max)
+            else:
+                h_next = h
+            break
+        if p is not None and p > 0:
+            self.hist.append((t0, G0))
+            self.hist = self.hist[-p:]
+        if self.renormalize:
+            nrm = np.sqrt(np.sum(Mc * Mc, axis=0))
+            Mc = Mc * (self.pa["Ms"] / nrm)[None]
+        self.abm_Fprev, self.abm_hprev = F0, h
+        self.M = Mc
+        self.t = t0 + h
+        self.h = h_next
+        self.abm_F, self.abm_G = self._exact_start(Mc)
         self.stats["accepted"] += 1
         self.stats["rejected"] += rejected
         self.stats["forced"] += int(forced)

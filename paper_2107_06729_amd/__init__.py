@@ -28,7 +28,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK, E_ARG, E_STATE, E_HIP, E_NONFINITE, E_OOM, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 F64, F32 = 0, 1
 SPEC_NATIVE, SPEC_BF16, SPEC_F16 = 0, 1, 2
-METHODS = {"RK4": 0, "RKF45": 1, "RKCK45": 2, "RKDP54": 3, "HEUN": 4, "RK23": 5, "RKF56": 6}
+METHODS = {"RK4": 0, "RKF45": 1, "RKCK45": 2, "RKDP54": 3, "HEUN": 4, "RK23": 5, "RKF56": 6, "ABM2": 7}
 EXTRAP_FULL, EXTRAP_MATCHED = -1, -2
 
 

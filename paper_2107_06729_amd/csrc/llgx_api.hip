@@ -87,6 +87,11 @@ struct Ctx {
     };
     std::vector<Hist> hist;  // previous accepted iterations, oldest first
     bool fsal_valid = false;
+    // ABM2: F_n (in F[0]) and its stored field (slot abm_slot) at (t, M);
+    // F_{n-1} (in F[2]) and h_{n-1}
+    bool abm_have_f = false, abm_have_prev = false;
+    double abm_hprev = 0.0;
+    int abm_slot = 0;
     int cur_method = -1, cur_p = -100;
     long long n_exact = 0, n_extrap = 0, n_acc = 0, n_rej = 0, n_forced = 0;
 
@@ -642,11 +647,175 @@ static llgx_status check_stepper(Ctx* c, const llgx_stepper* s, const Tableau** 
     if (s->method != c->cur_method || *p != c->cur_p) {
         c->hist.clear();
         c->fsal_valid = false;
+        c->abm_have_f = c->abm_have_prev = false;
         c->cur_method = s->method;
         c->cur_p = *p;
         c->h_next = 0.0;
     }
     if (s->renormalize) c->fsal_valid = false;
+    return LLGX_OK;
+}
+
+// One accepted ABM2 step (PECE, ref. [32]):
+//   P: M_p = M_n + h ((1 + r/2) F_n - (r/2) F_{n-1}), r = h / h_{n-1}
+//      (M_n + h F_n, Heun's predictor, when no F_{n-1} is held)
+//   E: F_p at (t_n + h, M_p), by Eq. (6) once the history is primed
+//   C: M_{n+1} = M_n + (h/2)(F_n + F_p)
+//   E: F_{n+1} at (t_{n+1}, M_{n+1}) with exact Eq. (2), after acceptance
+// e = k(r) max |M_{n+1} - M_p| / Ms with the Milne factor k = r / (3 (r + 1))
+// (1 on the starting Heun step).  The exact evaluation's stored field is the
+// next iteration's start node of Eq. (6).
+template <typename T>
+static llgx_status do_step_abm(Ctx* c, const llgx_stepper* s, int p, llgx_step_info* info) {
+    const long long ex0 = c->n_exact, xt0 = c->n_extrap;
+    if (!c->abm_have_f) {
+        const int slot = free_slot(c);
+        XinvOut out{nullptr, c->F[0], p >= 0 ? c->G[slot] : nullptr, nullptr, 0.0};
+        llgx_status st = eval_exact<T>(c, plain<T>(c->M), nullptr, XINV_RHS, (const T*)c->M, out);
+        if (st) return st;
+        c->abm_slot = slot;
+        c->abm_have_f = true;
+        c->n_exact++;
+    }
+    const bool extrap = p >= 0 && (int)c->hist.size() == p;
+    double h = s->h;
+    if (s->adaptive) {
+        if (c->h_next > 0) h = c->h_next;
+        h = std::min(std::max(h, s->h_min), s->h_max);
+    }
+    int rejected = 0;
+    bool forced = false;
+    double err = -1.0, h_next = h;
+    for (;;) {
+        const bool prev = c->abm_have_prev;
+        const double r = prev ? h / c->abm_hprev : 0.0;
+        Combo<T> pr{};
+        pr.base = (const T*)c->M;
+        pr.f[0] = (const T*)c->F[0];
+        pr.coef[0] = (T)(prev ? h * (1.0 + 0.5 * r) : h);
+        pr.nf = 1;
+        if (prev) {
+            pr.f[1] = (const T*)c->F[2];
+            pr.coef[1] = (T)(-0.5 * h * r);
+            pr.nf = 2;
+        }
+        {
+            PROF(LLGX_K_COMBINE);
+            HIPCHK(c, launch_combine<T>(c->stream, 3 * c->ncell * c->nb, pr, (T*)c->Mk));
+        }
+        if (extrap) {
+            Extrap<T> ex{};
+            ex.n = 1;
+            ex.w[0] = T(1);
+            if (p == 0) {
+                ex.g[0] = (const T*)c->G[c->abm_slot];
+            } else {
+                std::vector<double> nodes;
+                EPoly<T> ep{};
+                ep.ng = p + 1;
+                ep.nd = 1;
+                for (int i = 0; i < p; ++i) {
+                    nodes.push_back(c->hist[i].t - c->t);
+                    ep.g[i] = (const T*)c->G[c->hist[i].slot];
+                }
+                nodes.push_back(0.0);
+                ep.g[p] = (const T*)c->G[c->abm_slot];
+                const std::vector<double> w = lagrange(nodes, h);
+                for (int i = 0; i <= p; ++i) ep.w[0][i] = (T)w[i];
+                ep.out[0] = (T*)c->E[0];
+                {
+                    PROF(LLGX_K_EPOLY);
+                    HIPCHK(c, launch_epoly<T>(c->stream, 3 * c->ncell * c->nb, ep));
+                }
+                ex.g[0] = (const T*)c->E[0];
+            }
+            PROF(LLGX_K_EXTRAP);
+            HIPCHK(c, launch_extrap_rhs<T>(c->stream, plain<T>(c->Mk), ex, phys<T>(c), (T*)c->F[1],
+                                           NextStage<T>{nullptr, nullptr, T(0)}));
+            c->n_extrap++;
+        } else {
+            XinvOut out{nullptr, c->F[1], nullptr, nullptr, 0.0};
+            llgx_status st = eval_exact<T>(c, plain<T>(c->Mk), nullptr, XINV_RHS, (const T*)c->Mk, out);
+            if (st) return st;
+            c->n_exact++;
+        }
+        // corrector and M_{n+1} - M_p = h (-(1+r)/2 F_n + F_p/2 + (r/2) F_{n-1})
+        Final<T> fs{};
+        fs.err = s->adaptive ? 1 : 0;
+        const double k = prev ? r / (3.0 * (r + 1.0)) : 1.0;
+        fs.f[0] = (const T*)c->F[0];
+        fs.cb[0] = (T)(0.5 * h);
+        fs.ce[0] = k * h * (prev ? -0.5 * (1.0 + r) : -0.5);
+        fs.f[1] = (const T*)c->F[1];
+        fs.cb[1] = (T)(0.5 * h);
+        fs.ce[1] = k * h * 0.5;
+        fs.n = 2;
+        if (prev) {
+            fs.f[2] = (const T*)c->F[2];
+            fs.cb[2] = T(0);
+            fs.ce[2] = k * h * 0.5 * r;
+            fs.n = 3;
+        }
+        {
+            PROF(LLGX_K_FINAL);
+            HIPCHK(c, launch_final<T>(c->stream, c->ncell, c->nb, (const T*)c->M, fs, 1.0 / c->p.Ms, (T*)c->Mnew,
+                                      c->parts, c->nparts));
+        }
+        if (!s->adaptive) break;
+        {
+            PROF(LLGX_K_OTHER);
+            HIPCHK(c, launch_reduce_max(c->stream, c->parts, c->nparts, c->scal));
+        }
+        HIPCHK(c, hipMemcpyAsync(&err, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (!std::isfinite(err)) return c->fail(LLGX_E_NONFINITE, "non-finite error estimate at t=%g", c->t);
+        const double cf =
+            err <= 0.0 ? s->c_max : std::min(std::max(std::pow(0.8 * s->e_max / err, 1.0 / 3.0), s->c_min), s->c_max);
+        if (err > s->e_max) {
+            if (h > s->h_min) {
+                rejected++;
+                h = std::min(std::max(h * cf, s->h_min), s->h_max);
+                continue;
+            }
+            forced = true;
+        }
+        h_next = std::min(std::max(h * cf, s->h_min), s->h_max);
+        break;
+    }
+    // accept
+    if (p > 0) {
+        c->hist.push_back({c->t, c->abm_slot});
+        while ((int)c->hist.size() > p) c->hist.erase(c->hist.begin());
+    }
+    std::swap(c->M, c->Mnew);
+    c->t += h;
+    c->n_acc++;
+    if (s->renormalize) {
+        PROF(LLGX_K_OTHER);
+        HIPCHK(c, launch_renorm<T>(c->stream, c->ncell, c->nb, (T*)c->M, c->p.Ms));
+    }
+    std::swap(c->F[2], c->F[0]);
+    c->abm_hprev = h;
+    c->abm_have_prev = true;
+    const int slot = free_slot(c);
+    XinvOut out{nullptr, c->F[0], p >= 0 ? c->G[slot] : nullptr, nullptr, 0.0};
+    llgx_status st = eval_exact<T>(c, plain<T>(c->M), nullptr, XINV_RHS, (const T*)c->M, out);
+    if (st) return st;
+    c->abm_slot = slot;
+    c->n_exact++;
+    c->h_next = s->adaptive ? h_next : h;
+    c->n_rej += rejected;
+    c->n_forced += forced;
+    if (info) {
+        info->t = c->t;
+        info->h_used = h;
+        info->h_next = c->h_next;
+        info->err = err;
+        info->rejected = rejected;
+        info->exact_evals = (int)(c->n_exact - ex0);
+        info->extrap_evals = (int)(c->n_extrap - xt0);
+        info->forced = forced;
+    }
     return LLGX_OK;
 }
 
@@ -656,6 +825,7 @@ static llgx_status do_step(Ctx* c, const llgx_stepper* s, llgx_step_info* info) 
     int p;
     llgx_status st = check_stepper(c, s, &tab, &p);
     if (st) return st;
+    if (tab->multistep) return do_step_abm<T>(c, s, p, info);
     Plan pl{};
     pl.tab = tab;
     pl.p = p;
@@ -732,8 +902,8 @@ static llgx_status do_run_fixed(Ctx* c, const llgx_stepper* s, int64_t nsteps, i
         int p;
         llgx_status st = check_stepper(c, s, &tab, &p);
         if (st) return st;
-        const bool steady = (p < 0 && !tab->fsal) || (p >= 0 && (int)c->hist.size() == p) ||
-                            (p < 0 && tab->fsal && s->renormalize);
+        const bool steady = !tab->multistep && ((p < 0 && !tab->fsal) || (p >= 0 && (int)c->hist.size() == p) ||
+                                                (p < 0 && tab->fsal && s->renormalize));
         // the legacy default stream cannot be captured: replay needs a created stream
         if (!use_graph || !steady || c->stream == nullptr || c->prof) {
             st = do_step<T>(c, s, info);
@@ -1104,6 +1274,10 @@ static llgx_status batch_run_fixed(Batch* bt, const llgx_stepper* s, int64_t nst
         bt->err = "batched runs take a fixed step (adaptive = 0)";
         return LLGX_E_ARG;
     }
+    if (tableau_for(s->method) && tableau_for(s->method)->multistep) {
+        bt->err = "ABM2 is stepped per handle, not in batches";
+        return LLGX_E_UNSUPPORTED;
+    }
     for (int64_t i = 0; i < nsteps; ++i) {
         bool steady = use_graph && bt->stream != nullptr;
         std::vector<Plan> plans(bt->groups.size());
@@ -1299,6 +1473,7 @@ static llgx_status batch_copy(llgx_batch b, int32_t i, const void* src, void* ds
         e = hipMemcpyAsync(base, src, bytes, hipMemcpyDeviceToDevice, c->stream);
         c->hist.clear();  // the group's Eq. (6) history no longer matches its state
         c->fsal_valid = false;
+        c->abm_have_f = c->abm_have_prev = false;
         c->have_m = true;
     } else {
         e = hipMemcpyAsync(dst_or_null, base, bytes, hipMemcpyDeviceToDevice, c->stream);
@@ -1382,6 +1557,7 @@ llgx_status llgx_set_demag_tensor(llgx_handle h, const double* N_host) {
     for (int i = 0; i < 3; ++i) c->n00[i] = full[i * cs + o];
     c->hist.clear();
     c->fsal_valid = false;
+    c->abm_have_f = c->abm_have_prev = false;
     return c->prec == LLGX_F32 ? kernel_from_octant_or_real<float>(c, &full)
                                : kernel_from_octant_or_real<double>(c, &full);
 }
@@ -1412,6 +1588,7 @@ llgx_status llgx_set_m(llgx_handle h, const void* M_dev) {
     c->have_m = true;
     c->hist.clear();
     c->fsal_valid = false;
+    c->abm_have_f = c->abm_have_prev = false;
     return LLGX_OK;
 }
 
@@ -1507,6 +1684,7 @@ llgx_status llgx_set_time(llgx_handle h, double t) {
     c->t = t;
     c->hist.clear();
     c->fsal_valid = false;
+    c->abm_have_f = c->abm_have_prev = false;
     return LLGX_OK;
 }
 
@@ -1602,34 +1780,30 @@ llgx_status llgx_tune_import(const char* text) {
 }
 
 // ---- checkpoint ---------------------------------------------------------
-// Host image: header, then M, then the history fields oldest first, then the
-// FSAL stage-1 field when it is valid.  All arrays in the working precision.
+// Host image: header, then M, then the history fields oldest first, then
+// (when held) the start derivative F_n (FSAL stage or ABM2), the stored field
+// of the current ABM2 start and the ABM2 derivative F_{n-1}.  All arrays in
+// the working precision.
 struct CkptHeader {
     char magic[8];
     int32_t version, prec, nx, ny, nz, nb;
     int32_t method, p, nhist, fsal_valid;
-    double t, h_next;
+    int32_t abm_have_f, abm_have_g, abm_have_prev, pad;
+    double t, h_next, abm_hprev;
     double hist_t[MAX_HIST];
     int64_t counters[5];
 };
-static const char kCkptMagic[8] = {'L', 'L', 'G', 'X', 'C', 'K', 'P', '1'};
+static const char kCkptMagic[8] = {'L', 'L', 'G', 'X', 'C', 'K', 'P', '2'};
 
-static size_t ckpt_size(const Ctx* c) {
-    const size_t vec = 3 * (size_t)c->ncell * c->nb * c->tsz;
-    return sizeof(CkptHeader) + vec * (1 + c->hist.size() + (c->fsal_valid ? 1 : 0));
+static size_t ckpt_arrays(const CkptHeader& hd) {
+    return 1 + (size_t)hd.nhist + (size_t)(hd.fsal_valid || hd.abm_have_f) + (size_t)hd.abm_have_g +
+           (size_t)hd.abm_have_prev;
 }
 
-llgx_status llgx_save_state(llgx_handle h, void* host_buf, size_t cap, size_t* used) {
-    if (!h) return LLGX_E_ARG;
-    Ctx* c = (Ctx*)h;
-    if (!c->have_m) return c->fail(LLGX_E_STATE, "magnetization not set");
-    const size_t need = ckpt_size(c);
-    if (used) *used = need;
-    if (!host_buf) return LLGX_OK;
-    if (cap < need) return c->fail(LLGX_E_ARG, "checkpoint needs %zu bytes, buffer holds %zu", need, cap);
+static CkptHeader ckpt_header(const Ctx* c) {
     CkptHeader hd{};
     memcpy(hd.magic, kCkptMagic, 8);
-    hd.version = 1;
+    hd.version = 2;
     hd.prec = c->prec;
     hd.nx = c->nx;
     hd.ny = c->ny;
@@ -1639,25 +1813,45 @@ llgx_status llgx_save_state(llgx_handle h, void* host_buf, size_t cap, size_t* u
     hd.p = c->cur_p;
     hd.nhist = (int32_t)c->hist.size();
     hd.fsal_valid = c->fsal_valid ? 1 : 0;
+    hd.abm_have_f = c->abm_have_f ? 1 : 0;
+    hd.abm_have_g = (c->abm_have_f && c->cur_p >= 0) ? 1 : 0;
+    hd.abm_have_prev = c->abm_have_prev ? 1 : 0;
     hd.t = c->t;
     hd.h_next = c->h_next;
+    hd.abm_hprev = c->abm_hprev;
     for (size_t i = 0; i < c->hist.size(); ++i) hd.hist_t[i] = c->hist[i].t;
     hd.counters[0] = c->n_exact;
     hd.counters[1] = c->n_extrap;
     hd.counters[2] = c->n_acc;
     hd.counters[3] = c->n_rej;
     hd.counters[4] = c->n_forced;
+    return hd;
+}
+
+llgx_status llgx_save_state(llgx_handle h, void* host_buf, size_t cap, size_t* used) {
+    if (!h) return LLGX_E_ARG;
+    Ctx* c = (Ctx*)h;
+    if (!c->have_m) return c->fail(LLGX_E_STATE, "magnetization not set");
+    const CkptHeader hd = ckpt_header(c);
+    const size_t vec = 3 * (size_t)c->ncell * c->nb * c->tsz;
+    const size_t need = sizeof hd + vec * ckpt_arrays(hd);
+    if (used) *used = need;
+    if (!host_buf) return LLGX_OK;
+    if (cap < need) return c->fail(LLGX_E_ARG, "checkpoint needs %zu bytes, buffer holds %zu", need, cap);
     char* out = (char*)host_buf;
     memcpy(out, &hd, sizeof hd);
-    const size_t vec = 3 * (size_t)c->ncell * c->nb * c->tsz;
     size_t off = sizeof hd;
-    HIPCHK(c, hipMemcpyAsync(out + off, c->M, vec, hipMemcpyDeviceToHost, c->stream));
-    off += vec;
-    for (const auto& e : c->hist) {
-        HIPCHK(c, hipMemcpyAsync(out + off, c->G[e.slot], vec, hipMemcpyDeviceToHost, c->stream));
+    auto put = [&](const void* src) -> llgx_status {
+        HIPCHK(c, hipMemcpyAsync(out + off, src, vec, hipMemcpyDeviceToHost, c->stream));
         off += vec;
-    }
-    if (c->fsal_valid) HIPCHK(c, hipMemcpyAsync(out + off, c->F[0], vec, hipMemcpyDeviceToHost, c->stream));
+        return LLGX_OK;
+    };
+    llgx_status st = put(c->M);
+    for (size_t i = 0; i < c->hist.size() && !st; ++i) st = put(c->G[c->hist[i].slot]);
+    if (!st && (hd.fsal_valid || hd.abm_have_f)) st = put(c->F[0]);
+    if (!st && hd.abm_have_g) st = put(c->G[c->abm_slot]);
+    if (!st && hd.abm_have_prev) st = put(c->F[2]);
+    if (st) return st;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return LLGX_OK;
 }
@@ -1668,29 +1862,42 @@ llgx_status llgx_load_state(llgx_handle h, const void* host_buf, size_t len) {
     if (!host_buf || len < sizeof(CkptHeader)) return c->fail(LLGX_E_ARG, "checkpoint too short");
     CkptHeader hd;
     memcpy(&hd, host_buf, sizeof hd);
-    if (memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 1)
+    if (memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 2)
         return c->fail(LLGX_E_ARG, "not a checkpoint of this library");
     if (hd.prec != c->prec || hd.nx != c->nx || hd.ny != c->ny || hd.nz != c->nz || hd.nb != c->nb)
         return c->fail(LLGX_E_ARG, "checkpoint of a %dx%dx%d x%d mesh in precision %d does not fit this handle",
                        hd.nx, hd.ny, hd.nz, hd.nb, hd.prec);
-    if (hd.nhist < 0 || hd.nhist > MAX_HIST - 1 || (hd.fsal_valid != 0 && hd.fsal_valid != 1))
+    auto flag = [](int32_t v) { return v == 0 || v == 1; };
+    if (hd.nhist < 0 || hd.nhist > MAX_HIST - 1 || !flag(hd.fsal_valid) || !flag(hd.abm_have_f) ||
+        !flag(hd.abm_have_g) || !flag(hd.abm_have_prev) || (hd.abm_have_g && !hd.abm_have_f) ||
+        (hd.fsal_valid && hd.abm_have_f) || (hd.abm_have_prev && !(hd.abm_hprev > 0)))
         return c->fail(LLGX_E_ARG, "corrupt checkpoint header");
     const size_t vec = 3 * (size_t)c->ncell * c->nb * c->tsz;
-    const size_t need = sizeof hd + vec * (1 + (size_t)hd.nhist + (size_t)hd.fsal_valid);
+    const size_t need = sizeof hd + vec * ckpt_arrays(hd);
     if (len != need) return c->fail(LLGX_E_ARG, "checkpoint length %zu, expected %zu", len, need);
     const char* in = (const char*)host_buf;
     size_t off = sizeof hd;
-    HIPCHK(c, hipMemcpyAsync(c->M, in + off, vec, hipMemcpyHostToDevice, c->stream));
-    off += vec;
-    c->hist.clear();
-    for (int i = 0; i < hd.nhist; ++i) {
-        HIPCHK(c, hipMemcpyAsync(c->G[i], in + off, vec, hipMemcpyHostToDevice, c->stream));
-        c->hist.push_back({hd.hist_t[i], i});
+    auto get = [&](void* dst) -> llgx_status {
+        HIPCHK(c, hipMemcpyAsync(dst, in + off, vec, hipMemcpyHostToDevice, c->stream));
         off += vec;
+        return LLGX_OK;
+    };
+    llgx_status st = get(c->M);
+    c->hist.clear();
+    for (int i = 0; i < hd.nhist && !st; ++i) {
+        st = get(c->G[i]);
+        c->hist.push_back({hd.hist_t[i], i});
     }
-    if (hd.fsal_valid) HIPCHK(c, hipMemcpyAsync(c->F[0], in + off, vec, hipMemcpyHostToDevice, c->stream));
+    if (!st && (hd.fsal_valid || hd.abm_have_f)) st = get(c->F[0]);
+    if (!st && hd.abm_have_g) st = get(c->G[hd.nhist]);
+    if (!st && hd.abm_have_prev) st = get(c->F[2]);
+    if (st) return st;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->fsal_valid = hd.fsal_valid != 0;
+    c->abm_have_f = hd.abm_have_f != 0;
+    c->abm_have_prev = hd.abm_have_prev != 0;
+    c->abm_hprev = hd.abm_hprev;
+    c->abm_slot = hd.nhist;
     c->cur_method = hd.method;
     c->cur_p = hd.p;
     c->t = hd.t;

@@ -18,6 +18,7 @@ struct Tableau {
     double a[8][8];
     double b[8];
     double bh[8];
+    bool multistep;   // ABM2: stepped by its own predictor-corrector path, not by a, b
 };
 
 // clang-format off
@@ -82,6 +83,11 @@ static const Tableau TAB_RKF56 = {"RKF56", 8, 5, 6, false,
      {93.0 / 640, -3.6, 803.0 / 256, -11.0 / 160, 99.0 / 256, 0, 1}},
     {31.0 / 384, 0, 1125.0 / 2816, 9.0 / 32, 125.0 / 768, 5.0 / 66, 0, 0},
     {7.0 / 1408, 0, 1125.0 / 2816, 9.0 / 32, 125.0 / 768, 0, 5.0 / 66, 5.0 / 66}};
+// Adams-Bashforth-Moulton, 2nd order (ref. [32]): PECE with a variable-step
+// AB2 predictor and the trapezoidal corrector, two evaluations per step; the
+// entries below only carry its name and orders (propagated 2, Milne estimate
+// of the corrector's error: exponent 1/3 in Eq. (5)).
+static const Tableau TAB_ABM2 = {"ABM2", 2, 2, 2, false, {0, 1}, {{0}, {1}}, {0.5, 0.5}, {1, 0}, true};
 // clang-format on
 
 inline const Tableau* tableau_for(int method) {
@@ -93,6 +99,7 @@ inline const Tableau* tableau_for(int method) {
         case 4: return &TAB_HEUN;
         case 5: return &TAB_RK23;
         case 6: return &TAB_RKF56;
+        case 7: return &TAB_ABM2;
         default: return nullptr;
     }
 }

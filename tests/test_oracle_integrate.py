@@ -144,3 +144,85 @@ def test_matched_order_keeps_method_order(method, p_matched, p_low):
     assert obs["low"] < n - 1.2, (err, obs)     # linear extrapolation limits the order
     # matched order: errors very similar to full evaluation
     assert err["matched"][-1] < 3 * err["full"][-1]
+
+
+# --- ABM2 (Sec. II, ref. [32]) ---------------------------------------------------
+
+@pytest.mark.parametrize("r", [0.5, 1.0, 1.7, 3.0])
+def test_ab2_am2_on_polynomials(r):
+    """The predictor integrates y' = f exactly for quadratic y with any step
+    ratio, the trapezoidal corrector too; on cubic y (constant third
+    derivative) the corrector's error equals milne_factor(r) times
+    |corrector - predictor| (the constants come from the exact integrals)."""
+    h = 0.37
+    hp = h / r
+    tn, tm = 0.2, 0.2 - hp
+    for y, dy, cubic in [(lambda t: 3 * t * t - 2 * t + 1, lambda t: 6 * t - 2, False),
+                         (lambda t: 2 * t ** 3 - t * t + 0.5, lambda t: 6 * t * t - 2 * t, True)]:
+        y0 = np.array([y(tn)])
+        pred = integrate.ab2_predict(y0, np.array([dy(tn)]), np.array([dy(tm)]), h, hp)
+        corr = integrate.am2_correct(y0, np.array([dy(tn)]), np.array([dy(tn + h)]), h)
+        exact = y(tn + h)
+        if not cubic:
+            assert abs(pred[0] - exact) < 1e-14 and abs(corr[0] - exact) < 1e-14
+        else:
+            e_corr = exact - corr[0]
+            assert abs(e_corr - (-(12.0 / 12.0) * h ** 3)) < 1e-13          # -h^3 y'''/12, y''' = 12
+            assert abs(abs(e_corr) - integrate.milne_factor(r) * abs(corr[0] - pred[0])) < 1e-13
+    # no previous derivative: Euler predictor
+    assert integrate.ab2_predict(np.array([1.0]), np.array([2.0]), None, 0.5, None)[0] == 2.0
+
+
+def _spin_abm_error(h, T, extrap=None):
+    from tests.test_oracle_tableaux import SPIN, spin_exact
+    M0 = spin_exact(0.0).reshape(3, 1, 1, 1)
+    Nf = newell.tensor_full((1, 1, 1), SPIN["cell"])
+    it = integrate.Integrator(SPIN, M0, method="ABM2", h=h, adaptive=False, Nfull=Nf, extrap=extrap)
+    steps = int(round(T / h))
+    for _ in range(steps):
+        it.step()
+    return np.linalg.norm(it.M[:, 0, 0, 0] - spin_exact(steps * h)) / SPIN["Ms"], it
+
+
+def test_abm2_second_order_on_single_spin():
+    T = 128e-12
+    hs = [0.5e-12, 0.25e-12, 0.125e-12]
+    errs = [_spin_abm_error(h, T)[0] for h in hs]
+    obs = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert abs(obs[-1] - 2) < 0.2, (errs, obs)
+
+
+def test_abm2_evaluation_counts_and_rejection():
+    p = _film()
+    M0 = workloads.random_m(p["n"], p["Ms"], 21)
+    it = integrate.Integrator(p, M0, method="ABM2", h=1e-13, adaptive=False, extrap=2)
+    it.step()
+    assert it.stats == dict(exact=3, extrap=0, accepted=1, rejected=0, forced=0)  # start, E1 (priming), E2
+    it.step()
+    assert (it.stats["exact"], it.stats["extrap"]) == (5, 0)
+    for _ in range(3):
+        it.step()
+    assert (it.stats["exact"], it.stats["extrap"]) == (8, 3)  # primed: 1 exact + 1 extrapolated per step
+    # adaptive: a far too large first step is rejected, the start field is reused
+    it2 = integrate.Integrator(p, M0, method="ABM2", h=3e-12, e_max=1e-5)
+    info = it2.step()
+    assert info["rejected"] > 0 and info["err"] <= 1e-5
+    assert it2.stats["exact"] == 1 + (info["rejected"] + 1) + 1
+
+
+def test_abm2_matched_extrapolation_keeps_order():
+    """ABM2 with p = 2 (matched) keeps second order on a demag-dominated film;
+    p = 0 (field frozen over the step) costs accuracy."""
+    prob = _demag_only()
+    M0 = workloads.random_m(prob["n"], prob["Ms"], 19)
+    T = 2e-12
+    ref = _run(prob, M0, "RK4", 12.5e-15, T, None)
+    hs = [100e-15, 50e-15]
+    err = {}
+    for tag, pp in (("full", None), ("matched", 2), ("zero", 0)):
+        err[tag] = [metrics.epsilon_map(_run(prob, M0, "ABM2", h, T, pp), ref, prob["Ms"]) for h in hs]
+    obs = {k: math.log2(v[0] / v[1]) for k, v in err.items()}
+    assert abs(obs["full"] - 2) < 0.3, (err, obs)
+    assert obs["matched"] > 1.7, (err, obs)
+    assert err["matched"][-1] < 2 * err["full"][-1], err
+    assert err["zero"][-1] > 2 * err["matched"][-1], err
