@@ -146,7 +146,12 @@ llgx_status llgx_get_demag_tensor(llgx_handle h, double* N_host);
 llgx_status llgx_self_tensor(llgx_handle h, double n00[3]);
 
 /* Current magnetization (copied; the history of Eq. (6) is invalidated and
- * priming restarts; t is kept). */
+ * priming restarts; t is kept).  A cell with M = 0 is empty (no magnetic
+ * material, as between the particles of the array in Sec. III): it stays
+ * zero, and its magnetic neighbours see a free surface there (the exchange
+ * term treats it as a missing neighbour); renormalisation leaves it empty.
+ * The library notes on the stream whether any cell is empty, so meshes
+ * without empty cells skip that test. */
 llgx_status llgx_set_m(llgx_handle h, const void* M_dev);
 llgx_status llgx_get_m(llgx_handle h, void* M_dev);
 

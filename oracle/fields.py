@@ -43,14 +43,30 @@ def problem_arrays(p):
 
 
 def exchange_field(M, cell, Ms, A):
-    """2A/(mu0 Ms^2) * sum_d (M[i+e_d] - 2M[i] + M[i-e_d]) / d^2, Neumann boundary."""
+    """2A/(mu0 Ms^2) * sum_d (M[i+e_d] - 2M[i] + M[i-e_d]) / d^2, Neumann boundary.
+
+    A neighbour outside the mesh, or an empty cell (M = 0: no magnetic
+    material, as in the particle array of Sec. III), is replaced by the cell
+    itself: a free surface of the magnetic body."""
     dx, dy, dz = cell
     P = np.pad(M, ((0, 0), (1, 1), (1, 1), (1, 1)), mode="edge")  # edge copy = Neumann
     c = P[:, 1:-1, 1:-1, 1:-1]
-    lap = ((P[:, 1:-1, 1:-1, 2:] - 2 * c + P[:, 1:-1, 1:-1, :-2]) / dx ** 2
-           + (P[:, 1:-1, 2:, 1:-1] - 2 * c + P[:, 1:-1, :-2, 1:-1]) / dy ** 2
-           + (P[:, 2:, 1:-1, 1:-1] - 2 * c + P[:, :-2, 1:-1, 1:-1]) / dz ** 2)
+
+    def nb(a):
+        empty = np.sum(a * a, axis=0) == 0.0
+        return np.where(empty[None], c, a)
+
+    lap = ((nb(P[:, 1:-1, 1:-1, 2:]) - 2 * c + nb(P[:, 1:-1, 1:-1, :-2])) / dx ** 2
+           + (nb(P[:, 1:-1, 2:, 1:-1]) - 2 * c + nb(P[:, 1:-1, :-2, 1:-1])) / dy ** 2
+           + (nb(P[:, 2:, 1:-1, 1:-1]) - 2 * c + nb(P[:, :-2, 1:-1, 1:-1])) / dz ** 2)
     return 2.0 * A / (MU0 * Ms * Ms) * lap
+
+
+def renormalized(M, Ms):
+    """Every magnetic cell rescaled to |M| = Ms; empty cells (M = 0) stay 0."""
+    nrm = np.sqrt(np.sum(M * M, axis=0))
+    scale = np.where(nrm > 0.0, Ms / np.where(nrm > 0.0, nrm, 1.0), 0.0)
+    return M * scale[None]
 
 
 def anisotropy_field(M, Ms, K, u):
@@ -89,5 +105,6 @@ def energy(M, Hd, pa):
          - 0.5 * MU0 * np.sum(M * Hex, axis=0))
     if pa["K"] != 0.0:
         mu = np.einsum("i...,i->...", M, pa["u"]) / pa["Ms"]
-        e = e + pa["K"] * (1.0 - mu * mu)
+        magnetic = np.sum(M * M, axis=0) > 0.0  # empty cells carry no anisotropy energy
+        e = e + pa["K"] * (1.0 - mu * mu) * magnetic
     return V * float(np.sum(e))

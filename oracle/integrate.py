@@ -33,7 +33,7 @@ Readings of the paper taken here (the GPU library takes the same ones):
 * Full evaluation (extrap=None): every stage is exact; an FSAL tableau
   reuses its last stage as the next stage 1 when ``renormalize`` is off.
 * ``renormalize`` (off by default): rescale every cell to |M| = Ms after each
-  accepted iteration.
+  accepted iteration (empty cells, M = 0, stay empty).
 
 ABM2 (the 2nd-order Adams-Bashforth-Moulton predictor-corrector of Sec. II,
 ref. [32]), in PECE form with the readings taken here:
@@ -282,8 +282,7 @@ class Integrator:
         else:
             self.fsal_F = None
         if self.renormalize:
-            nrm = np.sqrt(np.sum(Mnew * Mnew, axis=0))
-            Mnew = Mnew * (self.pa["Ms"] / nrm)[None]
+            Mnew = _fields.renormalized(Mnew, self.pa["Ms"])
         self.M = Mnew
         self.t = t0 + h
         self.h = h_next
@@ -342,8 +341,7 @@ class Integrator:
             self.hist.append((t0, G0))
             self.hist = self.hist[-p:]
         if self.renormalize:
-            nrm = np.sqrt(np.sum(Mc * Mc, axis=0))
-            Mc = Mc * (self.pa["Ms"] / nrm)[None]
+            Mc = _fields.renormalized(Mc, self.pa["Ms"])
         self.abm_Fprev, self.abm_hprev = F0, h
         self.M = Mc
         self.t = t0 + h

@@ -76,6 +76,7 @@ struct Phys {
     T gpa;             // gamma alpha / ((1 + alpha^2) Ms)
     T n00[3];          // self term of Eq. (6)
     const T* hab;      // per-sample applied field [nb][3] (device), or null: ha for all
+    const int* empty;  // device flag: nonzero when some cell has M = 0 (no material)
     int nx, ny, nz;
     int nb;            // samples of this mesh processed by one launch
 };
@@ -92,7 +93,8 @@ struct XinvOut {
     double cnext;
 };
 
-// Host-side launchers (demag.hip).  All lengths are powers of two.  Spectra
+// Host-side launchers of the FFT passes (pass_x.hip, pass_col.hip, pass_z.hip)
+// and of the tensor setup (newell.hip).  All lengths are powers of two.  Spectra
 // are passed untyped (SpecPtr) and stored as S: the working precision T, or
 // _Float16 / __bf16 pairs for T = float.  fscale, scale, kscale and hscale
 // multiply the x-pass input, the y-pass output, the k-space kernel and the
@@ -162,6 +164,10 @@ template <typename T>
 hipError_t launch_final(hipStream_t s, long ncell, int nb, const T* base, const Final<T>& fs, double inv_ms, T* mnew,
                         double* parts, int nparts);
 hipError_t launch_reduce_max(hipStream_t s, const double* parts, int nparts, double* out);
+// flag = 1 if any of the n cells ([nb][3][ncell] layout) has M = 0 (flag is
+// not cleared here)
+template <typename T>
+hipError_t launch_detect_empty(hipStream_t s, long ncell, int nb, const T* M, int* flag);
 template <typename T>
 hipError_t launch_renorm(hipStream_t s, long ncell, int nb, T* M, double Ms);
 template <typename T>

@@ -314,10 +314,23 @@ __global__ __launch_bounds__(NTS) void k_renorm(long ncell, int nb, T* __restric
         const long b = ic / ncell, cell = ic - b * ncell;
         T* m = M + b * 3 * ncell;
         const double x = m[cell], y = m[ncell + cell], z = m[2 * ncell + cell];
-        const double s = Ms / sqrt(x * x + y * y + z * z);
+        const double n2 = x * x + y * y + z * z;
+        if (n2 == 0.0) continue;  // empty cell
+        const double s = Ms / sqrt(n2);
         m[cell] = (T)(x * s);
         m[ncell + cell] = (T)(y * s);
         m[2 * ncell + cell] = (T)(z * s);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NTS) void k_detect_empty(long ncell, int nb, const T* __restrict__ M,
+                                                      int* __restrict__ flag) {
+    for (long ic = (long)blockIdx.x * NTS + threadIdx.x; ic < ncell * nb; ic += (long)gridDim.x * NTS) {
+        const long b = ic / ncell, cell = ic - b * ncell;
+        const T* m = M + b * 3 * ncell;
+        const T x = m[cell], y = m[ncell + cell], z = m[2 * ncell + cell];
+        if (x * x + y * y + z * z == T(0)) *flag = 1;  // every writer stores the same value
     }
 }
 
@@ -503,6 +516,12 @@ hipError_t launch_renorm(hipStream_t s, long ncell, int nb, T* M, double Ms) {
 }
 
 template <typename T>
+hipError_t launch_detect_empty(hipStream_t s, long ncell, int nb, const T* M, int* flag) {
+    k_detect_empty<T><<<grid_for(ncell * nb), NTS, 0, s>>>(ncell, nb, M, flag);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_mean(hipStream_t s, long ncell, const T* M, double* parts, int nparts) {
     k_mean<T><<<(unsigned)nparts, NTS, 0, s>>>(ncell, M, parts);
     return hipGetLastError();
@@ -530,6 +549,7 @@ hipError_t launch_cast(hipStream_t s, long n, const double* src, T* dst) {
     template hipError_t launch_final<T>(hipStream_t, long, int, const T*, const Final<T>&, double, T*, double*,  \
                                         int);                                                                    \
     template hipError_t launch_renorm<T>(hipStream_t, long, int, T*, double);                                    \
+    template hipError_t launch_detect_empty<T>(hipStream_t, long, int, const T*, int*);                          \
     template hipError_t launch_mean<T>(hipStream_t, long, const T*, double*, int);                               \
     template hipError_t launch_cast<T>(hipStream_t, long, const double*, T*);
 INST(float)

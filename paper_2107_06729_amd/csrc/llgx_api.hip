@@ -74,6 +74,9 @@ struct Ctx {
     int nparts = 1;             // blocks of the 1-D reduction kernels
     long nparts_alloc = 1;      // capacity of parts (also covers the 2-D cell grid)
     double* scal = nullptr;     // [0] error norm, [1..3] sums for <M>
+    int* empty_flag = nullptr;  // device: [0] some cell of M has M = 0; [1] the same for the
+                                // input of a field call (llgx_demag / heff / rhs)
+    bool field_input = false;   // phys() reads flag [1] (during a field call)
     double* octant = nullptr;   // real-space tensor for offsets 0..n-1 (double)
     bool have_kernel = false;
     bool have_m = false;
@@ -222,6 +225,7 @@ static Phys<T> phys(const Ctx* c) {
     ph.nz = c->nz;
     ph.nb = c->nb;
     ph.hab = (const T*)c->hab;
+    ph.empty = c->empty_flag + (c->field_input ? 1 : 0);
     return ph;
 }
 
@@ -231,6 +235,19 @@ static Combo<T> plain(const void* base) {
     cb.base = (const T*)base;
     cb.nf = 0;
     return cb;
+}
+
+// Recompute an empty-cell flag (slot 0: from the state M; slot 1: from the
+// input of a field call) on the stream, with no host synchronisation.
+static llgx_status detect_empty(Ctx* c, const void* M = nullptr, int slot = 0) {
+    int* flag = c->empty_flag + slot;
+    if (!M) M = c->M;
+    HIPCHK(c, hipMemsetAsync(flag, 0, sizeof(int), c->stream));
+    if (c->prec == LLGX_F32)
+        HIPCHK(c, launch_detect_empty<float>(c->stream, c->ncell, c->nb, (const float*)M, flag));
+    else
+        HIPCHK(c, launch_detect_empty<double>(c->stream, c->ncell, c->nb, (const double*)M, flag));
+    return LLGX_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1029,7 +1046,8 @@ static void release(Ctx* c) {
     for (auto e : c->spare) (void)hipEventDestroy(e);
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
-    void* ptrs[] = {c->kfold, c->specA, c->specB, c->M, c->Mnew, c->Mk, c->Mk2, c->parts, c->scal, c->octant, c->hab};
+    void* ptrs[] = {c->kfold,  c->specA, c->specB,  c->M,      c->Mnew, c->Mk,
+                    c->Mk2,    c->parts, c->scal,   c->octant, c->hab,  c->empty_flag};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (int i = 0; i < MAX_F; ++i)
@@ -1217,12 +1235,14 @@ static llgx_status create_ctx(const llgx_problem* p, int nb, const double* ha_li
     c->nparts_alloc = std::max<long>(c->nparts, cell_grid(c->nx, c->ny, c->nz, nb).nblocks);
     A((void**)&c->parts, 3 * (size_t)c->nparts_alloc * sizeof(double));
     A((void**)&c->scal, 8 * sizeof(double));
+    A((void**)&c->empty_flag, 16);
     if (ha_list) A(&c->hab, 3 * (size_t)nb * c->tsz);
     if (st == LLGX_OK) {
         // padding columns of the spectra are read (never used) by 16-byte packs: keep them zero
         if (hipMemset(c->specA, 0, bytesA) != hipSuccess) st = c->fail(LLGX_E_HIP, "hipMemset failed");
         if (st == LLGX_OK && c->specB && hipMemset(c->specB, 0, bytesB) != hipSuccess)
             st = c->fail(LLGX_E_HIP, "hipMemset failed");
+        if (st == LLGX_OK && hipMemset(c->empty_flag, 0, 16) != hipSuccess) st = c->fail(LLGX_E_HIP, "hipMemset failed");
     }
     if (st == LLGX_OK && ha_list) {
         std::vector<char> hb(3 * (size_t)nb * c->tsz);
@@ -1475,6 +1495,10 @@ static llgx_status batch_copy(llgx_batch b, int32_t i, const void* src, void* ds
         c->fsal_valid = false;
         c->abm_have_f = c->abm_have_prev = false;
         c->have_m = true;
+        if (e == hipSuccess && detect_empty(c) != LLGX_OK) {
+            bt->err = c->err;
+            return LLGX_E_HIP;
+        }
     } else {
         e = hipMemcpyAsync(dst_or_null, base, bytes, hipMemcpyDeviceToDevice, c->stream);
     }
@@ -1585,6 +1609,8 @@ llgx_status llgx_set_m(llgx_handle h, const void* M_dev) {
     Ctx* c = (Ctx*)h;
     if (!M_dev) return c->fail(LLGX_E_ARG, "null M");
     HIPCHK(c, hipMemcpyAsync(c->M, M_dev, 3 * (size_t)c->ncell * c->nb * c->tsz, hipMemcpyDeviceToDevice, c->stream));
+    llgx_status st = detect_empty(c);
+    if (st) return st;
     c->have_m = true;
     c->hist.clear();
     c->fsal_valid = false;
@@ -1611,9 +1637,15 @@ static llgx_status field_call(llgx_handle h, const void* M_dev, void* out_dev, i
         out.f = out_dev;
     else
         out.h = out_dev;
+    llgx_status st = detect_empty(c, M_dev, 1);
+    if (st) return st;
+    c->field_input = true;
     if (c->prec == LLGX_F32)
-        return eval_exact<float>(c, plain<float>(M_dev), nullptr, mode, (const float*)M_dev, out);
-    return eval_exact<double>(c, plain<double>(M_dev), nullptr, mode, (const double*)M_dev, out);
+        st = eval_exact<float>(c, plain<float>(M_dev), nullptr, mode, (const float*)M_dev, out);
+    else
+        st = eval_exact<double>(c, plain<double>(M_dev), nullptr, mode, (const double*)M_dev, out);
+    c->field_input = false;
+    return st;
 }
 
 llgx_status llgx_demag(llgx_handle h, const void* M_dev, void* H_dev) { return field_call(h, M_dev, H_dev, XINV_DEMAG); }
@@ -1891,6 +1923,7 @@ llgx_status llgx_load_state(llgx_handle h, const void* host_buf, size_t len) {
     if (!st && (hd.fsal_valid || hd.abm_have_f)) st = get(c->F[0]);
     if (!st && hd.abm_have_g) st = get(c->G[hd.nhist]);
     if (!st && hd.abm_have_prev) st = get(c->F[2]);
+    if (!st) st = detect_empty(c);
     if (st) return st;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->fsal_valid = hd.fsal_valid != 0;

@@ -30,6 +30,20 @@ struct ComboField {
     }
 };
 
+// neighbour at flat offset d of cell (components at c N + cell + d), or the
+// cell itself where it is missing: outside the mesh (inside = false) or
+// empty (M = 0, no magnetic material) -- a free surface either way
+template <typename T, typename Fld>
+__device__ __forceinline__ void neighbour(const Fld& M, long N, long cell, long d, bool inside, bool masked,
+                                          const T m[3], T v[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = inside ? M(c * N + cell + d) : m[c];
+    if (masked && v[0] * v[0] + v[1] * v[1] + v[2] * v[2] == T(0)) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = m[c];
+    }
+}
+
 // M reads the sample's own [3][N] block; b is the sample index (applied field)
 template <typename T, typename Fld>
 __device__ __forceinline__ void heff_at(const Fld& M, long N, long cell, int x, int y, int z, int b,
@@ -38,16 +52,19 @@ __device__ __forceinline__ void heff_at(const Fld& M, long N, long cell, int x, 
     const long sy = ph.nx, sz = (long)ph.nx * ph.ny;
 #pragma unroll
     for (int c = 0; c < 3; ++c) m[c] = M(c * N + cell);
+    const bool masked = *ph.empty != 0;  // uniform: the mesh has empty cells
+    T xm[3], xp[3], ym[3], yp[3], zm[3], zp[3];
+    neighbour<T>(M, N, cell, -1, x > 0, masked, m, xm);
+    neighbour<T>(M, N, cell, 1, x + 1 < ph.nx, masked, m, xp);
+    neighbour<T>(M, N, cell, -sy, y > 0, masked, m, ym);
+    neighbour<T>(M, N, cell, sy, y + 1 < ph.ny, masked, m, yp);
+    neighbour<T>(M, N, cell, -sz, z > 0, masked, m, zm);
+    neighbour<T>(M, N, cell, sz, z + 1 < ph.nz, masked, m, zp);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const long o = c * N + cell;
         const T mc = m[c];
-        // Neumann boundary: a missing neighbour is replaced by the cell itself
-        const T xm = x > 0 ? M(o - 1) : mc, xp = x + 1 < ph.nx ? M(o + 1) : mc;
-        const T ym = y > 0 ? M(o - sy) : mc, yp = y + 1 < ph.ny ? M(o + sy) : mc;
-        const T zm = z > 0 ? M(o - sz) : mc, zp = z + 1 < ph.nz ? M(o + sz) : mc;
-        H[c] = hd[c] + ha[c] + ph.exx * ((xm + xp) - T(2) * mc) + ph.exy * ((ym + yp) - T(2) * mc) +
-               ph.exz * ((zm + zp) - T(2) * mc);
+        H[c] = hd[c] + ha[c] + ph.exx * ((xm[c] + xp[c]) - T(2) * mc) + ph.exy * ((ym[c] + yp[c]) - T(2) * mc) +
+               ph.exz * ((zm[c] + zp[c]) - T(2) * mc);
     }
     const T mu = m[0] * ph.u[0] + m[1] * ph.u[1] + m[2] * ph.u[2];
 #pragma unroll

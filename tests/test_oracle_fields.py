@@ -55,3 +55,48 @@ def test_rhs_is_orthogonal_to_m_and_satisfies_gilbert_form():
     # Eq. (1): dM/dt = -gamma M x H + (alpha/Ms) M x dM/dt
     rhs = -gamma * fields.cross(M, H) + (alpha / Ms) * fields.cross(M, F)
     assert np.max(np.abs(F - rhs)) <= 1e-12 * np.max(np.abs(F))
+
+
+# --- empty cells (M = 0): particle arrays ---------------------------------------
+
+def test_exchange_free_surface_at_empty_cells():
+    """A magnetic block inside empty cells has the exchange field of the same
+    block on its own mesh (whose Neumann boundary is pinned above)."""
+    n = (10, 8, 3)
+    cell = (3e-9, 4e-9, 5e-9)
+    M = workloads.random_m(n, 8e5, 11)
+    block = (slice(None), slice(0, 3), slice(1, 6), slice(2, 7))
+    Mm = np.zeros_like(M)
+    Mm[block] = M[block]
+    H = fields.exchange_field(Mm, cell, 8e5, 1.3e-11)
+    Hb = fields.exchange_field(np.ascontiguousarray(M[block]), cell, 8e5, 1.3e-11)
+    assert np.max(np.abs(H[block] - Hb)) <= 1e-12 * np.max(np.abs(Hb))
+
+
+def test_checkerboard_particles_do_not_exchange():
+    n, sq = (8, 8, 2), 2
+    mask = workloads.checkerboard_mask(n, sq)
+    M = workloads.masked(workloads.random_m(n, 8e5, 12), mask)
+    H = fields.exchange_field(M, (5e-9, 5e-9, 5e-9), 8e5, 1.3e-11)
+    for j0 in range(0, 8, sq):
+        for i0 in range(0, 8, sq):
+            if mask[0, j0, i0] == 0:
+                continue
+            blk = (slice(None), slice(None), slice(j0, j0 + sq), slice(i0, i0 + sq))
+            Hb = fields.exchange_field(np.ascontiguousarray(M[blk]), (5e-9, 5e-9, 5e-9), 8e5, 1.3e-11)
+            assert np.max(np.abs(H[blk] - Hb)) <= 1e-12 * np.max(np.abs(Hb))
+
+
+def test_empty_cells_stay_empty():
+    from oracle import integrate
+    p = workloads.problem((8, 8, 1), (5e-9, 5e-9, 5e-9), 8e5, 1.3e-11, 0.02, K=1e4, Ha=(2e4, 1e3, 0.0))
+    mask = workloads.checkerboard_mask(p["n"], 2)
+    M0 = workloads.masked(workloads.random_m(p["n"], p["Ms"], 13), mask)
+    it = integrate.Integrator(p, M0, method="RK4", h=5e-14, extrap=2, renormalize=True)
+    for _ in range(4):
+        it.step()
+    assert np.all(it.M[:, mask == 0] == 0.0)
+    nrm = np.sqrt(np.sum(it.M ** 2, axis=0))
+    assert np.max(np.abs(nrm[mask == 1] / p["Ms"] - 1)) < 1e-14
+    R = fields.renormalized(np.array([[[[0.0, 3.0]]], [[[0.0, 4.0]]], [[[0.0, 0.0]]]]), 10.0)
+    assert R[:, 0, 0, 0].tolist() == [0.0, 0.0, 0.0] and R[:, 0, 0, 1].tolist() == [6.0, 8.0, 0.0]

@@ -91,3 +91,25 @@ def batch_samples(count=64, seed=4):
         p = problem(n, (4e-9, 4e-9, 4e-9), 8.0e5, 1.3e-11, 0.05, Ha=(float(bmag[i]) / MU0, 0.0, 0.0))
         out.append((p, 1000 + i))
     return out
+
+
+# Checkerboard array of square particles that touch only at corners (no
+# exchange between particles), 300 nm x 300 nm x 5 nm in 5 nm cells with
+# 50 nm squares, Permalloy-like, field (20, 1, 0) kA/m: the particle-array
+# geometry of Sec. III (its relaxed starting state is not available, so the
+# particles start in seeded random or uniform states).  Empty cells hold M = 0.
+CHECKERBOARD_60x60x1 = problem((60, 60, 1), (5e-9, 5e-9, 5e-9), 8.0e5, 1.3e-11, 0.02, Ha=(20e3, 1e3, 0.0))
+CHECKERBOARD_SQUARE = 10
+
+
+def checkerboard_mask(n, square):
+    """1.0 in the magnetic squares ((i // square + j // square) even), else 0."""
+    nx, ny, nz = n
+    j, i = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    m = (((i // square) + (j // square)) % 2 == 0).astype(np.float64)
+    return np.broadcast_to(m[None], (nz, ny, nx)).copy()
+
+
+def masked(M, mask):
+    """M with the empty cells (mask 0) set to zero."""
+    return M * mask[None]
