@@ -73,9 +73,11 @@ def kernel_bytes(n, tsz, p, nnz_comb=1, nnz_final=4):
         "yfwd": sA + sB,
         "zmul": 2 * sB + kern,
         "yinv": sB + sA,
-        "xinv": sA + vec + vec + vec,             # spectrum + M in; F and G out
+        # spectrum + M in; F, G and the next stage input M_2 = M0 + h a F out
+        "xinv": sA + vec + 3 * vec,
         "combine": (1 + nnz_comb) * vec + vec,
-        "extrap": 3 * vec,                        # M_k and one Eq. (6) field in; F out
+        # M_k, one Eq. (6) field and M0 in; F and the next stage input out
+        "extrap": 5 * vec,
         # last sub-step fused with Eq. (3): M_k, its Eq. (6) field, M0 and
         # F_1..F_{S-1} in; M out (F_S stays in registers)
         "final": (2 + 1 + (nnz_final - 1)) * vec + vec,
