@@ -21,6 +21,7 @@
 #include "kernels.hpp"
 #include "physics.hpp"
 #include "fft_col.hpp"
+#include "fft_row.hpp"
 #include "spec_store.hpp"
 #include "tile_io.hpp"
 
@@ -94,77 +95,89 @@ __global__ __launch_bounds__(NT) void k_xfwd(Combo<T> in, T* __restrict__ mk_out
         }
         return;
     } else {
-        constexpr int CS = LX + 1;
-        constexpr int TOT = ROWS * LX, PER = (TOT + NT - 1) / NT;
-        __shared__ C buf[ROWS * CS];
+        using F = RowFFT<T, LX, false, ROWS, NT>;
+        __shared__ C buf[F::LDS_ELEMS];
         __shared__ C twl[LX];
         __shared__ C twp[LX + 1];
         TwStage<T, LX, NT> tw1;
         TwStage<T, LX + 1, NT> tw2;
         tw1.fetch(twL);
         tw2.fetch(twP);
-        // element pair (x[2i], x[2i+1]) of row g; staged: all loads of one
-        // operand are issued before they are used
-        C v[PER];
-        long off[PER];
-        int x0[PER];
-        bool ok[PER];
+        // stage-0 inputs z[i] = x[2i] + i x[2i+1] of the stage combination,
+        // straight from global memory: all loads of one operand are issued
+        // before they are used
+        C v[F::U0][F::R0];
+        long off[F::U0][F::R0];
+        bool ok[F::U0][F::R0];
+        bool two[F::U0][F::R0];
 #pragma unroll
-        for (int m = 0; m < PER; ++m) {
-            const int e = threadIdx.x + m * NT;
-            const int r = e / LX, i = e - r * LX;
-            const long g = row0 + r;
-            x0[m] = 2 * i;
-            off[m] = g * nin + 2 * i;
-            ok[m] = (TOT % NT == 0 || e < TOT) && g < nrows && 2 * i < nin;
+        for (int m = 0; m < F::U0; ++m) {
+            const int u = threadIdx.x + m * NT;
+#pragma unroll
+            for (int q = 0; q < F::R0; ++q) {
+                int r, i;
+                F::first_input(u, q, r, i);
+                const long g = row0 + r;
+                off[m][q] = g * nin + 2 * i;
+                ok[m][q] = F::live0(u) && g < nrows && 2 * i < nin;
+                two[m][q] = 2 * i + 1 < nin;
+            }
         }
         const bool pairs = (nin & 1) == 0;  // rows start 8/16-byte aligned: load both reals at once
-        auto load2 = [&](const T* __restrict__ p, int m) -> C {
+        auto load2 = [&](const T* __restrict__ p, int m, int q) -> C {
             C w{T(0), T(0)};
-            if (ok[m]) {
+            if (ok[m][q]) {
                 if (pairs) {
-                    w = *(const C*)(p + off[m]);
+                    w = *(const C*)(p + off[m][q]);
                 } else {
-                    w.x = p[off[m]];
-                    if (x0[m] + 1 < nin) w.y = p[off[m] + 1];
+                    w.x = p[off[m][q]];
+                    if (two[m][q]) w.y = p[off[m][q] + 1];
                 }
             }
             return w;
         };
 #pragma unroll
-        for (int m = 0; m < PER; ++m) v[m] = load2(in.base, m);
-        for (int l = 0; l < in.nf; ++l) {
-            C w[PER];
+        for (int m = 0; m < F::U0; ++m)
 #pragma unroll
-            for (int m = 0; m < PER; ++m) w[m] = load2(in.f[l], m);
+            for (int q = 0; q < F::R0; ++q) v[m][q] = load2(in.base, m, q);
+        for (int l = 0; l < in.nf; ++l) {
+            C w[F::U0][F::R0];
+#pragma unroll
+            for (int m = 0; m < F::U0; ++m)
+#pragma unroll
+                for (int q = 0; q < F::R0; ++q) w[m][q] = load2(in.f[l], m, q);
             const T cf = in.coef[l];
 #pragma unroll
-            for (int m = 0; m < PER; ++m) {
-                v[m].x += cf * w[m].x;
-                v[m].y += cf * w[m].y;
-            }
+            for (int m = 0; m < F::U0; ++m)
+#pragma unroll
+                for (int q = 0; q < F::R0; ++q) {
+                    v[m][q].x += cf * w[m][q].x;
+                    v[m][q].y += cf * w[m][q].y;
+                }
         }
 #pragma unroll
-        for (int m = 0; m < PER; ++m) {
-            const int e = threadIdx.x + m * NT;
-            if (TOT % NT != 0 && e >= TOT) continue;
-            const int r = e / LX, i = e - r * LX;
-            buf[r * CS + i] = C{v[m].x * fscale, v[m].y * fscale};
-            if (mk_out && ok[m]) {
-                mk_out[off[m]] = v[m].x;
-                if (x0[m] + 1 < nin) mk_out[off[m] + 1] = v[m].y;
+        for (int m = 0; m < F::U0; ++m)
+#pragma unroll
+            for (int q = 0; q < F::R0; ++q) {
+                if (mk_out && ok[m][q]) {
+                    mk_out[off[m][q]] = v[m][q].x;
+                    if (two[m][q]) mk_out[off[m][q] + 1] = v[m][q].y;
+                }
+                v[m][q].x *= fscale;
+                v[m][q].y *= fscale;
             }
-        }
         tw1.put(twl);
         tw2.put(twp);
+        F::first_to_lds(v, buf);
         __syncthreads();
-        lds_fft<T, LX, false, Cols<ROWS, CS, 1, false>, NT>(buf, twl);
+        F::rest(buf, twl);
         for (int e = threadIdx.x; e < ROWS * (LX + 1); e += NT) {
             const int r = e / (LX + 1), k = e - r * (LX + 1);
             const long g = row0 + r;
             if (g >= nrows) continue;
-            const C zk = buf[r * CS + (k & (LX - 1))];
-            const C zc = cconj(buf[r * CS + ((LX - k) & (LX - 1))]);
+            const C* rb = buf + r * F::RS;
+            const C zk = rb[F::P(k & (LX - 1))];
+            const C zc = cconj(rb[F::P((LX - k) & (LX - 1))]);
             const C E{(zk.x + zc.x) * T(0.5), (zk.y + zc.y) * T(0.5)};
             const C O{(zk.y - zc.y) * T(0.5), (zc.x - zk.x) * T(0.5)};  // -i (zk - zc)/2
             spec[g * SX + k] = Spec<T, S>::put(cadd(E, cmul(O, twp[k])));
@@ -182,9 +195,10 @@ __global__ __launch_bounds__(NT) void k_xinv(const typename Spec<T, S>::elem* __
                                              const cx<T>* __restrict__ twL, const cx<T>* __restrict__ twP,
                                              T hscale) {
     using C = cx<T>;
-    constexpr int LXE = LX > 0 ? LX : 1;
-    constexpr int CS = LXE + 1;
-    __shared__ C buf[3 * ROWS * CS];
+    constexpr int LXE = LX > 0 ? LX : 2;
+    using F = RowFFT<T, LXE, true, 3 * ROWS, NT>;
+    constexpr int RS = LX > 0 ? F::RS : 1;
+    __shared__ C buf[3 * ROWS * RS];
     __shared__ C twl[LXE];
     const long nrow = (long)ph.ny * ph.nz;
     const long N = nrow * ph.nx;
@@ -197,45 +211,50 @@ __global__ __launch_bounds__(NT) void k_xinv(const typename Spec<T, S>::elem* __
         for (int lr = threadIdx.x; lr < 3 * ROWS; lr += NT) {
             const int r = lr / 3, c = lr - 3 * r;
             const long g = row0 + r;
-            if (g < nrow) buf[lr * CS] = Spec<T, S>::get(spec[(c * nrow + g) * SX]);
+            if (g < nrow) buf[lr * RS] = Spec<T, S>::get(spec[(c * nrow + g) * SX]);
         }
         __syncthreads();
     } else {
-        constexpr int TOT = 3 * ROWS * LX, PER = (TOT + NT - 1) / NT;
         TwStage<T, LX, NT> tw1;
         tw1.fetch(twL);
-        // post-twiddles of this thread's k (fetched with the spectrum)
-        C wk[PER];
-        C xa[PER], xb[PER];
+        // stage-0 inputs Z[k] = (X[k] + X*[LX-k]) + i e^{+2 pi i k/P} (X[k] - X*[LX-k])
+        // of tile row lr = 3 r + c (component c of mesh row row0 + r), from
+        // global memory
+        C xa[F::U0][F::R0], xb[F::U0][F::R0], wk[F::U0][F::R0];
 #pragma unroll
-        for (int m = 0; m < PER; ++m) {
-            const int e = threadIdx.x + m * NT;
-            const int lr = e / LX, k = e - lr * LX;
-            const int r = lr / 3, c = lr - 3 * r;
-            const long g = row0 + r;
-            xa[m] = C{T(0), T(0)};
-            xb[m] = C{T(0), T(0)};
-            wk[m] = twP[k];
-            if ((TOT % NT == 0 || e < TOT) && g < nrow) {
-                const typename Spec<T, S>::elem* row = spec + (c * nrow + g) * SX;
-                xa[m] = Spec<T, S>::get(row[k]);
-                xb[m] = Spec<T, S>::get(row[LX - k]);
+        for (int m = 0; m < F::U0; ++m) {
+            const int u = threadIdx.x + m * NT;
+#pragma unroll
+            for (int q = 0; q < F::R0; ++q) {
+                int lr, k;
+                F::first_input(u, q, lr, k);
+                const int r = lr / 3, c = lr - 3 * r;
+                const long g = row0 + r;
+                xa[m][q] = C{T(0), T(0)};
+                xb[m][q] = C{T(0), T(0)};
+                wk[m][q] = twP[k];
+                if (F::live0(u) && g < nrow) {
+                    const typename Spec<T, S>::elem* row = spec + (c * nrow + g) * SX;
+                    xa[m][q] = Spec<T, S>::get(row[k]);
+                    xb[m][q] = Spec<T, S>::get(row[LX - k]);
+                }
             }
         }
+        C z[F::U0][F::R0];
 #pragma unroll
-        for (int m = 0; m < PER; ++m) {
-            const int e = threadIdx.x + m * NT;
-            if (TOT % NT != 0 && e >= TOT) continue;
-            const int lr = e / LX, k = e - lr * LX;
-            const C xk = xa[m];
-            const C xc = cconj(xb[m]);
-            const C sm = cadd(xk, xc);
-            const C wd = cmulc(csub(xk, xc), wk[m]);
-            buf[lr * CS + k] = C{sm.x - wd.y, sm.y + wd.x};
-        }
+        for (int m = 0; m < F::U0; ++m)
+#pragma unroll
+            for (int q = 0; q < F::R0; ++q) {
+                const C xk = xa[m][q];
+                const C xc = cconj(xb[m][q]);
+                const C sm = cadd(xk, xc);
+                const C wd = cmulc(csub(xk, xc), wk[m][q]);
+                z[m][q] = C{sm.x - wd.y, sm.y + wd.x};
+            }
         tw1.put(twl);
+        F::first_to_lds(z, buf);
         __syncthreads();
-        lds_fft<T, LX, true, Cols<3 * ROWS, CS, 1, false>, NT>(buf, twl);
+        F::rest(buf, twl);
     }
     const int nx = ph.nx;
     for (int e = threadIdx.x; e < ROWS * nx; e += NT) {
@@ -245,7 +264,7 @@ __global__ __launch_bounds__(NT) void k_xinv(const typename Spec<T, S>::elem* __
         T hd[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const C v = buf[(3 * r + c) * CS + (LX > 0 ? (x >> 1) : 0)];
+            const C v = buf[(3 * r + c) * RS + (LX > 0 ? F::P(x >> 1) : 0)];
             hd[c] = ((x & 1) ? v.y : v.x) * hscale;
         }
         const long cell = g * nx + x;
