@@ -393,9 +393,12 @@ static unsigned grid_for(long n) {
     return (unsigned)(b < 1 ? 1 : b);
 }
 
+// Blocks of 64 x-cells by 4 rows: the y neighbours of the stencil mostly
+// come from the same workgroup (measured against 256x1, 128x2 and 32x8 on the
+// 256x256x16 slab: the stage kernels are 5-10 % faster).
 CellGrid cell_grid(int nx, int ny, int nz, int nb) {
     int tx = 1;
-    while (tx < nx && tx < NTS) tx <<= 1;
+    while (tx < nx && tx < 64) tx <<= 1;
     const int ry = NTS / tx;
     const long rows = (long)ny * nz * nb;
     CellGrid g;
