@@ -178,3 +178,38 @@ def test_sampled_run_matches_oracle_fp64():
     assert np.max(np.abs(got - ref)) <= 1e-10 * p["Ms"]
     c = s.counters()
     assert c["accepted"] == ora.stats["accepted"] and c["rejected"] == ora.stats["rejected"]
+
+
+def test_benchmark_configuration_against_oracle():
+    """The benchmarked configuration itself: 256x256x16 slab, RK4 h = 250 fs,
+    FP32 with p = 4 extrapolation, autotuned launch variants, graph-replayed
+    steps on a created stream; 4 priming steps and 2 extrapolated steps
+    against the oracle from the same FP32-rounded state (shared tensor),
+    every cell within 1e-5 Ms."""
+    import torch
+    import paper_2107_06729_amd as llgx
+    p = workloads.SLAB_256x256x16
+    n = p["n"]
+    log("oracle tensor 256x256x16 ...")
+    Nf = newell.tensor_full(n, p["cell"])
+    M0 = f32_round(workloads.uniform_m(n, p["Ms"], workloads.SLAB_256x256x16_DIR)
+                   + 0.2 * workloads.random_m(n, p["Ms"], workloads.SLAB_256x256x16_SEED))
+    ora = integrate.Integrator(p, M0, method="RK4", h=250e-15, adaptive=False, extrap=4, Nfull=Nf)
+    stream = torch.cuda.Stream()
+    s = llgx.Sim(p, "f32", stream=stream)
+    s.set_demag_tensor(Nf)
+    with torch.cuda.stream(stream):
+        s.set_m(to_dev(M0, "f32"))
+    s.autotune(5)
+    s.run_fixed(_stepper("RK4", 4, 250e-15), 6, use_graph=True)
+    for k in range(6):
+        log(f"oracle step {k}")
+        ora.step()
+    with torch.cuda.stream(stream):
+        got = to_host(s.get_m())
+    err = np.max(np.abs(got - ora.M))
+    log(f"benchmark configuration: max |M_gpu - M_oracle| / Ms = {err / p['Ms']:.3e}")
+    assert err <= 1e-5 * p["Ms"]
+    c = s.counters()
+    assert (c["exact"], c["extrap"]) == (ora.stats["exact"], ora.stats["extrap"])
+    s.close()
