@@ -351,6 +351,7 @@ def main():
         log("fp64 full ...")
         with torch.cuda.stream(stream):
             s64.set_m(torch.as_tensor(M0, dtype=torch.float64, device=dev))
+        extras["fp64_autotune_us"] = s64.autotune(reps=10)
         st64 = llgx.make_stepper("RK4", extrap=None, h=h)
         s64.run_fixed(st64, p + W, use_graph=True)
         dt64 = timed_steps(s64, st64, K, torch, stream)
@@ -381,6 +382,7 @@ def main():
             with torch.cuda.stream(stream):
                 sa.set_m(torch.as_tensor(M0, dtype=torch.float32 if prec == "f32" else torch.float64, device=dev))
             sta = llgx.make_stepper("RKDP54", extrap=ex, h=1e-13, adaptive=True)
+            sa.autotune(reps=5)
             sa.run(sta, 1e-12, 0)  # warm-up window
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -406,6 +408,7 @@ def main():
                     bt.set_m(i, torch.as_tensor(workloads.random_m(q["n"], q["Ms"], seed), dtype=torch.float32,
                                                 device=dev))
             stb = llgx.make_stepper("RK4", extrap=ex, h=5e-14)
+            bt.autotune(reps=5)
             bt.run_fixed(stb, p + 20, use_graph=True)
             torch.cuda.synchronize()
             kb_ = args.batch_steps
@@ -447,6 +450,9 @@ def main():
             sb.precompute_demag()
             with torch.cuda.stream(stream):
                 Mb32 = torch.as_tensor(Mb, dtype=torch.float32, device=dev)
+                sb.set_m(Mb32)
+            extras[f"film512_{tag}_autotune_us"] = sb.autotune(reps=3)
+            with torch.cuda.stream(stream):
                 H = sb.demag(Mb32)
                 torch.cuda.synchronize()
                 extras[f"film512_{tag}_field_err_over_Ms"] = float((H.double() - Href).abs().max().item() / big["Ms"])
