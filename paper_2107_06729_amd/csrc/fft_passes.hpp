@@ -437,6 +437,49 @@ __device__ __forceinline__ void kspace_product(cx<T>* lb, const T* kl, int ng) {
     }
 }
 
+// The same product with the kernel values of each of this thread's product
+// units loaded from global memory into registers (kr, issued early by
+// KernelRegs::load) instead of staged in LDS.
+template <typename T, int LZ, int TK, int NTH>
+struct KernelRegs {
+    static constexpr int NU = LZ * 2 * TK, PER = (NU + NTH - 1) / NTH;
+    T k[PER][6];
+    __device__ __forceinline__ void load(const T* __restrict__ kfold, int kyf, int kx0, int SX, int Kzf) {
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int e = threadIdx.x + m * NTH;
+            const int col = e % TK, t = e / TK, kz = t >> 1;
+            const int kzf = (2 * kz <= LZ) ? kz : LZ - kz;
+#pragma unroll
+            for (int comp = 0; comp < 6; ++comp) {
+                k[m][comp] = T(0);
+                if (NU % NTH == 0 || e < NU) k[m][comp] = kfold[kernel_index<T>(kyf, kx0 + col, kzf, comp, SX, Kzf)];
+            }
+        }
+    }
+    __device__ __forceinline__ void product(cx<T>* lb, int ng, T kscale) const {
+        using C = cx<T>;
+        constexpr int W = 6 * TK;
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int e = threadIdx.x + m * NTH;
+            const int col = e % TK, t = e / TK, w = t & 1, kz = t >> 1;
+            if ((NU % NTH == 0 || e < NU) && 3 * (w + 1) <= ng) {
+                const T sz = (2 * kz > LZ) ? T(-1) : T(1);
+                const T sy = w ? T(-1) : T(1);
+                const T nxx = kscale * k[m][0], nyy = kscale * k[m][1], nzz = kscale * k[m][2];
+                const T nxy = sy * (kscale * k[m][3]), nxz = sz * (kscale * k[m][4]),
+                        nyz = sy * sz * (kscale * k[m][5]);
+                C* p = lb + kz * W + w * 3 * TK + col;
+                const C mx = p[0], my = p[TK], mz = p[2 * TK];
+                p[0] = C{nxx * mx.x + nxy * my.x + nxz * mz.x, nxx * mx.y + nxy * my.y + nxz * mz.y};
+                p[TK] = C{nxy * mx.x + nyy * my.x + nyz * mz.x, nxy * mx.y + nyy * my.y + nyz * mz.y};
+                p[2 * TK] = C{nxz * mx.x + nyz * my.x + nzz * mz.x, nxz * mx.y + nyz * my.y + nzz * mz.y};
+            }
+        }
+    }
+};
+
 template <typename T, typename S, int LZ, int TK>
 __global__ __launch_bounds__(NT) void k_zmul(typename Spec<T, S>::elem* __restrict__ buf, int SX, int Kx, int nz,
                                              int nyrows, int Py, const T* __restrict__ kfold,
@@ -448,7 +491,7 @@ __global__ __launch_bounds__(NT) void k_zmul(typename Spec<T, S>::elem* __restri
     using Ff = ColFFT<T, S, L, false, TK, 6, NT>;
     using Fi = ColFFT<T, S, L, true, TK, 6, NT>;
     __shared__ C lb[LZ * 6 * TK];
-    __shared__ T kl[KZF * 6 * TK];
+    __shared__ T kl[LZ == 1 ? KZF * 6 * TK : 1];
     __shared__ C twl[L];
     const int kx0 = blockIdx.x * TK;
     const int q = blockIdx.y;  // 0 <= q <= Py/2
@@ -489,7 +532,8 @@ __global__ __launch_bounds__(NT) void k_zmul(typename Spec<T, S>::elem* __restri
         tws.fetch(tw);
         typename Ff::Regs rg;
         Ff::load_first(rg, bases, zs, nz, ncol, ng);
-        load_kernel_tile<T, TK, KZF>(kl, kfold, q, kx0, ncol, SX, kscale);
+        KernelRegs<T, LZ, TK, NT> kr;
+        kr.load(kfold, q, kx0, SX, KZF);
         tws.put(twl);
         Ff::first_to_lds(rg, lb);
         __syncthreads();
@@ -498,7 +542,7 @@ __global__ __launch_bounds__(NT) void k_zmul(typename Spec<T, S>::elem* __restri
             Ff::last_in_lds(lb, twl);
             __syncthreads();
         }
-        kspace_product<T, LZ, TK, NT>(lb, kl, ng);
+        kr.product(lb, ng, kscale);
         __syncthreads();
         Fi::first_in_lds(lb);
         if constexpr (Fi::NSTAGE > 1) {
