@@ -163,8 +163,13 @@ def summarize(stats_dir, fetch_dir, write_dir, cmd_stats, cmd_fetch, cmd_write):
         kind = _kind_of(name)
         if kind is None or name not in write:
             continue
-        fk = sum(fetch[name]) / len(fetch[name])
-        wk = sum(write[name]) / len(write[name])
+        # the autotuner launches every variant a few times: keep the
+        # instantiation the steps use (most dispatches)
+        if kind in kernels and kernels[kind]["dispatches"] >= len(fetch[name]):
+            continue
+        # median over dispatches: the steady-state steps, not the priming ones
+        fk = sorted(fetch[name])[len(fetch[name]) // 2]
+        wk = sorted(write[name])[len(write[name]) // 2]
         kernels[kind] = {"name": short(name), "dispatches": len(fetch[name]), "fetch_kib": fk, "write_kib": wk,
                          "bytes_per_launch": 1024 * (fk * fcal + wk * wcal) if fcal and wcal else None}
     traffic = {"source_sha256_16": source_hash(), "calibration": {
@@ -211,6 +216,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--variants", nargs=5, type=int, default=None,
+                    help="launch variants of the five FFT passes instead of autotuning (profiling runs)")
+    ap.add_argument("--no-b2b", action="store_true", help="skip the back-to-back pass timing (profiling runs)")
     ap.add_argument("--summarize", nargs=6, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR", "CMD_STATS",
                                                      "CMD_FETCH", "CMD_WRITE"),
                     help="write the profiles/ summaries from rocprofv3 output of this script (no GPU)")
@@ -251,8 +259,11 @@ def main():
     with torch.cuda.stream(stream):
         s32.set_m(torch.as_tensor(M0, dtype=torch.float32, device=dev))
     st32 = llgx.make_stepper("RK4", extrap=p, h=h)
-    log("autotune ...")
-    rec["autotune_us"] = s32.autotune(reps=20)
+    if args.variants:
+        s32.set_variants(args.variants)
+    else:
+        log("autotune ...")
+        rec["autotune_us"] = s32.autotune(reps=20)
     rec["autotune_variants"] = s32.variants()
     log("warmup ...")
     s32.run_fixed(st32, p + W, use_graph=True)   # p priming steps, graph capture
@@ -284,7 +295,7 @@ def main():
     # FFT passes again, each launched 50 times back to back between two HIP
     # events on the library's stream (consecutive launches overlap a little,
     # so this reads slightly below the per-launch figure)
-    b2b = s32.time_passes(reps=50)
+    b2b = {} if args.no_b2b else s32.time_passes(reps=50)
     for k, us in b2b.items():
         if k in per_kernel and us > 0:
             per_kernel[k]["avg_us_b2b"] = us
