@@ -444,7 +444,9 @@ template <typename T, int LZ, int TK, int NTH>
 struct KernelRegs {
     static constexpr int NU = LZ * 2 * TK, PER = (NU + NTH - 1) / NTH;
     T k[PER][6];
-    __device__ __forceinline__ void load(const T* __restrict__ kfold, int kyf, int kx0, int SX, int Kzf) {
+    // columns >= ncol (past Kx) load as zero: a tile may reach past the row
+    // stride SX, and past the end of kfold on the last folded ky row
+    __device__ __forceinline__ void load(const T* __restrict__ kfold, int kyf, int kx0, int ncol, int SX, int Kzf) {
 #pragma unroll
         for (int m = 0; m < PER; ++m) {
             const int e = threadIdx.x + m * NTH;
@@ -453,7 +455,8 @@ struct KernelRegs {
 #pragma unroll
             for (int comp = 0; comp < 6; ++comp) {
                 k[m][comp] = T(0);
-                if (NU % NTH == 0 || e < NU) k[m][comp] = kfold[kernel_index<T>(kyf, kx0 + col, kzf, comp, SX, Kzf)];
+                if ((NU % NTH == 0 || e < NU) && col < ncol)
+                    k[m][comp] = kfold[kernel_index<T>(kyf, kx0 + col, kzf, comp, SX, Kzf)];
             }
         }
     }
@@ -533,7 +536,7 @@ __global__ __launch_bounds__(NT) void k_zmul(typename Spec<T, S>::elem* __restri
         typename Ff::Regs rg;
         Ff::load_first(rg, bases, zs, nz, ncol, ng);
         KernelRegs<T, LZ, TK, NT> kr;
-        kr.load(kfold, q, kx0, SX, KZF);
+        kr.load(kfold, q, kx0, ncol, SX, KZF);
         tws.put(twl);
         Ff::first_to_lds(rg, lb);
         __syncthreads();
