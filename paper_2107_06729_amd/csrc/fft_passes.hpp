@@ -202,7 +202,14 @@ __global__ __launch_bounds__(NT) void k_xinv(const typename Spec<T, S>::elem* __
     __shared__ C twl[LXE];
     const long nrow = (long)ph.ny * ph.nz;
     const long N = nrow * ph.nx;
-    const long row0 = (long)blockIdx.x * ROWS;
+    // the exchange stencil of the fused H_eff reads neighbour rows: y-slab
+    // block order (xcd_run, yslab) when the row blocks tile each plane
+    long row0 = (long)blockIdx.x * ROWS;
+    if (ph.ny % ROWS == 0) {
+        int plane, yg;
+        yslab(xcd_run(blockIdx.x, gridDim.x), ph.ny / ROWS, ph.nz, plane, yg);
+        row0 = (long)plane * ph.ny + (long)yg * ROWS;
+    }
     const int b = blockIdx.y;  // sample
     spec += (long)b * 3 * nrow * SX;
     if (M) M += (long)b * 3 * N;
@@ -318,9 +325,15 @@ __global__ __launch_bounds__(NT) void k_colfft(const typename Spec<T, S>::elem* 
     using C = cx<T>;
     using F = ColFFT<T, S, L, INV, TK, 1, NT>;
     using E = typename Spec<T, S>::elem;
-    const int kx0 = blockIdx.x * TK;
-    const Base1<const E> sp{src + blockIdx.z * s_cs + blockIdx.y * s_os + kx0};
-    const Base1<E> dp{dst + blockIdx.z * d_cs + blockIdx.y * d_os + kx0};
+    // each XCD takes a contiguous run of tiles (xcd_run): when a tile row is
+    // shorter than a 128-byte line, the neighbouring tiles that share its
+    // lines are mostly fetched into the same L2
+    const int ntx = gridDim.x, nby = gridDim.y;
+    const int pos = xcd_run(blockIdx.x + ntx * (blockIdx.y + nby * blockIdx.z), ntx * nby * gridDim.z);
+    const int bx = pos % ntx, by = (pos / ntx) % nby, bz = pos / (ntx * nby);
+    const int kx0 = bx * TK;
+    const Base1<const E> sp{src + bz * s_cs + by * s_os + kx0};
+    const Base1<E> dp{dst + bz * d_cs + by * d_os + kx0};
     typename F::Regs rg;
     if constexpr (F::NSTAGE == 1) {
         F::load_first(rg, sp, s_is, n_in, Kx - kx0, 1);
@@ -444,20 +457,21 @@ template <typename T, int LZ, int TK, int NTH>
 struct KernelRegs {
     static constexpr int NU = LZ * 2 * TK, PER = (NU + NTH - 1) / NTH;
     T k[PER][6];
-    // columns >= ncol (past Kx) load as zero: a tile may reach past the row
-    // stride SX, and past the end of kfold on the last folded ky row
+    // A tile may reach past Kx, past the row stride SX, and on the last
+    // folded ky row past the end of kfold: columns >= ncol read column Kx - 1
+    // instead (and units past NU the last unit), so every load stays in
+    // bounds and is issued unconditionally, its value first needed by
+    // product().  Those columns are never stored.
     __device__ __forceinline__ void load(const T* __restrict__ kfold, int kyf, int kx0, int ncol, int SX, int Kzf) {
 #pragma unroll
         for (int m = 0; m < PER; ++m) {
-            const int e = threadIdx.x + m * NTH;
+            const int e0 = threadIdx.x + m * NTH;
+            const int e = (NU % NTH == 0 || e0 < NU) ? e0 : NU - 1;
             const int col = e % TK, t = e / TK, kz = t >> 1;
             const int kzf = (2 * kz <= LZ) ? kz : LZ - kz;
+            const int kx = kx0 + (col < ncol ? col : ncol - 1);
 #pragma unroll
-            for (int comp = 0; comp < 6; ++comp) {
-                k[m][comp] = T(0);
-                if ((NU % NTH == 0 || e < NU) && col < ncol)
-                    k[m][comp] = kfold[kernel_index<T>(kyf, kx0 + col, kzf, comp, SX, Kzf)];
-            }
+            for (int comp = 0; comp < 6; ++comp) k[m][comp] = kfold[kernel_index<T>(kyf, kx, kzf, comp, SX, Kzf)];
         }
     }
     __device__ __forceinline__ void product(cx<T>* lb, int ng, T kscale) const {

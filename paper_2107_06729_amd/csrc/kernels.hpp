@@ -53,6 +53,30 @@ __device__ __forceinline__ int xcd_run(int b, int nblk) {
     return x * q + (x < r ? x : r) + i;
 }
 
+// Order of the row blocks of the stencil kernels: the run of positions that
+// xcd_run gives one XCD is a range of y-groups over all planes (z and
+// samples), not a range of planes, so the stencil's z neighbours come from
+// the same XCD's L2 and only the rows at the two ends of a y range are
+// fetched by two XCDs.  Maps position p to (plane, y-group) for gy y-groups
+// per plane, y fastest within a range; a bijection on [0, gy * planes).
+__device__ __forceinline__ void yslab(int p, int gy, int planes, int& plane, int& yg) {
+    const int q = gy >> 3, r = gy & 7;  // ranges 0..r-1 hold q + 1 groups, the rest q
+    const int big = planes * (q + 1);
+    int c, o, g;
+    if (p < r * big) {
+        c = p / big;
+        o = p - c * big;
+        g = q + 1;
+    } else {  // only reached when q > 0
+        const int small = planes * q, pp = p - r * big;
+        c = r + pp / small;
+        o = pp - (c - r) * small;
+        g = q;
+    }
+    plane = o / g;
+    yg = c * q + (c < r ? c : r) + (o - plane * g);
+}
+
 // Eq. (3): M = M0 + sum_k cb[k] f[k] (cb = h c_k) and, when err is set, the
 // per-cell estimate |sum_k ce[k] f[k]| (ce = h (c_k - c^_k)) over the union of
 // the stage derivatives either sum uses.

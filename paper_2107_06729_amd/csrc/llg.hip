@@ -131,15 +131,15 @@ template <typename T>
 __device__ __forceinline__ CellIdx cell_index(const Phys<T>& ph) {
     CellIdx c;
     c.x = blockIdx.y * blockDim.x + threadIdx.x;
-    const int row = xcd_run(blockIdx.x, gridDim.x) * blockDim.y + threadIdx.y;
-    const int rows = ph.ny * ph.nz;
-    c.ok = c.x < ph.nx && row < rows * ph.nb;
-    c.b = row / rows;
-    const int rl = row - c.b * rows;
-    c.y = rl % ph.ny;
-    c.z = rl / ph.ny;
-    c.cell = (long)rl * ph.nx + c.x;
-    c.off = (long)c.b * 3 * ((long)rows * ph.nx);
+    const int gy = (ph.ny + blockDim.y - 1) / blockDim.y;
+    int plane, yg;
+    yslab(xcd_run(blockIdx.x, gridDim.x), gy, ph.nz * ph.nb, plane, yg);
+    c.y = yg * blockDim.y + threadIdx.y;
+    c.ok = c.x < ph.nx && c.y < ph.ny;
+    c.b = plane / ph.nz;
+    c.z = plane - c.b * ph.nz;
+    c.cell = ((long)c.z * ph.ny + c.y) * ph.nx + c.x;
+    c.off = (long)c.b * 3 * ((long)ph.ny * ph.nz * ph.nx);
     return c;
 }
 
@@ -400,10 +400,11 @@ CellGrid cell_grid(int nx, int ny, int nz, int nb) {
     int tx = 1;
     while (tx < nx && tx < 64) tx <<= 1;
     const int ry = NTS / tx;
-    const long rows = (long)ny * nz * nb;
+    // row blocks never straddle two planes (ny % ry idle rows per plane)
+    const long groups = (long)((ny + ry - 1) / ry) * nz * nb;
     CellGrid g;
     g.block = dim3((unsigned)tx, (unsigned)ry, 1);
-    g.grid = dim3((unsigned)((rows + ry - 1) / ry), (unsigned)((nx + tx - 1) / tx), 1);
+    g.grid = dim3((unsigned)groups, (unsigned)((nx + tx - 1) / tx), 1);
     g.nblocks = (long)g.grid.x * g.grid.y;
     return g;
 }
