@@ -1280,6 +1280,12 @@ struct Batch {
     hipStream_t stream = nullptr;
     std::string err;
     std::map<std::vector<GraphKey>, hipGraphExec_t> graphs;
+    // groups 1.. get streams of their own (default priority) inside a captured
+    // step, forked from and joined back into `stream`, so meshes of different
+    // shapes run side by side
+    std::vector<hipStream_t> gstreams;
+    std::vector<hipEvent_t> joins;
+    hipEvent_t fork = nullptr;
 };
 
 static bool same_material(const llgx_problem& a, const llgx_problem& b) {
@@ -1348,10 +1354,42 @@ static llgx_status batch_run_fixed(Batch* bt, const llgx_stepper* s, int64_t nst
                 return LLGX_E_HIP;
             }
             llgx_status st = LLGX_OK;
-            for (size_t g = 0; g < bt->groups.size() && st == LLGX_OK; ++g) {
-                st = enqueue_attempt<T>(bt->groups[g], plans[g]);
-                if (st) bt->err = bt->groups[g]->err;
+            const size_t ng = bt->groups.size();
+            if (ng > 1 && bt->gstreams.empty()) {
+                hipError_t e = hipEventCreateWithFlags(&bt->fork, hipEventDisableTiming);
+                for (size_t g = 1; g < ng && e == hipSuccess; ++g) {
+                    hipStream_t gs = nullptr;
+                    hipEvent_t je = nullptr;
+                    e = hipStreamCreateWithFlags(&gs, hipStreamNonBlocking);
+                    if (e == hipSuccess) bt->gstreams.push_back(gs);
+                    if (e == hipSuccess) e = hipEventCreateWithFlags(&je, hipEventDisableTiming);
+                    if (e == hipSuccess) bt->joins.push_back(je);
+                }
+                if (e != hipSuccess) st = LLGX_E_HIP, bt->err = "stream creation failed";
             }
+            if (st == LLGX_OK && ng > 1 && hipEventRecord(bt->fork, bt->stream) != hipSuccess)
+                st = LLGX_E_HIP, bt->err = "event record failed";
+            for (size_t g = 0; g < ng && st == LLGX_OK; ++g) {
+                Ctx* c = bt->groups[g];
+                if (g > 0) {
+                    if (hipStreamWaitEvent(bt->gstreams[g - 1], bt->fork, 0) != hipSuccess) {
+                        st = LLGX_E_HIP;
+                        bt->err = "stream wait failed";
+                        break;
+                    }
+                    c->stream = bt->gstreams[g - 1];
+                }
+                st = enqueue_attempt<T>(c, plans[g]);
+                if (st) bt->err = c->err;
+                if (g > 0) {
+                    if (st == LLGX_OK && hipEventRecord(bt->joins[g - 1], c->stream) != hipSuccess)
+                        st = LLGX_E_HIP, bt->err = "event record failed";
+                    c->stream = bt->stream;
+                }
+            }
+            for (size_t g = 1; g < ng && st == LLGX_OK; ++g)
+                if (hipStreamWaitEvent(bt->stream, bt->joins[g - 1], 0) != hipSuccess)
+                    st = LLGX_E_HIP, bt->err = "stream wait failed";
             hipError_t e2 = hipStreamEndCapture(bt->stream, &gr);
             if (st) return st;
             if (e2 != hipSuccess) {
@@ -1453,6 +1491,9 @@ void llgx_batch_destroy(llgx_batch b) {
     Batch* bt = (Batch*)b;
     (void)hipStreamSynchronize(bt->stream);
     for (auto& kv : bt->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto e : bt->joins) (void)hipEventDestroy(e);
+    if (bt->fork) (void)hipEventDestroy(bt->fork);
+    for (auto st : bt->gstreams) (void)hipStreamDestroy(st);
     for (Ctx* c : bt->groups) {
         release(c);
         delete c;
