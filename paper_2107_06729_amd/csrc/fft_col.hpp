@@ -36,6 +36,14 @@ struct Base1 {
     __device__ __forceinline__ E* operator()(int) const { return p; }
 };
 
+// Element offset j * gs of a unit's first transform row j < L/2, in one
+// 24-bit multiply.  Exact when gs < 2^24 and (L/2) gs < 2^32, which the
+// launchers check (rows along y: L <= 2048 at stride SX <= 1040; along z:
+// L <= 1024 at stride Py SX <= 2048 * 1040).  The unit's other rows add
+// uniform offsets.
+__device__ __forceinline__ unsigned row_off(int j, long gs) { return __umul24((unsigned)j, (unsigned)gs); }
+inline bool row_off_ok(int L, long gs) { return gs >= 0 && gs < (1L << 24) && (long)(L / 2) * gs < (1L << 32); }
+
 template <typename T, typename S, int L, bool INV, int TK, int NG, int NT>
 struct ColFFT {
     using C = cx<T>;
@@ -74,12 +82,12 @@ struct ColFFT {
             const int u = threadIdx.x + m * NT;
             const Unit t = unit(u);
             const bool on = (NU0 % NT == 0 || u < NU0) && t.g < ng && t.p * PN < ncol;
-            const E* gp = bases(t.g) + t.p * PN;
+            const E* gp = bases(t.g) + t.p * PN + row_off(t.j, gs);
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
                 const int row = t.j + r * (L / R0);
                 rg.v[m][r].raw = {};
-                if (on && row < n_in) rg.v[m][r].raw = *(const RW*)(gp + row * gs);
+                if (on && row < n_in) rg.v[m][r].raw = *(const RW*)(gp + (long)(r * (L / R0)) * gs);
             }
         }
     }
@@ -226,7 +234,7 @@ struct ColFFT {
                 C x[PN][8];
                 last_regs(buf, tw, t, x);
                 if (t.g < ng && t.p * PN < ncol) {
-                    E* gp = bases(t.g) + t.p * PN;
+                    E* gp = bases(t.g) + t.p * PN + row_off(t.j, gs);
 #pragma unroll
                     for (int r = 0; r < 8; ++r) {
                         const int row = t.j + r * NS;
@@ -235,7 +243,7 @@ struct ColFFT {
 #pragma unroll
                             for (int q = 0; q < PN; ++q)
                                 o.e[q] = Spec<T, S>::put(C{x[q][r].x * scale, x[q][r].y * scale});
-                            *(RW*)(gp + row * gs) = o.raw;
+                            *(RW*)(gp + (long)(r * NS) * gs) = o.raw;
                         }
                     }
                 }

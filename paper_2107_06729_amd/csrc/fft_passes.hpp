@@ -171,16 +171,20 @@ __global__ __launch_bounds__(NT) void k_xfwd(Combo<T> in, T* __restrict__ mk_out
         F::first_to_lds(v, buf);
         __syncthreads();
         F::rest(buf, twl);
-        for (int e = threadIdx.x; e < ROWS * (LX + 1); e += NT) {
-            const int r = e / (LX + 1), k = e - r * (LX + 1);
+        // X[k] for k < LX; the lane of k = 0 also writes X[LX], which takes
+        // the same z_0 (LX - k and k both wrap to 0)
+        for (int e = threadIdx.x; e < ROWS * LX; e += NT) {
+            const int r = e / LX, k = e & (LX - 1);
             const long g = row0 + r;
             if (g >= nrows) continue;
             const C* rb = buf + r * F::RS;
-            const C zk = rb[F::P(k & (LX - 1))];
+            const C zk = rb[F::P(k)];
             const C zc = cconj(rb[F::P((LX - k) & (LX - 1))]);
             const C E{(zk.x + zc.x) * T(0.5), (zk.y + zc.y) * T(0.5)};
             const C O{(zk.y - zc.y) * T(0.5), (zc.x - zk.x) * T(0.5)};  // -i (zk - zc)/2
-            spec[g * SX + k] = Spec<T, S>::put(cadd(E, cmul(O, twp[k])));
+            typename Spec<T, S>::elem* out = spec + g * SX;
+            out[k] = Spec<T, S>::put(cadd(E, cmul(O, twp[k])));
+            if (k == 0) out[LX] = Spec<T, S>::put(cadd(E, cmul(O, twp[LX])));
         }
     }
 }
@@ -205,10 +209,13 @@ __global__ __launch_bounds__(NT) void k_xinv(const typename Spec<T, S>::elem* __
     // the exchange stencil of the fused H_eff reads neighbour rows: y-slab
     // block order (xcd_run, yslab) when the row blocks tile each plane
     long row0 = (long)blockIdx.x * ROWS;
-    if (ph.ny % ROWS == 0) {
-        int plane, yg;
+    const bool tiled = ph.ny % ROWS == 0;
+    int plane = 0, y0 = 0;  // z and first y of the block's rows when tiled
+    if (tiled) {
+        int yg;
         yslab(xcd_run(blockIdx.x, gridDim.x), ph.ny / ROWS, ph.nz, plane, yg);
-        row0 = (long)plane * ph.ny + (long)yg * ROWS;
+        y0 = yg * ROWS;
+        row0 = (long)plane * ph.ny + y0;
     }
     const int b = blockIdx.y;  // sample
     spec += (long)b * 3 * nrow * SX;
@@ -241,7 +248,9 @@ __global__ __launch_bounds__(NT) void k_xinv(const typename Spec<T, S>::elem* __
                 xb[m][q] = C{T(0), T(0)};
                 wk[m][q] = twP[k];
                 if (F::live0(u) && g < nrow) {
-                    const typename Spec<T, S>::elem* row = spec + (c * nrow + g) * SX;
+                    // (c nrow + g) < 3 ny nz <= 3 * 2^19 and SX <= 1040: exact in 32 bits
+                    const typename Spec<T, S>::elem* row =
+                        spec + __umul24((unsigned)(c * (int)nrow + (int)g), (unsigned)SX);
                     xa[m][q] = Spec<T, S>::get(row[k]);
                     xb[m][q] = Spec<T, S>::get(row[LX - k]);
                 }
@@ -264,8 +273,12 @@ __global__ __launch_bounds__(NT) void k_xinv(const typename Spec<T, S>::elem* __
         F::rest(buf, twl);
     }
     const int nx = ph.nx;
+    const float rnx = 1.0f / (float)nx;
     for (int e = threadIdx.x; e < ROWS * nx; e += NT) {
-        const int r = e / nx, x = e - r * nx;
+        // e / nx through a float reciprocal: (e + 1/2) / nx lies at least
+        // 1/(2 nx) >= 2^-12 from an integer, and the rounding error is below
+        // 2^-22 (e < 2^15, nx <= 2^10)
+        const int r = (int)(((float)e + 0.5f) * rnx), x = e - (int)__umul24((unsigned)r, (unsigned)nx);
         const long g = row0 + r;
         if (g >= nrow) continue;
         T hd[3];
@@ -280,7 +293,7 @@ __global__ __launch_bounds__(NT) void k_xinv(const typename Spec<T, S>::elem* __
 #pragma unroll
             for (int c = 0; c < 3; ++c) H[c * N + cell] = hd[c];
         } else {
-            const int y = (int)(g % ph.ny), z = (int)(g / ph.ny);
+            const int y = tiled ? y0 + r : (int)g % ph.ny, z = tiled ? plane : (int)g / ph.ny;
             T m[3], H[3];
             heff_at(PtrField<T>{M}, N, cell, x, y, z, b, ph, hd, m, H);
             if constexpr (MODE == XINV_HEFF) {
@@ -365,13 +378,16 @@ template <typename E>
 struct ZBases {
     E* row0;  // (ky = q, component 0, z = 0, kx0)
     E* row1;  // (ky = Py - q, ...)
-    long cs;
-    __device__ __forceinline__ E* operator()(int g) const { return (g >= 3 ? row1 : row0) + (g % 3) * cs; }
+    unsigned cs;  // component stride nz * nyrows * SX (< 2^31 for every supported mesh)
+    __device__ __forceinline__ E* operator()(int g) const {
+        const int c = g >= 3 ? g - 3 : g;
+        return (g >= 3 ? row1 : row0) + (c == 0 ? 0u : c == 1 ? cs : 2u * cs);
+    }
 };
 
 // folded kernel values of columns kx0 .. kx0+TK-1 of row kyf, loaded into
-// registers by load() and written to LDS kl[(kzf * 6 + comp) * TK + col],
-// times kscale, by put(); columns >= ncol read as zero
+// registers by load() and written to LDS kl[(kzf * 6 + comp) * TK + col] by
+// put(); columns >= ncol read as zero
 template <typename T, int TK, int KZF>
 struct KernelTile {
     static constexpr int KB = 16 / (int)sizeof(T);
@@ -399,7 +415,7 @@ struct KernelTile {
             }
         }
     }
-    __device__ __forceinline__ void put(T* kl, T kscale) const {
+    __device__ __forceinline__ void put(T* kl) const {
 #pragma unroll
         for (int m = 0; m < PER; ++m) {
             const int e = threadIdx.x + m * NT;
@@ -408,10 +424,10 @@ struct KernelTile {
                     const int b = e / (KZF * 6), rem = e - b * (KZF * 6);
                     const T* v = (const T*)&r[m];
 #pragma unroll
-                    for (int i = 0; i < KB; ++i) kl[rem * TK + b * KB + i] = kscale * v[i];
+                    for (int i = 0; i < KB; ++i) kl[rem * TK + b * KB + i] = v[i];
                 }
             } else {
-                if (NE % NT == 0 || e < NE) kl[e] = kscale * r[m];
+                if (NE % NT == 0 || e < NE) kl[e] = r[m];
             }
         }
     }
@@ -419,10 +435,10 @@ struct KernelTile {
 
 template <typename T, int TK, int KZF>
 __device__ __forceinline__ void load_kernel_tile(T* kl, const T* __restrict__ kfold, int kyf, int kx0, int ncol,
-                                                 int SX, T kscale) {
+                                                 int SX) {
     KernelTile<T, TK, KZF> kt;
     kt.load(kfold, kyf, kx0, ncol, SX);
-    kt.put(kl, kscale);
+    kt.put(kl);
 }
 
 // H = K M on LDS rows: row kz, groups (w, c), TK columns
@@ -451,11 +467,16 @@ __device__ __forceinline__ void kspace_product(cx<T>* lb, const T* kl, int ng) {
 }
 
 // The same product with the kernel values of each of this thread's product
-// units loaded from global memory into registers (kr, issued early by
-// KernelRegs::load) instead of staged in LDS.
+// units loaded from global memory into registers (issued early by
+// KernelRegs::load) instead of staged in LDS.  A unit is one (column, kz):
+// it applies the tensor to row ky = q (groups 0..2) and, when the tile holds
+// it, to row ky = Py - q (groups 3..5), whose xy and yz components change
+// sign; so the six values are loaded once for both rows and the ky sign is a
+// negated operand.
 template <typename T, int LZ, int TK, int NTH>
 struct KernelRegs {
-    static constexpr int NU = LZ * 2 * TK, PER = (NU + NTH - 1) / NTH;
+    static constexpr int NU = LZ * TK, PER = (NU + NTH - 1) / NTH;
+    static constexpr int KB = 16 / (int)sizeof(T);
     T k[PER][6];
     // A tile may reach past Kx, past the row stride SX, and on the last
     // folded ky row past the end of kfold: columns >= ncol read column Kx - 1
@@ -463,35 +484,37 @@ struct KernelRegs {
     // bounds and is issued unconditionally, its value first needed by
     // product().  Those columns are never stored.
     __device__ __forceinline__ void load(const T* __restrict__ kfold, int kyf, int kx0, int ncol, int SX, int Kzf) {
+        const T* __restrict__ kb = kfold + kernel_row(kyf, SX, Kzf);  // uniform
 #pragma unroll
         for (int m = 0; m < PER; ++m) {
             const int e0 = threadIdx.x + m * NTH;
             const int e = (NU % NTH == 0 || e0 < NU) ? e0 : NU - 1;
-            const int col = e % TK, t = e / TK, kz = t >> 1;
+            const int col = e % TK, kz = e / TK;
             const int kzf = (2 * kz <= LZ) ? kz : LZ - kz;
-            const int kx = kx0 + (col < ncol ? col : ncol - 1);
+            const int off = kernel_off<T>(kx0 + (col < ncol ? col : ncol - 1), kzf, 0, Kzf);
 #pragma unroll
-            for (int comp = 0; comp < 6; ++comp) k[m][comp] = kfold[kernel_index<T>(kyf, kx, kzf, comp, SX, Kzf)];
+            for (int comp = 0; comp < 6; ++comp) k[m][comp] = kb[off + comp * KB];
         }
     }
-    __device__ __forceinline__ void product(cx<T>* lb, int ng, T kscale) const {
+    static __device__ __forceinline__ void apply(cx<T>* p, T nxx, T nyy, T nzz, T nxy, T nxz, T nyz) {
         using C = cx<T>;
+        const C mx = p[0], my = p[TK], mz = p[2 * TK];
+        p[0] = C{nxx * mx.x + nxy * my.x + nxz * mz.x, nxx * mx.y + nxy * my.y + nxz * mz.y};
+        p[TK] = C{nxy * mx.x + nyy * my.x + nyz * mz.x, nxy * mx.y + nyy * my.y + nyz * mz.y};
+        p[2 * TK] = C{nxz * mx.x + nyz * my.x + nzz * mz.x, nxz * mx.y + nyz * my.y + nzz * mz.y};
+    }
+    __device__ __forceinline__ void product(cx<T>* lb, int ng) const {
         constexpr int W = 6 * TK;
 #pragma unroll
         for (int m = 0; m < PER; ++m) {
             const int e = threadIdx.x + m * NTH;
-            const int col = e % TK, t = e / TK, w = t & 1, kz = t >> 1;
-            if ((NU % NTH == 0 || e < NU) && 3 * (w + 1) <= ng) {
-                const T sz = (2 * kz > LZ) ? T(-1) : T(1);
-                const T sy = w ? T(-1) : T(1);
-                const T nxx = kscale * k[m][0], nyy = kscale * k[m][1], nzz = kscale * k[m][2];
-                const T nxy = sy * (kscale * k[m][3]), nxz = sz * (kscale * k[m][4]),
-                        nyz = sy * sz * (kscale * k[m][5]);
-                C* p = lb + kz * W + w * 3 * TK + col;
-                const C mx = p[0], my = p[TK], mz = p[2 * TK];
-                p[0] = C{nxx * mx.x + nxy * my.x + nxz * mz.x, nxx * mx.y + nxy * my.y + nxz * mz.y};
-                p[TK] = C{nxy * mx.x + nyy * my.x + nyz * mz.x, nxy * mx.y + nyy * my.y + nyz * mz.y};
-                p[2 * TK] = C{nxz * mx.x + nyz * my.x + nzz * mz.x, nxz * mx.y + nyz * my.y + nzz * mz.y};
+            if (NU % NTH == 0 || e < NU) {
+                const int col = e % TK, kz = e / TK;
+                const bool zneg = 2 * kz > LZ;  // the xz and yz components change sign
+                const T nxz = zneg ? -k[m][4] : k[m][4], nyz = zneg ? -k[m][5] : k[m][5];
+                cx<T>* p = lb + kz * W + col;
+                apply(p, k[m][0], k[m][1], k[m][2], k[m][3], nxz, nyz);
+                if (ng == 6) apply(p + 3 * TK, k[m][0], k[m][1], k[m][2], -k[m][3], nxz, -nyz);
             }
         }
     }
@@ -500,7 +523,7 @@ struct KernelRegs {
 template <typename T, typename S, int LZ, int TK>
 __global__ __launch_bounds__(NT) void k_zmul(typename Spec<T, S>::elem* __restrict__ buf, int SX, int Kx, int nz,
                                              int nyrows, int Py, const T* __restrict__ kfold,
-                                             const cx<T>* __restrict__ tw, T kscale) {
+                                             const cx<T>* __restrict__ tw) {
     using C = cx<T>;
     using E = typename Spec<T, S>::elem;
     constexpr int L = LZ > 1 ? LZ : 2;  // LZ = 1 uses no transform
@@ -516,7 +539,7 @@ __global__ __launch_bounds__(NT) void k_zmul(typename Spec<T, S>::elem* __restri
     const int ncol = Kx - kx0;
     const long cs = (long)nz * nyrows * SX, zs = (long)nyrows * SX;
     E* sb = buf + (long)blockIdx.z * 3 * cs;  // sample
-    const ZBases<E> bases{sb + (long)q * SX + kx0, sb + (long)(Py - q) * SX + kx0, cs};
+    const ZBases<E> bases{sb + (long)q * SX + kx0, sb + (long)(Py - q) * SX + kx0, (unsigned)cs};
     if constexpr (LZ == 1) {
         // no z transform: load the 6 x TK values, multiply, store
         using PU = typename Ff::PU;
@@ -531,7 +554,7 @@ __global__ __launch_bounds__(NT) void k_zmul(typename Spec<T, S>::elem* __restri
                 for (int i = 0; i < PN; ++i) lb[g * TK + p * PN + i] = Spec<T, S>::get(v.e[i]);
             }
         }
-        load_kernel_tile<T, TK, KZF>(kl, kfold, q, kx0, ncol, SX, kscale);
+        load_kernel_tile<T, TK, KZF>(kl, kfold, q, kx0, ncol, SX);
         __syncthreads();
         kspace_product<T, 1, TK, NT>(lb, kl, ng);
         __syncthreads();
@@ -559,7 +582,7 @@ __global__ __launch_bounds__(NT) void k_zmul(typename Spec<T, S>::elem* __restri
             Ff::last_in_lds(lb, twl);
             __syncthreads();
         }
-        kr.product(lb, ng, kscale);
+        kr.product(lb, ng);
         __syncthreads();
         Fi::first_in_lds(lb);
         if constexpr (Fi::NSTAGE > 1) {

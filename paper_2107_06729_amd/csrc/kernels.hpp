@@ -120,9 +120,9 @@ struct XinvOut {
 // Host-side launchers of the FFT passes (pass_x.hip, pass_col.hip, pass_z.hip)
 // and of the tensor setup (newell.hip).  All lengths are powers of two.  Spectra
 // are passed untyped (SpecPtr) and stored as S: the working precision T, or
-// _Float16 / __bf16 pairs for T = float.  fscale, scale, kscale and hscale
-// multiply the x-pass input, the y-pass output, the k-space kernel and the
-// final field (all 1 for storage in the working precision).
+// _Float16 / __bf16 pairs for T = float.  fscale, scale and hscale multiply
+// the x-pass input, the y-pass output and the final field (all 1 for storage
+// in the working precision); the folded k-space kernel carries its own scale.
 using SpecPtr = void*;
 template <typename T, typename S>
 hipError_t launch_xfwd(hipStream_t s, int LX, const Combo<T>& in, T* mk_out, int nin, long nrows, SpecPtr spec,
@@ -136,7 +136,7 @@ hipError_t launch_colfft(hipStream_t s, int L, bool inv, SpecPtr src, long s_cs,
                          const cx<T>* tw, T scale, int variant);
 template <typename T, typename S>
 hipError_t launch_zmul(hipStream_t s, int LZ, SpecPtr buf, int SX, int Kx, int nz, int nyrows, int Py, int Pz,
-                       const T* kfold, int Kyf, int Kzf, const cx<T>* tw, int nb, T kscale, int variant);
+                       const T* kfold, int Kyf, int Kzf, const cx<T>* tw, int nb, int variant);
 hipError_t launch_newell_octant(hipStream_t s, int nx, int ny, int nz, double dx, double dy, double dz,
                                 double* octant);
 hipError_t launch_scatter_tensor(hipStream_t s, const double* octant, int comp, int nx, int ny, int nz,
@@ -148,10 +148,17 @@ hipError_t launch_fold(hipStream_t s, const cx<double>* spec, int SX, int Kx, in
 // Folded k-space kernel layout: blocks of KB = 16 / sizeof(T) adjacent kx,
 // each block holding all (kz, component) values of one ky, so the z pass
 // reads a tile's kernel values as contiguous 16-byte packs.
+// kernel_index = kernel_row (start of the ky row, 64-bit) + kernel_off (within
+// the row, < 6 Kzf SX, 32-bit).
+__host__ __device__ __forceinline__ long kernel_row(int kyf, int SX, int Kzf) { return (long)kyf * SX * Kzf * 6; }
+template <typename T>
+__host__ __device__ __forceinline__ int kernel_off(int kx, int kzf, int comp, int Kzf) {
+    constexpr int KB = 16 / (int)sizeof(T);
+    return (((kx / KB) * Kzf + kzf) * 6 + comp) * KB + kx % KB;
+}
 template <typename T>
 __host__ __device__ __forceinline__ long kernel_index(int kyf, int kx, int kzf, int comp, int SX, int Kzf) {
-    constexpr int KB = 16 / (int)sizeof(T);
-    return ((((long)kyf * (SX / KB) + kx / KB) * Kzf + kzf) * 6 + comp) * KB + kx % KB;
+    return kernel_row(kyf, SX, Kzf) + kernel_off<T>(kx, kzf, comp, Kzf);
 }
 
 // Launch variants per FFT pass (bit-identical results, different tiles).

@@ -178,16 +178,19 @@ __global__ __launch_bounds__(NTS) void k_stage(Combo<T> mk, Extrap<T> ex, Phys<T
     const long N = (long)ph.nx * ph.ny * ph.nz;
     const CellIdx ci = cell_index(ph);
     if (!ci.ok) return;
+    // M0 of the chained output is loaded with the stencil, not after it
+    T m0[3] = {T(0), T(0), T(0)};
+    if (nx.mnext) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) m0[c] = nx.m0[ci.off + c * N + ci.cell];
+    }
     T m[3], f[3];
     stage_rhs<T, NC>(mk, ex, ph, ci, N, m, f);
 #pragma unroll
     for (int c = 0; c < 3; ++c) F[ci.off + c * N + ci.cell] = f[c];
     if (nx.mnext) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const long i = ci.off + c * N + ci.cell;
-            nx.mnext[i] = nx.m0[i] + nx.cnext * f[c];
-        }
+        for (int c = 0; c < 3; ++c) nx.mnext[ci.off + c * N + ci.cell] = m0[c] + nx.cnext * f[c];
     }
 }
 
@@ -204,8 +207,7 @@ __global__ __launch_bounds__(NTS) void k_stage_final(Combo<T> mk, Extrap<T> ex, 
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
     double emax = 0.0;
     if (ci.ok) {
-        T m[3], fS[3];
-        stage_rhs<T, NC>(mk, ex, ph, ci, N, m, fS);
+        // M0 and the stored stage derivatives are loaded with the stencil
         T m0[3], f[NF > 1 ? NF - 1 : 1][3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) m0[c] = M0[ci.off + c * N + ci.cell];
@@ -213,6 +215,8 @@ __global__ __launch_bounds__(NTS) void k_stage_final(Combo<T> mk, Extrap<T> ex, 
         for (int k = 0; k < NF - 1; ++k)
 #pragma unroll
             for (int c = 0; c < 3; ++c) f[k][c] = fs.f[k][ci.off + c * N + ci.cell];
+        T m[3], fS[3];
+        stage_rhs<T, NC>(mk, ex, ph, ci, N, m, fS);
         double e2 = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {

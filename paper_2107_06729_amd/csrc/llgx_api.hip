@@ -295,12 +295,11 @@ static llgx_status run_pass(Ctx* c, int kind, const EvalArgs<T>& a) {
             break;
         }
         case LLGX_K_ZMUL: {
-            const T kscale = native ? T(1) : (T)((double)c->Px * c->Py);
             void* work = c->Py > 1 ? B : A;
             const int nyrows = c->Py > 1 ? c->Py : c->ny;
             HIPCHK(c, (launch_zmul<T, S>(s, c->Pz, work, c->SX, c->Kx, c->nz, nyrows, c->Py, c->Pz,
                                          (const T*)c->kfold, c->Kyf, c->Kzf, table<T>(c, c->Pz, false), c->nb,
-                                         kscale, c->var[kind])));
+                                         c->var[kind])));
             break;
         }
         case LLGX_K_YINV:
@@ -398,7 +397,11 @@ static llgx_status kernel_from_octant_or_real(Ctx* c, const std::vector<double>*
         st = make_table<double>(c, c->tw_f64, L);
         if (st) return st;
     }
-    const double scale = -1.0 / ((double)c->Px * c->Py * c->Pz);
+    // K^ = -N^ / (Px Py Pz); with 16-bit spectra (scaled by 1/(Px Py) in the x
+    // and y passes) the kernel also carries Px Py, a power of two, so the
+    // fold's rounding is unchanged
+    const bool native_spec = c->spectral == LLGX_SPEC_NATIVE;
+    const double scale = native_spec ? -1.0 / ((double)c->Px * c->Py * c->Pz) : -1.0 / (double)c->Pz;
     std::vector<double> hreal;
     for (int comp = 0; comp < 6; ++comp) {
         if (full_host) {

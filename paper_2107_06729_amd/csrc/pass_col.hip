@@ -12,6 +12,7 @@ hipError_t launch_colfft(hipStream_t s, int L, bool inv, SpecPtr src, long s_cs,
     const E* sp = (const E*)src;
     E* dp = (E*)dst;
     if (variant < 0 || variant >= NVAR_COL) return hipErrorInvalidValue;
+    if (!row_off_ok(L, s_is) || !row_off_ok(L, d_is)) return hipErrorInvalidValue;
 #define CF_T(LL, TK)                                                                                             \
     {                                                                                                            \
         dim3 g((unsigned)((Kx + TK - 1) / TK), (unsigned)nouter, (unsigned)ncomp);                               \

@@ -6,17 +6,19 @@ namespace llgx {
 
 template <typename T, typename S>
 hipError_t launch_zmul(hipStream_t s, int LZ, SpecPtr buf, int SX, int Kx, int nz, int nyrows, int Py, int Pz,
-                       const T* kfold, int Kyf, int Kzf, const cx<T>* tw, int nb, T kscale, int variant) {
+                       const T* kfold, int Kyf, int Kzf, const cx<T>* tw, int nb, int variant) {
     using E = typename Spec<T, S>::elem;
     E* bp = (E*)buf;
     (void)Pz;
     (void)Kyf;
     (void)Kzf;
     if (variant < 0 || variant >= NVAR_ZMUL) return hipErrorInvalidValue;
+    // 32-bit row and component offsets (ColFFT row_off, ZBases)
+    if (!row_off_ok(LZ, (long)nyrows * SX) || (long)nz * nyrows * SX >= (1L << 31)) return hipErrorInvalidValue;
 #define ZM_T(LL, TK)                                                                                \
     {                                                                                               \
         dim3 g((unsigned)((Kx + TK - 1) / TK), (unsigned)(Py / 2 + 1), (unsigned)nb);               \
-        k_zmul<T, S, LL, TK><<<g, NT, 0, s>>>(bp, SX, Kx, nz, nyrows, Py, kfold, tw, kscale);         \
+        k_zmul<T, S, LL, TK><<<g, NT, 0, s>>>(bp, SX, Kx, nz, nyrows, Py, kfold, tw);                 \
     }
 #define ZM(LL)                                          \
     case LL: {                                          \
@@ -44,7 +46,7 @@ hipError_t launch_zmul(hipStream_t s, int LZ, SpecPtr buf, int SX, int Kx, int n
 
 #define INST_TS(T, S)                                                                                         \
     template hipError_t launch_zmul<T, S>(hipStream_t, int, SpecPtr, int, int, int, int, int, int, const T*, int,  \
-                                          int, const cx<T>*, int, T, int);
+                                          int, const cx<T>*, int, int);
 INST_TS(float, float)
 INST_TS(float, _Float16)
 INST_TS(float, __bf16)

@@ -30,41 +30,45 @@ struct ComboField {
     }
 };
 
-// neighbour at flat offset d of cell (components at c N + cell + d), or the
-// cell itself where it is missing: outside the mesh (inside = false) or
-// empty (M = 0, no magnetic material) -- a free surface either way
-template <typename T, typename Fld>
-__device__ __forceinline__ void neighbour(const Fld& M, long N, long cell, long d, bool inside, bool masked,
-                                          const T m[3], T v[3]) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) v[c] = inside ? M(c * N + cell + d) : m[c];
-    if (masked && v[0] * v[0] + v[1] * v[1] + v[2] * v[2] == T(0)) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) v[c] = m[c];
-    }
-}
-
-// M reads the sample's own [3][N] block; b is the sample index (applied field)
+// M reads the sample's own [3][N] block; b is the sample index (applied
+// field).  A missing neighbour, outside the mesh or empty (M = 0, no magnetic
+// material), is replaced by the cell itself: a free surface either way.  All
+// 21 values are loaded unconditionally (a neighbour outside the mesh reads the
+// cell itself, in bounds), so a wave issues them back to back; the empty-cell
+// test follows, only on meshes that have empty cells.
 template <typename T, typename Fld>
 __device__ __forceinline__ void heff_at(const Fld& M, long N, long cell, int x, int y, int z, int b,
                                         const Phys<T>& ph, const T hd[3], T m[3], T H[3]) {
     const T* ha = ph.hab ? ph.hab + 3 * b : ph.ha;
-    const long sy = ph.nx, sz = (long)ph.nx * ph.ny;
+    const int sy = ph.nx, sz = ph.nx * ph.ny;
+    const int d[7] = {0,
+                      x > 0 ? -1 : 0,
+                      x + 1 < ph.nx ? 1 : 0,
+                      y > 0 ? -sy : 0,
+                      y + 1 < ph.ny ? sy : 0,
+                      z > 0 ? -sz : 0,
+                      z + 1 < ph.nz ? sz : 0};
+    T v[7][3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) m[c] = M(c * N + cell);
-    const bool masked = *ph.empty != 0;  // uniform: the mesh has empty cells
-    T xm[3], xp[3], ym[3], yp[3], zm[3], zp[3];
-    neighbour<T>(M, N, cell, -1, x > 0, masked, m, xm);
-    neighbour<T>(M, N, cell, 1, x + 1 < ph.nx, masked, m, xp);
-    neighbour<T>(M, N, cell, -sy, y > 0, masked, m, ym);
-    neighbour<T>(M, N, cell, sy, y + 1 < ph.ny, masked, m, yp);
-    neighbour<T>(M, N, cell, -sz, z > 0, masked, m, zm);
-    neighbour<T>(M, N, cell, sz, z + 1 < ph.nz, masked, m, zp);
+    for (int k = 0; k < 7; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[k][c] = M(c * N + cell + d[k]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) m[c] = v[0][c];
+    if (*ph.empty != 0) {  // uniform: the mesh has empty cells
+#pragma unroll
+        for (int k = 1; k < 7; ++k) {
+            if (v[k][0] * v[k][0] + v[k][1] * v[k][1] + v[k][2] * v[k][2] == T(0)) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[k][c] = m[c];
+            }
+        }
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const T mc = m[c];
-        H[c] = hd[c] + ha[c] + ph.exx * ((xm[c] + xp[c]) - T(2) * mc) + ph.exy * ((ym[c] + yp[c]) - T(2) * mc) +
-               ph.exz * ((zm[c] + zp[c]) - T(2) * mc);
+        H[c] = hd[c] + ha[c] + ph.exx * ((v[1][c] + v[2][c]) - T(2) * mc) +
+               ph.exy * ((v[3][c] + v[4][c]) - T(2) * mc) + ph.exz * ((v[5][c] + v[6][c]) - T(2) * mc);
     }
     const T mu = m[0] * ph.u[0] + m[1] * ph.u[1] + m[2] * ph.u[2];
 #pragma unroll
