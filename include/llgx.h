@@ -220,6 +220,8 @@ llgx_status llgx_profile_read(llgx_handle h, double ms[LLGX_K_COUNT], int64_t la
  * llgx_time_passes: the same measurement for the current variants only.
  * llgx_get_variants / llgx_set_variants: read or force the choice
  * (LLGX_E_ARG for an index out of range).
+ * llgx_variant_counts: number of variants of each pass (n[5], host memory);
+ * no handle needed, never fails for a non-null n.
  * llgx_tune_export: the process-wide table as JSON lines
  *   {"key": "f32/native/256x256x16/1", "variant": [v0..v4], "us": [t0..t4]}
  * with the same size protocol as llgx_save_state (buf NULL: size only,
@@ -229,6 +231,7 @@ llgx_status llgx_profile_read(llgx_handle h, double ms[LLGX_K_COUNT], int64_t la
 llgx_status llgx_autotune(llgx_handle h, int32_t reps, double us_out[5]);
 llgx_status llgx_time_passes(llgx_handle h, int32_t reps, double us_out[5]);
 llgx_status llgx_get_variants(llgx_handle h, int32_t v[5]);
+llgx_status llgx_variant_counts(int32_t n[5]);
 llgx_status llgx_set_variants(llgx_handle h, const int32_t v[5]);
 llgx_status llgx_tune_export(char* buf, size_t cap, size_t* used);
 llgx_status llgx_tune_import(const char* text);

@@ -85,6 +85,7 @@ _sig = {
     "llgx_autotune": (_S, [_H, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "llgx_time_passes": (_S, [_H, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "llgx_get_variants": (_S, [_H, ctypes.POINTER(ctypes.c_int32)]),
+    "llgx_variant_counts": (_S, [ctypes.POINTER(ctypes.c_int32)]),
     "llgx_set_variants": (_S, [_H, ctypes.POINTER(ctypes.c_int32)]),
     "llgx_tune_export": (_S, [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
     "llgx_tune_import": (_S, [ctypes.c_char_p]),
@@ -336,6 +337,15 @@ class Sim:
         blob = bytes(blob)
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(_lib.llgx_load_state(self._h, buf, len(blob)), self._h)
+
+
+def variant_counts():
+    """Launch variants of each FFT pass (x fwd, y fwd, z, y inv, x inv)."""
+    n = (ctypes.c_int32 * 5)()
+    code = _lib.llgx_variant_counts(n)
+    if code != OK:
+        raise LlgxError(code, "llgx_variant_counts")
+    return list(n)
 
 
 def tune_export():

@@ -1784,6 +1784,12 @@ llgx_status llgx_time_passes(llgx_handle h, int32_t reps, double us_out[5]) {
     return LLGX_OK;
 }
 
+llgx_status llgx_variant_counts(int32_t n[5]) {
+    if (!n) return LLGX_E_ARG;
+    for (int k = 0; k < 5; ++k) n[k] = kNumVar[k];
+    return LLGX_OK;
+}
+
 llgx_status llgx_get_variants(llgx_handle h, int32_t v[5]) {
     if (!h || !v) return LLGX_E_ARG;
     Ctx* c = (Ctx*)h;

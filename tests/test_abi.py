@@ -46,3 +46,11 @@ def test_defaults_and_argument_errors_without_gpu():
     assert llgx._lib.llgx_create(ctypes.byref(ok), 7, 0, None, ctypes.byref(h)) == llgx.E_ARG
     big = llgx.make_problem({"n": (4096, 2, 2), "cell": (1e-9,) * 3, "Ms": 8e5, "A": 1e-11, "alpha": 0.02})
     assert llgx._lib.llgx_create(ctypes.byref(big), llgx.F32, 0, None, ctypes.byref(h)) == llgx.E_UNSUPPORTED
+
+
+def test_variant_counts_without_gpu():
+    import paper_2107_06729_amd as llgx
+    n = llgx.variant_counts()
+    assert len(n) == 5 and all(k >= 1 for k in n)
+    assert n[1] == n[3]  # the y forward and y inverse share one column pass
+    assert llgx._lib.llgx_variant_counts(None) == llgx.E_ARG
