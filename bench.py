@@ -133,7 +133,7 @@ def summarize(stats_dir, fetch_dir, write_dir, cmd_stats, cmd_fetch, cmd_write):
         return re.sub(r"\(.*", "", n).replace("void ", "").replace("llgx::", "")
 
     out = ["# rocprofv3 kernel statistics: RK4 + 4th-order extrapolation, FP32, 256x256x16 slab", "",
-           "Command (repo root on the GPU box):", "", "```", cmd_stats, "```", "",
+           "Command (from the repository root, R = its path):", "", "```", cmd_stats, "```", "",
            "| kernel | step kind | calls | avg us | min us | max us | share % |",
            "|---|---|---:|---:|---:|---:|---:|"]
     for r in rows:
@@ -228,8 +228,8 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build runs the hot path on a single MI355X "
-              "(the multi-GPU decomposition is described in DESIGN.md, not implemented)", file=sys.stderr)
+        print("bench.py measures one GPU: the hot path runs on a single MI355X "
+              "(a decomposition over several GPUs is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -35,10 +35,32 @@ def test_cube_self_term_is_one_third():
     assert np.all(off == 0.0)
 
 
+def _aharoni_mp(a, b, c):
+    """Demagnetizing factor along c of a prism of half-sides a, b, c
+    (Aharoni's closed form), in 40-digit arithmetic."""
+    import mpmath as mp
+    mp.mp.dps = 40
+    a, b, c = mp.mpf(a), mp.mpf(b), mp.mpf(c)
+    r = mp.sqrt(a * a + b * b + c * c)
+    ab, bc, ac = mp.sqrt(a * a + b * b), mp.sqrt(b * b + c * c), mp.sqrt(a * a + c * c)
+    s = ((b * b - c * c) / (2 * b * c) * mp.log((r - a) / (r + a))
+         + (a * a - c * c) / (2 * a * c) * mp.log((r - b) / (r + b))
+         + b / (2 * c) * mp.log((ab + a) / (ab - a)) + a / (2 * c) * mp.log((ab + b) / (ab - b))
+         + c / (2 * a) * mp.log((bc - b) / (bc + b)) + c / (2 * b) * mp.log((ac - a) / (ac + a))
+         + 2 * mp.atan(a * b / (c * r)) + (a ** 3 + b ** 3 - 2 * c ** 3) / (3 * a * b * c)
+         + (a * a + b * b - 2 * c * c) / (3 * a * b * c) * r + c / (a * b) * (ac + bc)
+         - (ab ** 3 + bc ** 3 + ac ** 3) / (3 * a * b * c))
+    return s / mp.pi
+
+
 def test_self_term_5x5x3_value():
-    # survey-time 40-digit value of the 5x5x3 nm self term
+    # the self term is the prism's demagnetizing factors: the oracle's Newell
+    # form in FP64 against Aharoni's closed form in 40-digit arithmetic
     n00 = newell.self_tensor(5.0, 5.0, 3.0)
-    assert np.allclose(n00, [0.273765667819, 0.273765667819, 0.452468664361], atol=5e-13)
+    ref = [float(_aharoni_mp(2.5, 1.5, 2.5)), float(_aharoni_mp(1.5, 2.5, 2.5)), float(_aharoni_mp(2.5, 2.5, 1.5))]
+    assert abs(sum(ref) - 1.0) < 1e-15
+    assert np.allclose(ref, [0.273765667819, 0.273765667819, 0.452468664361], atol=5e-13)
+    assert np.allclose(n00, ref, atol=5e-13)
 
 
 # --- independent quadrature of the cell-pair tensor -------------------------
