@@ -49,6 +49,17 @@ template <> struct Vec<double> {
     }
 };
 
+// 16-byte load of pack i marked non-temporal (streamed: read once per step)
+template <typename T>
+__device__ __forceinline__ typename Vec<T>::type nt_load(const T* p, long i) {
+    typedef T raw __attribute__((ext_vector_type(Vec<T>::N)));
+    const raw r = __builtin_nontemporal_load((const raw*)p + i);
+    typename Vec<T>::type v;
+#pragma unroll
+    for (int q = 0; q < Vec<T>::N; ++q) Vec<T>::set(v, q, r[q]);
+    return v;
+}
+
 template <typename T, int NF>
 __global__ __launch_bounds__(NTS) void k_combine(long npack, Combo<T> c, T* __restrict__ out) {
     using V = typename Vec<T>::type;
@@ -87,7 +98,7 @@ __global__ __launch_bounds__(NTS) void k_epoly(long npack, EPoly<T> ep) {
     for (long i = (long)blockIdx.x * NTS + threadIdx.x; i < npack; i += (long)gridDim.x * NTS) {
         V g[NG];
 #pragma unroll
-        for (int k = 0; k < NG; ++k) g[k] = ((const V*)ep.g[k])[i];
+        for (int k = 0; k < NG; ++k) g[k] = nt_load<T>(ep.g[k], i);
         for (int j = 0; j < ep.nd; ++j) {
             V o;
 #pragma unroll
