@@ -95,20 +95,30 @@ template <typename T, int NG>
 __global__ __launch_bounds__(NTS) void k_epoly(long npack, EPoly<T> ep) {
     using V = typename Vec<T>::type;
     constexpr int VN = Vec<T>::N;
-    for (long i = (long)blockIdx.x * NTS + threadIdx.x; i < npack; i += (long)gridDim.x * NTS) {
-        V g[NG];
+    // two packs per thread, i and i + stride, their loads issued together
+    const long stride = (long)gridDim.x * NTS;
+    for (long i0 = (long)blockIdx.x * NTS + threadIdx.x; i0 < npack; i0 += 2 * stride) {
+        const bool two = i0 + stride < npack;
+        V g[2][NG];
 #pragma unroll
-        for (int k = 0; k < NG; ++k) g[k] = nt_load<T>(ep.g[k], i);
+        for (int k = 0; k < NG; ++k) {
+            g[0][k] = nt_load<T>(ep.g[k], i0);
+            if (two) g[1][k] = nt_load<T>(ep.g[k], i0 + stride);
+        }
         for (int j = 0; j < ep.nd; ++j) {
-            V o;
 #pragma unroll
-            for (int q = 0; q < VN; ++q) {
-                T v = T(0);
+            for (int h = 0; h < 2; ++h) {
+                if (h == 1 && !two) break;
+                V o;
 #pragma unroll
-                for (int k = 0; k < NG; ++k) v += ep.w[j][k] * Vec<T>::get(g[k], q);
-                Vec<T>::set(o, q, v);
+                for (int q = 0; q < VN; ++q) {
+                    T v = T(0);
+#pragma unroll
+                    for (int k = 0; k < NG; ++k) v += ep.w[j][k] * Vec<T>::get(g[h][k], q);
+                    Vec<T>::set(o, q, v);
+                }
+                ((V*)ep.out[j])[i0 + h * stride] = o;
             }
-            ((V*)ep.out[j])[i] = o;
         }
     }
 }
@@ -454,7 +464,7 @@ hipError_t launch_epoly(hipStream_t s, long n, const EPoly<T>& ep) {
     for (int k = 0; k < ep.ng; ++k) vec = vec && aligned16(ep.g[k]);
     for (int j = 0; j < ep.nd; ++j) vec = vec && aligned16(ep.out[j]);
     const long np = vec ? n / VN : n;
-    const unsigned g = grid_for(np);
+    const unsigned g = grid_for(vec ? (np + 1) / 2 : np);  // the vector kernel takes two packs a thread
     switch (ep.ng) {
 #define EP(K)                                               \
     case K:                                                 \
