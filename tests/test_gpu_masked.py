@@ -63,3 +63,34 @@ def test_masked_steps_fp64(method, extrap):
         got = to_host(s.get_m())
         assert np.max(np.abs(got - ora.M)) <= 1e-12 * p["Ms"], (k, np.max(np.abs(got - ora.M)))
         assert np.all(got[:, mask == 0] == 0.0)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_all_empty_mesh(prec):
+    """The degenerate mesh with no magnetic material (M = 0 everywhere):
+    no demagnetizing or exchange field (H_eff is the applied field, as in the
+    oracle), F = 0, and fixed and adaptive steps, with and without
+    renormalisation, leave M exactly zero."""
+    import paper_2107_06729_amd as llgx
+    log(f"all-empty mesh {prec}")
+    p = dict(workloads.CHECKERBOARD_60x60x1)
+    p["n"] = (20, 16, 3)
+    n = p["n"]
+    M = np.zeros((3,) + n[::-1])
+    Nf = newell.tensor_full(n, p["cell"])
+    it = integrate.Integrator(p, M, method="RK4", Nfull=Nf)
+    Hd = it.demag(M)
+    H = fields.effective_field(M, Hd, it.pa)
+    s = sim(p, prec, tensor=Nf)
+    Md = to_dev(M, prec)
+    assert np.all(to_host(s.demag(Md)) == 0.0)
+    assert np.allclose(to_host(s.heff(Md)), H, rtol=1e-6 if prec == "f32" else 1e-14, atol=0)
+    assert np.all(to_host(s.rhs(Md)) == 0.0)
+    for st in (llgx.make_stepper("RK4", extrap=4, h=5e-14),
+               llgx.make_stepper("RK4", extrap=4, h=5e-14, renormalize=True),
+               llgx.make_stepper("RKDP54", extrap="matched", h=5e-14, adaptive=True)):
+        s.set_m(Md)
+        for _ in range(7):
+            s.step(st)
+        assert np.all(to_host(s.get_m()) == 0.0)
+    s.close()
