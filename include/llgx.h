@@ -40,7 +40,7 @@ typedef int32_t llgx_status;
 #define LLGX_E_HIP (-3)         /* HIP runtime failure (message has details)  */
 #define LLGX_E_NONFINITE (-4)   /* NaN/Inf in the error norm of a step        */
 #define LLGX_E_OOM (-5)         /* device allocation failed                   */
-#define LLGX_E_UNSUPPORTED (-6) /* valid request this build does not provide  */
+#define LLGX_E_UNSUPPORTED (-6) /* valid request the library does not provide */
 
 #define LLGX_F64 0 /* fields, FFTs and stages in double                       */
 #define LLGX_F32 1 /* fields, FFTs and stages in float (error norm in double) */

@@ -22,8 +22,8 @@ come from the Cartesian recurrence (obtained from r^2 = x.x by Leibniz' rule)
 |k| r^2 a_k = -(2|k|-1) sum_i x_i a_{k-e_i} - (|k|-1) sum_i a_{k-2e_i}.
 
 The switch between the two forms (``R >= R_SWITCH * max(dx,dy,dz)`` uses the
-expansion) and its order ``K_ORDER`` are a reading of this build, not of the
-paper, chosen so that each form is used where its float64 error is ~1e-10
+expansion) and its order ``K_ORDER`` are this implementation's reading, not the
+paper's, chosen so that each form is used where its float64 error is ~1e-10
 of V/(4 pi R^3) or better.
 
 Pins (tests/test_oracle_newell.py): self term vs Aharoni's closed-form prism
