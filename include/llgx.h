@@ -90,6 +90,8 @@ typedef struct {
     int32_t adaptive;      /* 1: Eq. (5) controller (embedded pairs only)      */
     int32_t renormalize;   /* 1: rescale |M| to Ms after every accepted step   */
     int32_t exponent_mode; /* Eq. (5) exponent: 0 -> 1/(min(n,n^)+1), 1 -> 1/(n+1) */
+    int32_t report_dmdt;   /* 1: llgx_step fills info->max_dmdt (one more pass
+                              over dM/dt and a synchronisation per step)     */
     double h;              /* step (fixed) or first trial step (adaptive), s   */
     double h_min, h_max, c_min, c_max, e_max;
 } llgx_stepper;
@@ -103,6 +105,13 @@ typedef struct {
     int32_t exact_evals;   /* Eq. (2) evaluations in this step                  */
     int32_t extrap_evals;  /* Eq. (6) evaluations in this step                  */
     int32_t forced;        /* 1 if accepted at h_min with err > e_max           */
+    double max_dmdt;       /* max over cells of |dM/dt| / Ms (1/s) at the state
+                              the step started from: the first stage's
+                              derivative, Eq. (1) with the exact field of
+                              Eq. (2); a diagnostic (e.g. a relaxation test),
+                              not part of the paper's method.  Filled by
+                              llgx_step when the stepper's report_dmdt is set,
+                              else -1 */
 } llgx_step_info;
 
 typedef struct llgx_ctx* llgx_handle;
@@ -166,13 +175,14 @@ llgx_status llgx_rhs(llgx_handle h, const void* M_dev, void* F_dev);
  * s->adaptive the Eq. (5) controller repeats rejected attempts and the next
  * call starts from info->h_next; otherwise s->h is used.  A change of method
  * or extrap between calls restarts priming.  Synchronises once per attempt
- * when adaptive (to read e), else not at all.  Errors: LLGX_E_ARG,
+ * when adaptive (to read e), and once more with s->report_dmdt and info
+ * given (to read max_dmdt); else not at all.  Errors: LLGX_E_ARG,
  * LLGX_E_STATE, LLGX_E_NONFINITE, LLGX_E_HIP. */
 llgx_status llgx_step(llgx_handle h, const llgx_stepper* s, llgx_step_info* info);
 
 /* nsteps fixed steps (s->adaptive must be 0) with no host synchronisation;
  * with use_graph the steady-state step is captured once per history phase
- * into HIP graphs and replayed.  info may be NULL. */
+ * into HIP graphs and replayed.  info may be NULL; its max_dmdt is -1. */
 llgx_status llgx_run_fixed(llgx_handle h, const llgx_stepper* s, int64_t nsteps, int32_t use_graph,
                            llgx_step_info* info);
 

@@ -19,7 +19,10 @@ Pins (tests/test_oracle_fields.py): uniform M has zero exchange field;
 cos(pi m (i+1/2)/n) patterns are eigenvectors of the Neumann Laplacian with
 eigenvalue -(2-2cos(pi m/n))/d^2; M.F = 0; the LL form satisfies Eq. (1)
 (substituted back) at random states; the energy decreases along damped
-trajectories (tests/test_oracle_integrate.py).
+trajectories (tests/test_oracle_integrate.py); max_dmdt of one cube cell
+equals gamma |m x H_a| / sqrt(1 + alpha^2), the length of the LL form when
+the field is H_a plus a part parallel to M (a cube's self field is -M/3),
+and of a mesh the largest of the per-cell values.
 """
 
 import math
@@ -94,6 +97,13 @@ def llg_rhs(M, H, Ms, alpha, gamma):
     gp = gamma / (1.0 + alpha * alpha)
     mxh = cross(M, H)
     return -gp * mxh - (gp * alpha / Ms) * cross(M, mxh)
+
+
+def max_dmdt(F, Ms):
+    """max over cells of |dM/dt| / Ms (1/s), the fastest turning rate of
+    m = M/Ms: a diagnostic of a step, not part of the paper's method."""
+    F = np.asarray(F, dtype=np.float64).reshape(3, -1)
+    return float(np.sqrt(np.sum(F * F, axis=0)).max() / Ms)
 
 
 def energy(M, Hd, pa):

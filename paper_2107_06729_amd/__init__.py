@@ -42,7 +42,7 @@ class Problem(ctypes.Structure):
 
 class Stepper(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("extrap", ctypes.c_int32), ("adaptive", ctypes.c_int32),
-                ("renormalize", ctypes.c_int32), ("exponent_mode", ctypes.c_int32),
+                ("renormalize", ctypes.c_int32), ("exponent_mode", ctypes.c_int32), ("report_dmdt", ctypes.c_int32),
                 ("h", ctypes.c_double), ("h_min", ctypes.c_double), ("h_max", ctypes.c_double),
                 ("c_min", ctypes.c_double), ("c_max", ctypes.c_double), ("e_max", ctypes.c_double)]
 
@@ -50,7 +50,7 @@ class Stepper(ctypes.Structure):
 class StepInfo(ctypes.Structure):
     _fields_ = [("t", ctypes.c_double), ("h_used", ctypes.c_double), ("h_next", ctypes.c_double),
                 ("err", ctypes.c_double), ("rejected", ctypes.c_int32), ("exact_evals", ctypes.c_int32),
-                ("extrap_evals", ctypes.c_int32), ("forced", ctypes.c_int32)]
+                ("extrap_evals", ctypes.c_int32), ("forced", ctypes.c_int32), ("max_dmdt", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -141,7 +141,8 @@ def stepper_defaults():
     return s
 
 
-def make_stepper(method="RK4", extrap=None, h=1e-13, adaptive=False, renormalize=False, exponent_mode=0, **kw):
+def make_stepper(method="RK4", extrap=None, h=1e-13, adaptive=False, renormalize=False, exponent_mode=0,
+                 report_dmdt=False, **kw):
     s = stepper_defaults()
     s.method = METHODS[method] if isinstance(method, str) else int(method)
     if extrap is None:
@@ -154,6 +155,7 @@ def make_stepper(method="RK4", extrap=None, h=1e-13, adaptive=False, renormalize
     s.adaptive = int(bool(adaptive))
     s.renormalize = int(bool(renormalize))
     s.exponent_mode = int(exponent_mode)
+    s.report_dmdt = int(bool(report_dmdt))
     for k, v in kw.items():
         setattr(s, k, float(v))
     return s

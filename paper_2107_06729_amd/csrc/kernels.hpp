@@ -195,6 +195,9 @@ template <typename T>
 hipError_t launch_final(hipStream_t s, long ncell, int nb, const T* base, const Final<T>& fs, double inv_ms, T* mnew,
                         double* parts, int nparts);
 hipError_t launch_reduce_max(hipStream_t s, const double* parts, int nparts, double* out);
+// per-block partials (nparts blocks) of max over cells |v| / Ms, for launch_reduce_max
+template <typename T>
+hipError_t launch_max_norm(hipStream_t s, long ncell, int nb, const T* v, double inv_ms, double* parts, int nparts);
 // flag = 1 if any of the n cells ([nb][3][ncell] layout) has M = 0 (flag is
 // not cleared here)
 template <typename T>

@@ -333,6 +333,35 @@ __global__ __launch_bounds__(NTS) void k_reduce_max(const double* __restrict__ p
     if (threadIdx.x == 0) out[0] = red[0];
 }
 
+__device__ __forceinline__ double nan_max(double a, double b) { return (a != a || b != b) ? a + b : fmax(a, b); }
+
+// Per-block partials of max over cells of |v| / Ms for a vector field v
+// ([nb][3][ncell]; the |dM/dt| diagnostic of a step).  Each wavefront
+// reduces its 64 lanes with cross-lane shuffles, then the block's waves are
+// combined through LDS; NaN propagates.  k_reduce_max finishes the partials.
+template <typename T>
+__global__ __launch_bounds__(NTS) void k_max_norm(long ncell, int nb, const T* __restrict__ v, double inv_ms,
+                                                  double* __restrict__ parts) {
+    __shared__ double wv[NTS / 64];
+    double mx = 0.0;
+    for (long ic = (long)blockIdx.x * NTS + threadIdx.x; ic < ncell * nb; ic += (long)gridDim.x * NTS) {
+        const long b = ic / ncell, cell = ic - b * ncell;
+        const T* p = v + b * 3 * ncell + cell;
+        const double x = p[0], y = p[ncell], z = p[2 * ncell];
+        mx = nan_max(mx, sqrt(x * x + y * y + z * z) * inv_ms);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = nan_max(mx, __shfl_xor(mx, off, 64));
+    if ((threadIdx.x & 63) == 0) wv[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = wv[0];
+#pragma unroll
+        for (int w = 1; w < NTS / 64; ++w) r = nan_max(r, wv[w]);
+        parts[blockIdx.x] = r;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(NTS) void k_renorm(long ncell, int nb, T* __restrict__ M, double Ms) {
     for (long ic = (long)blockIdx.x * NTS + threadIdx.x; ic < ncell * nb; ic += (long)gridDim.x * NTS) {
@@ -539,6 +568,12 @@ hipError_t launch_reduce_max(hipStream_t s, const double* parts, int nparts, dou
 }
 
 template <typename T>
+hipError_t launch_max_norm(hipStream_t s, long ncell, int nb, const T* v, double inv_ms, double* parts, int nparts) {
+    k_max_norm<T><<<(unsigned)nparts, NTS, 0, s>>>(ncell, nb, v, inv_ms, parts);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_renorm(hipStream_t s, long ncell, int nb, T* M, double Ms) {
     k_renorm<T><<<grid_for(ncell * nb), NTS, 0, s>>>(ncell, nb, M, Ms);
     return hipGetLastError();
@@ -578,6 +613,7 @@ hipError_t launch_cast(hipStream_t s, long n, const double* src, T* dst) {
     template hipError_t launch_final<T>(hipStream_t, long, int, const T*, const Final<T>&, double, T*, double*,  \
                                         int);                                                                    \
     template hipError_t launch_renorm<T>(hipStream_t, long, int, T*, double);                                    \
+    template hipError_t launch_max_norm<T>(hipStream_t, long, int, const T*, double, double*, int);              \
     template hipError_t launch_detect_empty<T>(hipStream_t, long, int, const T*, int*);                          \
     template hipError_t launch_mean<T>(hipStream_t, long, const T*, double*, int);                               \
     template hipError_t launch_cast<T>(hipStream_t, long, const double*, T*);

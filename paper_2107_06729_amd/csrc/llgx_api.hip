@@ -676,6 +676,24 @@ static llgx_status check_stepper(Ctx* c, const llgx_stepper* s, const Tableau** 
     return LLGX_OK;
 }
 
+// max over cells of |dM/dt| / Ms of the derivative in F[0] (the first
+// stage's, at the state the step starts from), read back to the host
+template <typename T>
+static llgx_status read_max_dmdt(Ctx* c, double* out) {
+    {
+        PROF(LLGX_K_OTHER);
+        HIPCHK(c, launch_max_norm<T>(c->stream, c->ncell, c->nb, (const T*)c->F[0], 1.0 / c->p.Ms, c->parts,
+                                     c->nparts));
+    }
+    {
+        PROF(LLGX_K_OTHER);
+        HIPCHK(c, launch_reduce_max(c->stream, c->parts, c->nparts, c->scal + 4));
+    }
+    HIPCHK(c, hipMemcpyAsync(out, c->scal + 4, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LLGX_OK;
+}
+
 // One accepted ABM2 step (PECE, ref. [32]):
 //   P: M_p = M_n + h ((1 + r/2) F_n - (r/2) F_{n-1}), r = h / h_{n-1}
 //      (M_n + h F_n, Heun's predictor, when no F_{n-1} is held)
@@ -802,7 +820,12 @@ static llgx_status do_step_abm(Ctx* c, const llgx_stepper* s, int p, llgx_step_i
         h_next = std::min(std::max(h * cf, s->h_min), s->h_max);
         break;
     }
-    // accept
+    // accept; F[0] still holds F_n at (t_n, M_n)
+    double dmdt = -1.0;
+    if (s->report_dmdt && info) {
+        llgx_status st = read_max_dmdt<T>(c, &dmdt);
+        if (st) return st;
+    }
     if (p > 0) {
         c->hist.push_back({c->t, c->abm_slot});
         while ((int)c->hist.size() > p) c->hist.erase(c->hist.begin());
@@ -835,6 +858,7 @@ static llgx_status do_step_abm(Ctx* c, const llgx_stepper* s, int p, llgx_step_i
         info->exact_evals = (int)(c->n_exact - ex0);
         info->extrap_evals = (int)(c->n_extrap - xt0);
         info->forced = forced;
+        info->max_dmdt = dmdt;
     }
     return LLGX_OK;
 }
@@ -892,6 +916,12 @@ static llgx_status do_step(Ctx* c, const llgx_stepper* s, llgx_step_info* info) 
         h_next = std::min(std::max(h * cf, s->h_min), s->h_max);
         break;
     }
+    // F[0] holds the first stage's derivative at (t, M0) until commit
+    double dmdt = -1.0;
+    if (s->report_dmdt && info) {
+        st = read_max_dmdt<T>(c, &dmdt);
+        if (st) return st;
+    }
     st = commit<T>(c, pl, h);
     if (st) return st;
     if (s->renormalize) {
@@ -910,6 +940,7 @@ static llgx_status do_step(Ctx* c, const llgx_stepper* s, llgx_step_info* info) 
         info->exact_evals = (int)(c->n_exact - ex0);
         info->extrap_evals = (int)(c->n_extrap - xt0);
         info->forced = forced;
+        info->max_dmdt = dmdt;
     }
     return LLGX_OK;
 }
@@ -917,6 +948,13 @@ static llgx_status do_step(Ctx* c, const llgx_stepper* s, llgx_step_info* info) 
 template <typename T>
 static llgx_status do_run_fixed(Ctx* c, const llgx_stepper* s, int64_t nsteps, int use_graph, llgx_step_info* info) {
     if (s && s->adaptive) return c->fail(LLGX_E_ARG, "llgx_run_fixed needs a fixed step (adaptive = 0)");
+    // no per-step synchronisation: the |dM/dt| diagnostic is not reported
+    llgx_stepper sf{};
+    if (s) {
+        sf = *s;
+        sf.report_dmdt = 0;
+        s = &sf;
+    }
     for (int64_t i = 0; i < nsteps; ++i) {
         const Tableau* tab;
         int p;
@@ -980,6 +1018,7 @@ static llgx_status do_run_fixed(Ctx* c, const llgx_stepper* s, int64_t nsteps, i
             info->exact_evals = 1 + (pl.extrap ? 0 : tab->S - 1);
             info->extrap_evals = pl.extrap ? tab->S - 1 : 0;
             info->forced = 0;
+            info->max_dmdt = -1.0;
         }
     }
     return LLGX_OK;
@@ -1007,6 +1046,7 @@ static llgx_status do_run(Ctx* c, const llgx_stepper* s, double t_end, double sa
         return LLGX_OK;
     };
     llgx_stepper sc = *s;
+    sc.report_dmdt = 0;  // steps report nothing to the caller here
     llgx_status st = LLGX_OK;
     double next_s = 0.0;
     if (sample_dt > 0) {

@@ -54,3 +54,38 @@ def test_variant_counts_without_gpu():
     assert len(n) == 5 and all(k >= 1 for k in n)
     assert n[1] == n[3]  # the y forward and y inverse share one column pass
     assert llgx._lib.llgx_variant_counts(None) == llgx.E_ARG
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every field of the three structs the binding passes by pointer has the
+    offset and the struct the size that a C compiler gives them from
+    include/llgx.h."""
+    import shutil
+    import subprocess
+    import paper_2107_06729_amd as llgx
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"llgx_problem": llgx.Problem, "llgx_stepper": llgx.Stepper, "llgx_step_info": llgx.StepInfo}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "llgx.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {(a, b): int(c) for a, b, c in (l.split() for l in out if l)}
+    for cname, py in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+    # and the C structs have no fields the binding lacks
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    for cname, py in structs.items():
+        body = re.search(r"typedef struct \{([^{}]*)\}\s*" + cname + ";", text).group(1)
+        names = re.findall(r"(\w+)(?:\[\d+\])?\s*[,;]", body)
+        assert sorted(names) == sorted(f for f, _ in py._fields_), cname

@@ -213,3 +213,36 @@ def test_benchmark_configuration_against_oracle():
     c = s.counters()
     assert (c["exact"], c["extrap"]) == (ora.stats["exact"], ora.stats["extrap"])
     s.close()
+
+
+@pytest.mark.parametrize("prec,method,extrap", [("f64", "RK4", None), ("f64", "RKDP54", None), ("f64", "ABM2", None),
+                                                ("f64", "RK4", 4), ("f32", "RK4", 4), ("f32", "RKF45", None)])
+def test_max_dmdt_against_oracle(prec, method, extrap):
+    """max_dmdt of each step is max over cells |F(t, M)| / Ms at the state the
+    step started from (first stages, FSAL reuse, priming and extrapolated
+    steps, ABM2's F_n): the oracle's F at that state, within 1e-12 (FP64) or
+    1e-5 (FP32) of the bound of |F|/Ms.  Without report_dmdt, and from
+    llgx_run_fixed, it is -1."""
+    from oracle import fields
+    log(f"max_dmdt {prec} {method} {extrap}")
+    p = film(N_SMALL, CELL_SMALL)
+    Nf = newell.tensor_full(N_SMALL, CELL_SMALL)
+    M0 = workloads.random_m(N_SMALL, p["Ms"], 35)
+    if prec == "f32":
+        M0 = f32_round(M0)
+    ora = integrate.Integrator(p, M0, method="RK4", h=1e-14, Nfull=Nf)  # its fields only
+    pa = ora.pa
+    gp = pa["gamma"] / (1 + pa["alpha"] ** 2)
+    s = sim(p, prec, tensor=Nf)
+    s.set_m(to_dev(M0, prec))
+    st = _stepper(method, extrap, 1e-14, report_dmdt=True)
+    for k in range(7):
+        M = to_host(s.get_m())
+        Hd = ora.demag(M)
+        want = fields.max_dmdt(ora.rhs(M, Hd), p["Ms"])
+        bound = gp * np.max(np.abs(fields.effective_field(M, Hd, pa))) * (1 + pa["alpha"])
+        info = s.step(st)
+        tol = (1e-12 if prec == "f64" else 1e-5) * bound
+        assert abs(info["max_dmdt"] - want) <= tol, (k, info["max_dmdt"], want)
+    assert s.step(_stepper(method, extrap, 1e-14))["max_dmdt"] == -1.0
+    assert s.run_fixed(st, 2)["max_dmdt"] == -1.0

@@ -100,3 +100,27 @@ def test_empty_cells_stay_empty():
     assert np.max(np.abs(nrm[mask == 1] / p["Ms"] - 1)) < 1e-14
     R = fields.renormalized(np.array([[[[0.0, 3.0]]], [[[0.0, 4.0]]], [[[0.0, 0.0]]]]), 10.0)
     assert R[:, 0, 0, 0].tolist() == [0.0, 0.0, 0.0] and R[:, 0, 0, 1].tolist() == [6.0, 8.0, 0.0]
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.02, 0.5])
+def test_max_dmdt_of_one_cube_cell_closed_form(alpha):
+    # one cube cell: the demagnetizing field -M/3 is parallel to M and
+    # exchange vanishes, so m turns at gamma |m x H_a| / sqrt(1 + alpha^2)
+    from oracle import integrate
+    Ha = np.array([2e4, -1e4, 5e3])
+    p = workloads.problem((1, 1, 1), (5e-9,) * 3, 8e5, 1.3e-11, alpha, Ha=tuple(Ha))
+    m = np.array([0.6, 0.0, 0.8])
+    M0 = (p["Ms"] * m).reshape(3, 1, 1, 1)
+    it = integrate.Integrator(p, M0, method="RK4", h=1e-13)
+    Hd = it.demag(M0)
+    assert np.allclose(Hd.reshape(3), -M0.reshape(3) / 3.0, rtol=1e-12, atol=0)
+    F = it.rhs(M0, Hd)
+    want = p["gamma"] * np.linalg.norm(np.cross(m, Ha)) / math.sqrt(1.0 + alpha * alpha)
+    assert fields.max_dmdt(F, p["Ms"]) == pytest.approx(want, rel=1e-12)
+
+
+def test_max_dmdt_is_the_largest_cell():
+    F = workloads.random_m((3, 4, 2), 1.0, 5) * np.arange(1, 25).reshape(2, 4, 3)
+    best = max(math.sqrt(sum(F[c, z, y, x] ** 2 for c in range(3)))
+               for z in range(2) for y in range(4) for x in range(3))
+    assert fields.max_dmdt(F, 2.0) == pytest.approx(best / 2.0, rel=1e-15)
