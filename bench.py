@@ -408,6 +408,38 @@ def main():
         extras["rkdp54_speedup_f32_p4_over_f64_full"] = (extras["rkdp54_f32_p4_sim_ns_per_h"]
                                                           / extras["rkdp54_f64_full_sim_ns_per_h"])
 
+        # ---- anisotropic slab 128x128x32 (2 nm): RKCK45, matched p vs FP64 full ----
+        log("slab 128x128x32 rkck45 ...")
+        s3 = workloads.SLAB_128x128x32
+        M3 = workloads.random_m(s3["n"], s3["Ms"], workloads.SLAB_128x128x32_SEED)
+        win3 = 0.5e-12
+        H3 = {}
+        for tag, prec, ex in (("f32_matched", "f32", "matched"), ("f64_full", "f64", None)):
+            sa = llgx.Sim(s3, prec, stream=stream)
+            sa.precompute_demag()
+            with torch.cuda.stream(stream):
+                M3d = torch.as_tensor(M3, dtype=torch.float32 if prec == "f32" else torch.float64, device=dev)
+                sa.set_m(M3d)
+                H3[tag] = sa.demag(M3d).double()
+            sa.autotune(reps=3)
+            sta = llgx.make_stepper("RKCK45", extrap=ex, h=1e-14, adaptive=True)
+            sa.run(sta, 0.1e-12, 0)  # warm-up window (includes priming)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            t_start, _ = sa.time()
+            sa.run(sta, t_start + win3, 0)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            extras[f"slab128_rkck45_{tag}_sim_ns_per_h"] = win3 * 1e9 / wall * 3600.0
+            extras[f"slab128_rkck45_{tag}_counters"] = sa.counters()
+            sa.close()
+            del M3d
+        extras["slab128_f32_field_err_over_Ms"] = float((H3["f32_matched"] - H3["f64_full"]).abs().max().item()
+                                                        / s3["Ms"])
+        extras["slab128_rkck45_speedup_f32_matched_over_f64_full"] = (
+            extras["slab128_rkck45_f32_matched_sim_ns_per_h"] / extras["slab128_rkck45_f64_full_sim_ns_per_h"])
+        del H3
+
         # ---- batched sweep: 64 samples over 4 meshes, RK4 h = 50 fs, FP32 ---
         log("batch of 64 samples ...")
         samples = workloads.batch_samples(64)

@@ -246,3 +246,46 @@ def test_max_dmdt_against_oracle(prec, method, extrap):
         assert abs(info["max_dmdt"] - want) <= tol, (k, info["max_dmdt"], want)
     assert s.step(_stepper(method, extrap, 1e-14))["max_dmdt"] == -1.0
     assert s.run_fixed(st, 2)["max_dmdt"] == -1.0
+
+
+_SLAB128 = {}
+
+
+def _slab128_tensor():
+    if "Nf" not in _SLAB128:
+        p = workloads.SLAB_128x128x32
+        _SLAB128["Nf"] = newell.tensor_full(p["n"], p["cell"])
+    return _SLAB128["Nf"]
+
+
+@pytest.mark.parametrize("method", ["RKCK45", "RKF45"])
+def test_anisotropic_slab_fp32_fields_along_matched_runs(method):
+    """The 128x128x32 slab of 2 nm cells with uniaxial anisotropy, FP32 with
+    the GPU's own tensor: the demagnetizing field of Eq. (2) at the seeded
+    state and at the states of an adaptive run with matched extrapolation
+    (p = 4: priming, then extrapolated steps) is within 1e-5 Ms of the FP64
+    oracle's field at the same state, and |M| stays Ms."""
+    import paper_2107_06729_amd as llgx
+    from oracle import demag
+    p = workloads.SLAB_128x128x32
+    log(f"slab 128x128x32 fp32 {method}")
+    Nf = _slab128_tensor()
+    M0 = f32_round(workloads.random_m(p["n"], p["Ms"], workloads.SLAB_128x128x32_SEED))
+    s = sim(p, "f32")
+    s.set_m(to_dev(M0, "f32"))
+
+    def field_err(M):
+        H = to_host(s.demag(to_dev(M, "f32")))
+        return np.max(np.abs(H - demag.demag_fft(M, Nf))) / p["Ms"]
+
+    assert field_err(M0) <= 1e-5
+    st = llgx.make_stepper(method, extrap="matched", h=2e-14, adaptive=True)
+    for k in range(3):
+        for _ in range(3):
+            info = s.step(st)
+            assert info["err"] <= st.e_max or info["forced"]
+        M = to_host(s.get_m())
+        assert field_err(M) <= 1e-5, k
+        assert np.max(np.abs(np.linalg.norm(M, axis=0) / p["Ms"] - 1.0)) <= 1e-3
+    c = s.counters()
+    assert c["extrap"] > 0  # the last steps ran extrapolated
