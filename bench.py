@@ -408,6 +408,41 @@ def main():
         extras["rkdp54_speedup_f32_p4_over_f64_full"] = (extras["rkdp54_f32_p4_sim_ns_per_h"]
                                                           / extras["rkdp54_f64_full_sim_ns_per_h"])
 
+        # ---- every method: extrapolation of matched order against full evaluation at
+        # the same precision (the paper's speed-up measure: wall time of the same
+        # simulated window), adaptive where the method has an error estimate ----
+        log("method sweep ...")
+        sweep = {}
+        win_m = 20e-12
+        for meth, adaptive, h0 in (("RK4", False, 2.5e-13), ("HEUN", True, 1e-13), ("RK23", True, 1e-13),
+                                   ("RKF45", True, 1e-13), ("RKCK45", True, 1e-13), ("RKDP54", True, 1e-13),
+                                   ("RKF56", True, 1e-13), ("ABM2", True, 1e-13)):
+            row = {}
+            for prec in ("f32", "f64"):
+                for mode, ex in (("full", None), ("matched", "matched")):
+                    sa = llgx.Sim(prob, prec, stream=stream)
+                    sa.precompute_demag()
+                    with torch.cuda.stream(stream):
+                        sa.set_m(torch.as_tensor(M0, dtype=torch.float32 if prec == "f32" else torch.float64,
+                                                 device=dev))
+                    sta = llgx.make_stepper(meth, extrap=ex, h=h0, adaptive=adaptive)
+                    sa.run(sta, 5e-12, 0)  # warm-up window, includes the priming iterations
+                    torch.cuda.synchronize()
+                    c0 = sa.counters()
+                    t0 = time.perf_counter()
+                    t_start, _ = sa.time()
+                    sa.run(sta, t_start + win_m, 0)
+                    torch.cuda.synchronize()
+                    wall = time.perf_counter() - t0
+                    c1 = sa.counters()
+                    row[f"{prec}_{mode}_sim_ns_per_h"] = win_m * 1e9 / wall * 3600.0
+                    row[f"{prec}_{mode}_steps"] = c1["accepted"] - c0["accepted"]
+                    sa.close()
+                row[f"{prec}_speedup_matched_over_full"] = (row[f"{prec}_matched_sim_ns_per_h"]
+                                                            / row[f"{prec}_full_sim_ns_per_h"])
+            sweep[meth] = row
+        extras["method_sweep_20ps"] = sweep
+
         # ---- anisotropic slab 128x128x32 (2 nm): RKCK45, matched p vs FP64 full ----
         log("slab 128x128x32 rkck45 ...")
         s3 = workloads.SLAB_128x128x32
