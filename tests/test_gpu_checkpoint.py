@@ -1,8 +1,9 @@
 """Checkpoint / resume of the stepping state (llgx_save_state /
 llgx_load_state): a run resumed from an image continues bit for bit as the
 uninterrupted run, in the same handle and in a fresh one, including the Eq. (6)
-history (no re-priming) and the FSAL stage field of full-evaluation embedded
-pairs; foreign or mismatched images are refused."""
+history (no re-priming), the FSAL stage field of full-evaluation embedded
+pairs and ABM2's derivatives and previous step; foreign or mismatched images
+are refused."""
 
 import numpy as np
 import pytest
@@ -31,7 +32,8 @@ def _run(s, st, nsteps, adaptive):
     return to_host(s.get_m()), s.time(), s.counters()
 
 
-@pytest.mark.parametrize("case", ["rk4_p4_f32", "rkdp54_full_fsal_f64", "rkf45_p4_adaptive_f64"])
+@pytest.mark.parametrize("case", ["rk4_p4_f32", "rkdp54_full_fsal_f64", "rkf45_p4_adaptive_f64",
+                                  "abm2_p2_adaptive_f64"])
 def test_resume_is_bitwise(case):
     import paper_2107_06729_amd as llgx
     log(f"checkpoint {case}")
@@ -43,8 +45,11 @@ def test_resume_is_bitwise(case):
     elif case == "rkdp54_full_fsal_f64":
         st = llgx.make_stepper("RKDP54", extrap=None, h=1e-13, adaptive=True, renormalize=False)
         adaptive = True
-    else:
+    elif case == "rkf45_p4_adaptive_f64":
         st = llgx.make_stepper("RKF45", extrap=4, h=1e-13, adaptive=True)
+        adaptive = True
+    else:  # ABM2: F_n, its stored field, F_{n-1} and h_{n-1} travel in the image
+        st = llgx.make_stepper("ABM2", extrap=2, h=1e-13, adaptive=True)
         adaptive = True
     a = sim(p, prec, tensor=Nf)
     a.set_m(to_dev(M0, prec))
