@@ -83,3 +83,43 @@ def test_batch_of_benchmark_shapes_runs_graphs():
         M = to_host(bt.get_m(i))
         nrm = np.sqrt(np.sum(M * M, axis=0)) / p["Ms"]
         assert np.all(np.isfinite(M)) and np.max(np.abs(nrm - 1)) < 1e-3
+
+
+@pytest.mark.parametrize("extrap", [None, 4], ids=["full", "p4"])
+def test_batch_with_particle_array_sample(extrap):
+    """One mesh group holding the checkerboard particle array (empty cells)
+    beside solid samples of the same mesh: the group's empty-cell flag is set
+    for all of them, which changes nothing where no neighbour is empty, so
+    every sample still equals the same sample stepped alone, bit for bit; the
+    particle array's empty cells stay zero."""
+    import torch
+
+    import paper_2107_06729_amd as llgx
+    log(f"batch particle array {extrap}")
+    base = workloads.CHECKERBOARD_60x60x1
+    mask = workloads.checkerboard_mask(base["n"], workloads.CHECKERBOARD_SQUARE)
+    probs = [dict(base, Ha=ha) for ha in ((20e3, 1e3, 0.0), (-2e4, 5e3, 0.0), (0.0, 3e4, 1e3))]
+    M0s = [f32_round(workloads.masked(workloads.random_m(base["n"], base["Ms"], 70), mask)),
+           f32_round(workloads.random_m(base["n"], base["Ms"], 71)),
+           f32_round(workloads.random_m(base["n"], base["Ms"], 72))]
+    stream = torch.cuda.Stream()
+    bt = llgx.Batch(probs, "f32", stream=stream)
+    assert bt.info()["groups"] == 1
+    bt.precompute_demag()
+    with torch.cuda.stream(stream):
+        for i, M0 in enumerate(M0s):
+            bt.set_m(i, to_dev(M0, "f32"))
+    st = llgx.make_stepper("RK4", extrap=extrap, h=5e-14)
+    nsteps = 12
+    bt.run_fixed(st, nsteps, use_graph=True)
+    torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        got = to_host(bt.get_m(i))
+        s = sim(p, "f32", stream=stream)
+        with torch.cuda.stream(stream):
+            s.set_m(to_dev(M0s[i], "f32"))
+        for _ in range(nsteps):
+            s.step(st)
+        assert np.array_equal(got, to_host(s.get_m())), i
+    got0 = to_host(bt.get_m(0))
+    assert np.all(got0[:, mask == 0] == 0)
