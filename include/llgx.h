@@ -219,12 +219,13 @@ llgx_status llgx_profile_read(llgx_handle h, double ms[LLGX_K_COUNT], int64_t la
  * and differ only in speed.  Variant 0 is the default.
  *
  * llgx_autotune: times every variant of every pass (reps back-to-back
- * launches each, between HIP events on the handle's stream), keeps the
- * fastest, and remembers the choice for the rest of the process under the
- * key (precision, spectral storage, mesh, sample count), so handles created
- * later with that key start with it.  us_out (may be NULL) receives the
- * chosen variants' average microseconds per launch (0 for a pass the mesh
- * does not need).  Needs llgx_precompute_demag and llgx_set_m (LLGX_E_STATE);
+ * launches each, between HIP events on the handle's stream, in three rounds
+ * that take the variants in turn; a variant's time is its fastest round),
+ * keeps the fastest, and remembers the choice for the rest of the process
+ * under the key (precision, spectral storage, mesh, sample count), so handles
+ * created later with that key start with it.  us_out (may be NULL) receives
+ * the chosen variants' fastest-round microseconds per launch (0 for a pass
+ * the mesh does not need).  Needs llgx_precompute_demag and llgx_set_m (LLGX_E_STATE);
  * uses only the spectral workspace and the stage scratch array, so the
  * stepping state is unchanged.  Synchronises.
  * llgx_time_passes: the same measurement for the current variants only.
