@@ -18,7 +18,6 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
 import time

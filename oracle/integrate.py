@@ -61,7 +61,6 @@ controller clamps and rejection; monotone energy decay under damping; |M|
 conservation.
 """
 
-import math
 import numpy as np
 
 from . import demag as _demag

@@ -4,8 +4,6 @@ seeded state, with the oracle's tensor uploaded (so the comparison isolates
 the stepping).  FP64: 1e-12 relative per step (adaptive: the same accepted
 steps and rejections); FP32: 1e-5 Ms."""
 
-import ctypes
-
 import numpy as np
 import pytest
 

@@ -102,7 +102,6 @@ def test_tune_table_roundtrip():
 
 
 def test_batch_autotune_bitwise():
-    import torch
     import paper_2107_06729_amd as llgx
     probs = [film((32, 24, 2), CELL, Ha=(1e4 * i, 0.0, 0.0)) for i in range(3)] + [film((24, 16, 4), CELL)]
     Ms = [workloads.random_m(q["n"], q["Ms"], 60 + i) for i, q in enumerate(probs)]

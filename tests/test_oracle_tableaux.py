@@ -8,7 +8,6 @@
   field is parallel to M and exerts no torque.
 """
 
-import copy
 import math
 from fractions import Fraction
 
