@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "demag-field evals/s & simulated ns/h at 256x256x16, FP32 vs FP64, err<=1e-5"
 HBM_PEAK_GBS = 8000.0
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "rk4_p4_f32_256x256x16_hbm_traffic.json")
 # kernels of the FP32 step, by demangled-name pattern (rocprofv3 names)
 KIND_PATTERNS = (
     ("xfwd", r"k_xfwd<float, float,"),
