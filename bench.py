@@ -188,16 +188,38 @@ def timed_steps(sim, stepper, k, torch, stream):
     return time.perf_counter() - t0
 
 
-def cpu_baseline(prob, M0, h, p, steps=16):
-    """The oracle as it stands (oracle.integrate.Integrator, single-threaded
-    NumPy/SciPy), steady-state RK4 + p-order extrapolation steps on the same
-    mesh.  The tensor is the oracle's own; the p history entries are zero
-    fields (the cost of a step does not depend on their values), so no
-    priming steps are spent."""
+def host_cores():
+    """Threads the oracle may use on this host: the CPUs this process may run
+    on, capped by OMP_NUM_THREADS when that is set (the host's share)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    if omp.isdigit() and int(omp) > 0:
+        n = min(n, int(omp))
+    return max(n, 1)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(prob, M0, h, p, steps=16, workers=None):
+    """The oracle as it stands (oracle.integrate.Integrator, NumPy/SciPy FP64;
+    its FFTs of Eq. (2) on `workers` threads, the rest in one thread),
+    steady-state RK4 + p-order extrapolation steps on the same mesh.  The
+    tensor is the oracle's own; the p history entries are zero fields (the
+    cost of a step does not depend on their values), so no priming steps are
+    spent."""
     import numpy as np
     from oracle import integrate, newell
     Nf = newell.tensor_full(prob["n"], prob["cell"])
-    it = integrate.Integrator(prob, M0, method="RK4", h=h, adaptive=False, extrap=p, Nfull=Nf)
+    it = integrate.Integrator(prob, M0, method="RK4", h=h, adaptive=False, extrap=p, Nfull=Nf, workers=workers)
     it.hist = [(-(p - j) * h, np.zeros_like(M0)) for j in range(p)]
     it.step()  # warm caches and allocator
     t0 = time.perf_counter()
@@ -584,12 +606,19 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        log("cpu baseline (oracle) ...")
-        v, secs, nst = cpu_baseline(prob, M0, h, p)
-        cpu = {"value": v, "unit": "evals/s", "cores": 1, "kind": "oracle",
+        cores = host_cores()
+        log(f"cpu baseline (oracle, {cores} threads) ...")
+        v, secs, nst = cpu_baseline(prob, M0, h, p, workers=cores)
+        log("cpu baseline (oracle, 1 thread) ...")
+        v1, secs1, nst1 = cpu_baseline(prob, M0, h, p, workers=1)
+        cpu = {"value": v, "unit": "evals/s", "cores": cores, "kind": "oracle",
+               "cpu_model": cpu_model(),
                "sample": f"{nst} steady-state RK4+p{p} steps (4 field evaluations each) of the 256x256x16 "
-                         f"slab, oracle.integrate.Integrator (NumPy/SciPy FP64, one thread), {secs:.1f} s; "
-                         f"tensor setup and one warm-up step untimed"}
+                         f"slab, oracle.integrate.Integrator (NumPy/SciPy FP64; the FFTs of Eq. (2) on "
+                         f"{cores} threads, the rest in one), {secs:.1f} s; tensor setup and one warm-up step "
+                         f"untimed",
+               "one_thread_value": v1,
+               "one_thread_sample": f"the same {nst1} steps with every FFT on one thread, {secs1:.1f} s"}
 
     out = {
         "metric": METRIC,

@@ -142,8 +142,9 @@ class Integrator:
 
     def __init__(self, problem, M0, method="RK4", extrap=None, h=1e-13, adaptive=None,
                  h_min=H_MIN, h_max=H_MAX, c_min=C_MIN, c_max=C_MAX, e_max=E_MAX,
-                 renormalize=False, exponent="min", Nfull=None, demag_fn=None):
+                 renormalize=False, exponent="min", Nfull=None, demag_fn=None, workers=None):
         self.pa = _fields.problem_arrays(problem)
+        self.workers = workers  # threads of scipy.fft in Eq. (2) (None: one)
         self.multistep = method == "ABM2"
         if self.multistep:
             self.tab = None
@@ -193,7 +194,7 @@ class Integrator:
     def demag(self, M):
         if self.demag_fn is not None:
             return self.demag_fn(M)
-        return _demag.demag_fft(M, self.Nfull, self.Khat)
+        return _demag.demag_fft(M, self.Nfull, self.Khat, workers=self.workers)
 
     def rhs(self, M, Hd):
         pa = self.pa

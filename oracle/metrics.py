@@ -12,10 +12,13 @@ import numpy as np
 
 
 def epsilon_series(mavg, mavg_ref, Ms):
+    """Eq. (7) over two <M> series sampled at the same times; series of
+    different length are an error (the points must correspond)."""
     a = np.asarray(mavg, dtype=np.float64).reshape(-1, 3)
     b = np.asarray(mavg_ref, dtype=np.float64).reshape(-1, 3)
-    n = min(len(a), len(b))
-    return float(np.mean(np.linalg.norm(a[:n] - b[:n], axis=1)) / Ms)
+    if len(a) != len(b):
+        raise ValueError(f"series of different length: {len(a)} and {len(b)} points")
+    return float(np.mean(np.linalg.norm(a - b, axis=1)) / Ms)
 
 
 def epsilon_map(M, M_ref, Ms):

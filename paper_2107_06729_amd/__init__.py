@@ -162,10 +162,34 @@ def make_stepper(method="RK4", extrap=None, h=1e-13, adaptive=False, renormalize
 
 
 def _stream_ptr(stream):
-    import torch
-    if stream is None:
-        stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+class _Ordered:
+    """Orders a call's work on the handle's stream after the work already
+    enqueued on torch's current stream (which made the call's tensors), and
+    the current stream's later work after the call's; inputs and outputs are
+    recorded as used on the handle's stream, so the caching allocator does
+    not hand their memory out again before the library is done with it."""
+
+    def __init__(self, owner, *tensors):
+        self.owner, self.tensors = owner, tensors
+
+    def __enter__(self):
+        torch = self.owner.torch
+        self.cur = torch.cuda.current_stream(self.owner.device)
+        self.lib = self.owner._stream
+        self.other = self.cur != self.lib
+        if self.other:
+            self.lib.wait_stream(self.cur)
+        return self
+
+    def __exit__(self, *exc):
+        if self.other:
+            self.cur.wait_stream(self.lib)
+            for t in self.tensors:
+                t.record_stream(self.lib)
+        return False
 
 
 class Sim:
@@ -181,9 +205,11 @@ class Sim:
         self.n = tuple(int(v) for v in problem["n"])
         self.stream = stream
         with torch.cuda.device(self.device):
+            # the handle's HIP stream: the one given, else torch's current stream now
+            self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
             self._h = _H()
             _check(_lib.llgx_create(ctypes.byref(make_problem(problem)), self.prec, int(spectral),
-                                    _stream_ptr(stream), ctypes.byref(self._h)), None)
+                                    _stream_ptr(self._stream), ctypes.byref(self._h)), None)
 
     @property
     def shape(self):
@@ -235,18 +261,21 @@ class Sim:
 
     def set_m(self, M):
         M = self._dev(M)
-        _check(_lib.llgx_set_m(self._h, ctypes.c_void_p(M.data_ptr())), self._h)
+        with _Ordered(self, M):
+            _check(_lib.llgx_set_m(self._h, ctypes.c_void_p(M.data_ptr())), self._h)
         self._keep = M  # the copy is enqueued: keep the source alive until the stream passes it
 
     def get_m(self):
         out = self.torch.empty(self.shape, dtype=self.dtype, device=self.device)
-        _check(_lib.llgx_get_m(self._h, ctypes.c_void_p(out.data_ptr())), self._h)
+        with _Ordered(self, out):
+            _check(_lib.llgx_get_m(self._h, ctypes.c_void_p(out.data_ptr())), self._h)
         return out
 
     def _field(self, fn, M):
         M = self._dev(M)
         out = self.torch.empty_like(M)
-        _check(fn(self._h, ctypes.c_void_p(M.data_ptr()), ctypes.c_void_p(out.data_ptr())), self._h)
+        with _Ordered(self, M, out):
+            _check(fn(self._h, ctypes.c_void_p(M.data_ptr()), ctypes.c_void_p(out.data_ptr())), self._h)
         self._keep = M
         return out
 
@@ -398,8 +427,9 @@ class Batch:
         self.dtype = torch.float32 if self.prec == F32 else torch.float64
         arr = (Problem * len(self.problems))(*[make_problem(p) for p in self.problems])
         with torch.cuda.device(self.device):
+            self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
             self._h = _H()
-            _bcheck(_lib.llgx_batch_create(len(self.problems), arr, self.prec, _stream_ptr(stream),
+            _bcheck(_lib.llgx_batch_create(len(self.problems), arr, self.prec, _stream_ptr(self._stream),
                                            ctypes.byref(self._h)), None)
         self._keep = []
 
@@ -428,12 +458,14 @@ class Batch:
         t = self.torch.as_tensor(M).to(device=self.device, dtype=self.dtype).contiguous()
         if tuple(t.shape) != self.shape(i):
             raise ValueError(f"expected shape {self.shape(i)}, got {tuple(t.shape)}")
-        _bcheck(_lib.llgx_batch_set_m(self._h, int(i), ctypes.c_void_p(t.data_ptr())), self._h)
+        with _Ordered(self, t):
+            _bcheck(_lib.llgx_batch_set_m(self._h, int(i), ctypes.c_void_p(t.data_ptr())), self._h)
         self._keep.append(t)
 
     def get_m(self, i):
         out = self.torch.empty(self.shape(i), dtype=self.dtype, device=self.device)
-        _bcheck(_lib.llgx_batch_get_m(self._h, int(i), ctypes.c_void_p(out.data_ptr())), self._h)
+        with _Ordered(self, out):
+            _bcheck(_lib.llgx_batch_get_m(self._h, int(i), ctypes.c_void_p(out.data_ptr())), self._h)
         return out
 
     def run_fixed(self, stepper, nsteps, use_graph=True):

@@ -304,28 +304,6 @@ struct ColFFT {
             }
         }
     }
-
-    // length-L <= 8 transform of LDS columns in place (single stage)
-    static __device__ __forceinline__ void single_in_lds(C* buf) {
-        static_assert(NSTAGE == 1, "single-stage lengths only");
-#pragma unroll
-        for (int m = 0; m < U0; ++m) {
-            const int u = threadIdx.x + m * NT;
-            if (NU0 % NT == 0 || u < NU0) {
-                const Unit t = unit(u);
-                C* col = buf + t.g * TK + t.p * PN;
-#pragma unroll
-                for (int q = 0; q < PN; ++q) {
-                    C x[R0];
-#pragma unroll
-                    for (int r = 0; r < R0; ++r) x[r] = col[r * W + q];
-                    dft_r<R0, INV>(x);
-#pragma unroll
-                    for (int r = 0; r < R0; ++r) col[r * W + q] = x[r];
-                }
-            }
-        }
-    }
 };
 
 }  // namespace llgx

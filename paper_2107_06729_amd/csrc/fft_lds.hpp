@@ -1,11 +1,5 @@
-// LDS-resident Stockham FFT building blocks for gfx950.
-//
-// A workgroup holds NCOL independent complex sequences of length L in LDS;
-// element (column c, index i) lives at buf[c * CSTR + i * ESTR].  One radix-R
-// stage reads R elements per butterfly into registers, applies the stage
-// twiddles and an R-point DFT, and writes them back to their Stockham
-// (self-sorting) positions.  Reads and writes of a stage are separated by a
-// barrier, so the transform runs in place in one LDS buffer.
+// Complex arithmetic and small DFTs of the Stockham FFT passes for gfx950
+// (fft_col.hpp: column tiles; fft_row.hpp: rows of the x passes).
 //
 // Stage with span NS (product of the radices already applied), butterfly j:
 //   k = j mod NS
@@ -93,77 +87,6 @@ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 // radix of the first stage: 2 or 4 when log2(L) is not a multiple of 3
 constexpr int first_radix(int L) {
     return (ilog2(L) % 3 == 1) ? 2 : (ilog2(L) % 3 == 2) ? 4 : 8;
-}
-
-// Geometry of the columns held in LDS by one workgroup.
-//   NCOL columns, CSTR column stride, ESTR element stride (in complex units).
-//   COLFAST: consecutive threads take consecutive columns (true) or
-//   consecutive butterflies of one column (false) -- whichever keeps the LDS
-//   accesses of a wavefront on consecutive addresses.
-template <int NCOL_, int CSTR_, int ESTR_, bool COLFAST_>
-struct Cols {
-    static constexpr int NCOL = NCOL_, CSTR = CSTR_, ESTR = ESTR_;
-    static constexpr bool COLFAST = COLFAST_;
-};
-
-template <typename T, int L, int R, int NS, bool INV, typename G, int NT>
-__device__ __forceinline__ void stockham_stage(cx<T>* buf, const cx<T>* __restrict__ tw) {
-    using C = cx<T>;
-    constexpr int NB = (L / R) * G::NCOL;
-    constexpr int BPT = (NB + NT - 1) / NT;
-    C v[BPT][R];
-    const int tid = threadIdx.x;
-#pragma unroll
-    for (int m = 0; m < BPT; ++m) {
-        const int bf = tid + m * NT;
-        if ((NB % NT) == 0 || bf < NB) {
-            const int c = G::COLFAST ? (bf % G::NCOL) : (bf / (L / R));
-            const int j = G::COLFAST ? (bf / G::NCOL) : (bf % (L / R));
-            const int k = j & (NS - 1);
-            C* col = buf + c * G::CSTR;
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[m][r] = col[(j + r * (L / R)) * G::ESTR];
-            if constexpr (NS > 1) {
-#pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    const C w = tw[r * k * (L / (NS * R))];
-                    v[m][r] = INV ? cmulc(v[m][r], w) : cmul(v[m][r], w);
-                }
-            }
-            dft_r<R, INV>(v[m]);
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < BPT; ++m) {
-        const int bf = tid + m * NT;
-        if ((NB % NT) == 0 || bf < NB) {
-            const int c = G::COLFAST ? (bf % G::NCOL) : (bf / (L / R));
-            const int j = G::COLFAST ? (bf / G::NCOL) : (bf % (L / R));
-            const int k = j & (NS - 1);
-            C* col = buf + c * G::CSTR;
-            const int base = (j / NS) * NS * R + k;
-#pragma unroll
-            for (int r = 0; r < R; ++r) col[(base + r * NS) * G::ESTR] = v[m][r];
-        }
-    }
-    __syncthreads();
-}
-
-template <typename T, int L, int NS, bool INV, typename G, int NT>
-__device__ __forceinline__ void stockham_from(cx<T>* buf, const cx<T>* __restrict__ tw) {
-    if constexpr (NS < L) {
-        constexpr int R = (NS == 1) ? first_radix(L) : 8;
-        stockham_stage<T, L, R, NS, INV, G, NT>(buf, tw);
-        stockham_from<T, L, NS * R, INV, G, NT>(buf, tw);
-    }
-}
-
-// Full length-L transform of every column held in LDS.  Callers must
-// __syncthreads() after filling buf; the routine ends with a barrier.
-template <typename T, int L, bool INV, typename G, int NT>
-__device__ __forceinline__ void lds_fft(cx<T>* buf, const cx<T>* __restrict__ tw) {
-    if constexpr (L > 1) stockham_from<T, L, 1, INV, G, NT>(buf, tw);
 }
 
 }  // namespace llgx

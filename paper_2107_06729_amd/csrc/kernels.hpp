@@ -177,12 +177,10 @@ struct NextStage {
     T cnext;
 };
 
-// Sub-step F with M_k = mk.base + sum of mk.nf terms formed at every read
-// (mk.nf <= MAX_FUSED_TERMS; longer stage rows are combined beforehand) and
-// ex.n == 1.  Forming M_k inside the 7-point stencil re-reads every term at
-// the neighbours, which measured slower than one combine pass on gfx950
-// even for a single term, so stage inputs are always combined first.
-constexpr int MAX_FUSED_TERMS = 0;
+// Sub-step F at the stage input mk.base (mk.nf must be 0: a stage input with
+// terms is formed once by launch_combine; forming M_k inside the 7-point
+// stencil re-reads every term at the neighbours, which measured slower than
+// one combine pass on gfx950 even for a single term).
 template <typename T>
 hipError_t launch_extrap_rhs(hipStream_t s, const Combo<T>& mk, const Extrap<T>& ex, const Phys<T>& ph, T* F,
                              const NextStage<T>& nx);

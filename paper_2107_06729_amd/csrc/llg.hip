@@ -27,6 +27,27 @@ namespace llgx {
 
 constexpr int NTS = 256;
 
+// max that propagates NaN (fmax alone would drop it)
+__device__ __forceinline__ double nan_max(double a, double b) { return (a != a || b != b) ? a + b : fmax(a, b); }
+
+// Max over the block's threads (tid = linear thread index, NTS threads):
+// each 64-lane wavefront reduces with cross-lane shuffles, then one thread
+// combines the NTS/64 wave results through LDS.  Max is exact, so the
+// result does not depend on the order.  The value is valid in thread 0.
+__device__ __forceinline__ double block_max(double v, int tid) {
+    __shared__ double wv[NTS / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = nan_max(v, __shfl_xor(v, off, 64));
+    if ((tid & 63) == 0) wv[tid >> 6] = v;
+    __syncthreads();
+    double r = wv[0];
+    if (tid == 0) {
+#pragma unroll
+        for (int w = 1; w < NTS / 64; ++w) r = nan_max(r, wv[w]);
+    }
+    return r;
+}
+
 // ---------------------------------------------------------------------------
 // 16-byte vector access: 4 floats or 2 doubles per pack
 template <typename T> struct Vec;
@@ -164,24 +185,12 @@ __device__ __forceinline__ CellIdx cell_index(const Phys<T>& ph) {
     return c;
 }
 
-template <typename T, int NC>
-__device__ __forceinline__ ComboField<T, NC> combo_field(const Combo<T>& c, long off) {
-    ComboField<T, NC> f;
-    f.base = c.base + off;
-#pragma unroll
-    for (int l = 0; l < NC; ++l) {
-        f.f[l] = c.f[l] + off;
-        f.coef[l] = c.coef[l];
-    }
-    return f;
-}
-
 // F at a sub-step: H_d = g - N00 M_k with g the Eq. (6) field of the stage's
-// time, H_eff and the LLG right-hand side; M_k = M0 + sum of NC terms
-template <typename T, int NC>
+// time, H_eff and the LLG right-hand side; M_k = mk.base
+template <typename T>
 __device__ __forceinline__ void stage_rhs(const Combo<T>& mk, const Extrap<T>& ex, const Phys<T>& ph,
                                           const CellIdx& ci, long N, T m[3], T f[3]) {
-    const ComboField<T, NC> M = combo_field<T, NC>(mk, ci.off);
+    const PtrField<T> M{mk.base + ci.off};
     T g[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) g[c] = ex.g[0][ci.off + c * N + ci.cell];
@@ -193,7 +202,7 @@ __device__ __forceinline__ void stage_rhs(const Combo<T>& mk, const Extrap<T>& e
     llg_at(m, H, ph, f);
 }
 
-template <typename T, int NC>
+template <typename T>
 __global__ __launch_bounds__(NTS) void k_stage(Combo<T> mk, Extrap<T> ex, Phys<T> ph, T* __restrict__ F,
                                                NextStage<T> nx) {
     const long N = (long)ph.nx * ph.ny * ph.nz;
@@ -206,7 +215,7 @@ __global__ __launch_bounds__(NTS) void k_stage(Combo<T> mk, Extrap<T> ex, Phys<T
         for (int c = 0; c < 3; ++c) m0[c] = nx.m0[ci.off + c * N + ci.cell];
     }
     T m[3], f[3];
-    stage_rhs<T, NC>(mk, ex, ph, ci, N, m, f);
+    stage_rhs<T>(mk, ex, ph, ci, N, m, f);
 #pragma unroll
     for (int c = 0; c < 3; ++c) F[ci.off + c * N + ci.cell] = f[c];
     if (nx.mnext) {
@@ -218,11 +227,10 @@ __global__ __launch_bounds__(NTS) void k_stage(Combo<T> mk, Extrap<T> ex, Phys<T
 // last sub-step fused with Eq. (3): fs lists the stage derivatives used by
 // the update or the estimate; its final entry (index fs.n - 1) is this
 // stage's own F_S, which is taken from registers and never stored
-template <typename T, int NC, int NF>
+template <typename T, int NF>
 __global__ __launch_bounds__(NTS) void k_stage_final(Combo<T> mk, Extrap<T> ex, Phys<T> ph, const T* __restrict__ M0,
                                                      Final<T> fs, double inv_ms, T* __restrict__ mnew,
                                                      double* __restrict__ parts) {
-    __shared__ double red[NTS];
     const long N = (long)ph.nx * ph.ny * ph.nz;
     const CellIdx ci = cell_index(ph);
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
@@ -237,7 +245,7 @@ __global__ __launch_bounds__(NTS) void k_stage_final(Combo<T> mk, Extrap<T> ex, 
 #pragma unroll
             for (int c = 0; c < 3; ++c) f[k][c] = fs.f[k][ci.off + c * N + ci.cell];
         T m[3], fS[3];
-        stage_rhs<T, NC>(mk, ex, ph, ci, N, m, fS);
+        stage_rhs<T>(mk, ex, ph, ci, N, m, fS);
         double e2 = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -257,22 +265,13 @@ __global__ __launch_bounds__(NTS) void k_stage_final(Combo<T> mk, Extrap<T> ex, 
         emax = sqrt(e2) * inv_ms;
         if (e2 != e2) emax = e2;
     }
-    red[tid] = emax;
-    __syncthreads();
-    for (int s = NTS / 2; s > 0; s >>= 1) {
-        if (tid < s) {
-            const double a = red[tid], b = red[tid + s];
-            red[tid] = (a != a || b != b) ? (a + b) : fmax(a, b);
-        }
-        __syncthreads();
-    }
-    if (tid == 0) parts[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+    const double bm = block_max(emax, tid);
+    if (tid == 0) parts[blockIdx.y * gridDim.x + blockIdx.x] = bm;
 }
 
 template <typename T, int NF>
 __global__ __launch_bounds__(NTS) void k_final(long ncell, int nb, const T* __restrict__ base, Final<T> fs,
                                                double inv_ms, T* __restrict__ mnew, double* __restrict__ parts) {
-    __shared__ double red[NTS];
     double emax = 0.0;
     for (long ic = (long)blockIdx.x * NTS + threadIdx.x; ic < ncell * nb; ic += (long)gridDim.x * NTS) {
         const long b = ic / ncell, cell = ic - b * ncell;
@@ -302,47 +301,23 @@ __global__ __launch_bounds__(NTS) void k_final(long ncell, int nb, const T* __re
         // NaN in the estimate must not be lost by fmax
         if (e2 != e2) emax = e2;
     }
-    red[threadIdx.x] = emax;
-    __syncthreads();
-    for (int s = NTS / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            const double a = red[threadIdx.x], b = red[threadIdx.x + s];
-            red[threadIdx.x] = (a != a || b != b) ? (a + b) : fmax(a, b);
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) parts[blockIdx.x] = red[0];
+    const double bm = block_max(emax, threadIdx.x);
+    if (threadIdx.x == 0) parts[blockIdx.x] = bm;
 }
 
 __global__ __launch_bounds__(NTS) void k_reduce_max(const double* __restrict__ parts, int n, double* __restrict__ out) {
-    __shared__ double red[NTS];
     double m = 0.0;
-    for (int i = threadIdx.x; i < n; i += NTS) {
-        const double v = parts[i];
-        m = (v != v || m != m) ? (v + m) : fmax(m, v);
-    }
-    red[threadIdx.x] = m;
-    __syncthreads();
-    for (int s = NTS / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            const double a = red[threadIdx.x], b = red[threadIdx.x + s];
-            red[threadIdx.x] = (a != a || b != b) ? (a + b) : fmax(a, b);
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[0] = red[0];
+    for (int i = threadIdx.x; i < n; i += NTS) m = nan_max(m, parts[i]);
+    const double bm = block_max(m, threadIdx.x);
+    if (threadIdx.x == 0) out[0] = bm;
 }
 
-__device__ __forceinline__ double nan_max(double a, double b) { return (a != a || b != b) ? a + b : fmax(a, b); }
-
 // Per-block partials of max over cells of |v| / Ms for a vector field v
-// ([nb][3][ncell]; the |dM/dt| diagnostic of a step).  Each wavefront
-// reduces its 64 lanes with cross-lane shuffles, then the block's waves are
-// combined through LDS; NaN propagates.  k_reduce_max finishes the partials.
+// ([nb][3][ncell]; the |dM/dt| diagnostic of a step), by block_max; NaN
+// propagates.  k_reduce_max finishes the partials.
 template <typename T>
 __global__ __launch_bounds__(NTS) void k_max_norm(long ncell, int nb, const T* __restrict__ v, double inv_ms,
                                                   double* __restrict__ parts) {
-    __shared__ double wv[NTS / 64];
     double mx = 0.0;
     for (long ic = (long)blockIdx.x * NTS + threadIdx.x; ic < ncell * nb; ic += (long)gridDim.x * NTS) {
         const long b = ic / ncell, cell = ic - b * ncell;
@@ -350,16 +325,8 @@ __global__ __launch_bounds__(NTS) void k_max_norm(long ncell, int nb, const T* _
         const double x = p[0], y = p[ncell], z = p[2 * ncell];
         mx = nan_max(mx, sqrt(x * x + y * y + z * z) * inv_ms);
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) mx = nan_max(mx, __shfl_xor(mx, off, 64));
-    if ((threadIdx.x & 63) == 0) wv[threadIdx.x >> 6] = mx;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double r = wv[0];
-#pragma unroll
-        for (int w = 1; w < NTS / 64; ++w) r = nan_max(r, wv[w]);
-        parts[blockIdx.x] = r;
-    }
+    const double bm = block_max(mx, threadIdx.x);
+    if (threadIdx.x == 0) parts[blockIdx.x] = bm;
 }
 
 template <typename T>
@@ -513,28 +480,8 @@ template <typename T>
 hipError_t launch_extrap_rhs(hipStream_t s, const Combo<T>& mk, const Extrap<T>& ex, const Phys<T>& ph, T* F,
                              const NextStage<T>& nx) {
     const CellGrid cg = cell_grid(ph.nx, ph.ny, ph.nz, ph.nb);
-    if (ex.n != 1) return hipErrorInvalidValue;
-    switch (mk.nf) {
-#define EX(K) \
-    case K: k_stage<T, K><<<cg.grid, cg.block, 0, s>>>(mk, ex, ph, F, nx); break;
-        EX(0)
-#undef EX
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-template <typename T, int NC>
-static hipError_t stage_final_nc(hipStream_t s, const CellGrid& cg, const Combo<T>& mk, const Extrap<T>& ex,
-                                 const Phys<T>& ph, const T* M0, const Final<T>& fs, double inv_ms, T* mnew,
-                                 double* parts) {
-    switch (fs.n) {
-#define SF(K)                                                                                                   \
-    case K: k_stage_final<T, NC, K><<<cg.grid, cg.block, 0, s>>>(mk, ex, ph, M0, fs, inv_ms, mnew, parts); break;
-        SF(1) SF(2) SF(3) SF(4) SF(5) SF(6) SF(7) SF(8)
-#undef SF
-        default: return hipErrorInvalidValue;
-    }
+    if (ex.n != 1 || mk.nf != 0) return hipErrorInvalidValue;
+    k_stage<T><<<cg.grid, cg.block, 0, s>>>(mk, ex, ph, F, nx);
     return hipGetLastError();
 }
 
@@ -542,11 +489,15 @@ template <typename T>
 hipError_t launch_stage_final(hipStream_t s, const Combo<T>& mk, const Extrap<T>& ex, const Phys<T>& ph, const T* M0,
                               const Final<T>& fs, double inv_ms, T* mnew, double* parts) {
     const CellGrid cg = cell_grid(ph.nx, ph.ny, ph.nz, ph.nb);
-    if (ex.n != 1) return hipErrorInvalidValue;
-    switch (mk.nf) {
-        case 0: return stage_final_nc<T, 0>(s, cg, mk, ex, ph, M0, fs, inv_ms, mnew, parts);
+    if (ex.n != 1 || mk.nf != 0) return hipErrorInvalidValue;
+    switch (fs.n) {
+#define SF(K)                                                                                                   \
+    case K: k_stage_final<T, K><<<cg.grid, cg.block, 0, s>>>(mk, ex, ph, M0, fs, inv_ms, mnew, parts); break;
+        SF(1) SF(2) SF(3) SF(4) SF(5) SF(6) SF(7) SF(8)
+#undef SF
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
 }
 
 template <typename T>

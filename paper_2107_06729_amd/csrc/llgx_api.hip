@@ -29,15 +29,24 @@ static int next_pow2(long v) {
     return p;
 }
 
+// A captured step depends on everything its launches take by value or by
+// pointer: the state buffer, the history slots, h (Lagrange weights, stage
+// coefficients), the method and order (launch sequence) and the tensor
+// generation (N00 inside the per-cell constants, the folded kernel).
 struct GraphKey {
     const void* M;
     int slot0;
     std::vector<int> hist_slots;
     double h;
+    int method, p;
+    long gen;
     bool operator<(const GraphKey& o) const {
         if (M != o.M) return M < o.M;
         if (slot0 != o.slot0) return slot0 < o.slot0;
         if (hist_slots != o.hist_slots) return hist_slots < o.hist_slots;
+        if (method != o.method) return method < o.method;
+        if (p != o.p) return p < o.p;
+        if (gen != o.gen) return gen < o.gen;
         return h < o.h;
     }
 };
@@ -79,6 +88,7 @@ struct Ctx {
     bool field_input = false;   // phys() reads flag [1] (during a field call)
     double* octant = nullptr;   // real-space tensor for offsets 0..n-1 (double)
     bool have_kernel = false;
+    long kernel_gen = 0;        // bumped whenever the tensor (and N00) changes
     bool have_m = false;
     double n00[3] = {0, 0, 0};
 
@@ -440,6 +450,10 @@ static llgx_status kernel_from_octant_or_real(Ctx* c, const std::vector<double>*
     (void)hipFree(real);
     (void)hipFree(spec);
     c->have_kernel = true;
+    // graphs captured with the previous tensor are never replayed again
+    c->kernel_gen++;
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
     return LLGX_OK;
 }
 
@@ -582,7 +596,7 @@ static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
         if (pl.extrap) {
             if (formed[k]) {
                 cb = plain<T>(mkbuf(k));
-            } else if (cb.nf > MAX_FUSED_TERMS) {
+            } else if (cb.nf > 0) {
                 // form M_k once instead of at every stencil read
                 PROF(LLGX_K_COMBINE);
                 HIPCHK(c, launch_combine<T>(c->stream, 3 * c->ncell * c->nb, cb, (T*)mkbuf(k)));
@@ -976,7 +990,7 @@ static llgx_status do_run_fixed(Ctx* c, const llgx_stepper* s, int64_t nsteps, i
         pl.slot0 = free_slot(c);
         pl.want_err = false;
         pl.h = s->h;
-        GraphKey key{c->M, pl.slot0, {}, s->h};
+        GraphKey key{c->M, pl.slot0, {}, s->h, s->method, p, c->kernel_gen};
         for (auto& hh : c->hist) key.hist_slots.push_back(hh.slot);
         // the Lagrange nodes are relative times: graphs are reused only while steps stay uniform
         bool uniform = true;
@@ -1387,7 +1401,7 @@ static llgx_status batch_run_fixed(Batch* bt, const llgx_stepper* s, int64_t nst
             pl.slot0 = free_slot(c);
             pl.want_err = false;
             pl.h = s->h;
-            GraphKey key{c->M, pl.slot0, {}, s->h};
+            GraphKey key{c->M, pl.slot0, {}, s->h, s->method, p, c->kernel_gen};
             for (auto& hh : c->hist) key.hist_slots.push_back(hh.slot);
             keys.push_back(key);
         }

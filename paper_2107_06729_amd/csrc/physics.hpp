@@ -8,26 +8,11 @@
 
 namespace llgx {
 
-// M at flat index i of the sample's [3][N] block: a plain array ...
+// M at flat index i of the sample's [3][N] block
 template <typename T>
 struct PtrField {
     const T* __restrict__ p;
     __device__ __forceinline__ T operator()(long i) const { return p[i]; }
-};
-
-// ... or a stage input M_k = M0 + sum_l coef_l F_l (Eq. 4) formed where it is
-// read, so no M_k array is written and read back
-template <typename T, int NC>
-struct ComboField {
-    const T* __restrict__ base;
-    const T* __restrict__ f[NC > 0 ? NC : 1];
-    T coef[NC > 0 ? NC : 1];
-    __device__ __forceinline__ T operator()(long i) const {
-        T v = base[i];
-#pragma unroll
-        for (int l = 0; l < NC; ++l) v += coef[l] * f[l][i];
-        return v;
-    }
 };
 
 // M reads the sample's own [3][N] block; b is the sample index (applied

@@ -46,47 +46,4 @@ struct TwStage {
     }
 };
 
-// Tile of R rows x TK complex columns.  Global row i starts at g + i*gs
-// (complex units, 16-byte aligned); LDS row stride TK.  Rows >= nrows and
-// packs starting at a column >= ncols read as zero.
-template <typename T, int R, int TK, int NT>
-__device__ __forceinline__ void load_tile(cx<T>* lds, const cx<T>* __restrict__ g, long gs, int nrows, int ncols) {
-    using P = typename Pack<T>::type;
-    constexpr int PN = Pack<T>::N, PR = TK / PN, TOT = R * PR, PER = (TOT + NT - 1) / NT;
-    static_assert(TK % PN == 0, "tile width");
-    P r[PER];
-#pragma unroll
-    for (int m = 0; m < PER; ++m) {
-        const int e = threadIdx.x + m * NT;
-        const int i = e / PR, j = e - i * PR;
-        r[m] = Pack<T>::zero();
-        if ((TOT % NT == 0 || e < TOT) && i < nrows && j * PN < ncols) r[m] = *(const P*)(g + i * gs + j * PN);
-    }
-#pragma unroll
-    for (int m = 0; m < PER; ++m) {
-        const int e = threadIdx.x + m * NT;
-        if (TOT % NT == 0 || e < TOT) *(P*)(lds + e * PN) = r[m];
-    }
-}
-
-// Inverse of load_tile for rows < nrows and packs starting below ncols (a pack
-// straddling ncols also writes the row padding after it, which no pass reads).
-template <typename T, int R, int TK, int NT>
-__device__ __forceinline__ void store_tile(cx<T>* __restrict__ g, long gs, const cx<T>* lds, int nrows, int ncols) {
-    using P = typename Pack<T>::type;
-    constexpr int PN = Pack<T>::N, PR = TK / PN, TOT = R * PR, PER = (TOT + NT - 1) / NT;
-    P r[PER];
-#pragma unroll
-    for (int m = 0; m < PER; ++m) {
-        const int e = threadIdx.x + m * NT;
-        if (TOT % NT == 0 || e < TOT) r[m] = *(const P*)(lds + e * PN);
-    }
-#pragma unroll
-    for (int m = 0; m < PER; ++m) {
-        const int e = threadIdx.x + m * NT;
-        const int i = e / PR, j = e - i * PR;
-        if ((TOT % NT == 0 || e < TOT) && i < nrows && j * PN < ncols) *(P*)(g + i * gs + j * PN) = r[m];
-    }
-}
-
 }  // namespace llgx

@@ -123,3 +123,49 @@ def test_batch_with_particle_array_sample(extrap):
         assert np.array_equal(got, to_host(s.get_m())), i
     got0 = to_host(bt.get_m(0))
     assert np.all(got0[:, mask == 0] == 0)
+
+
+_CONFIG4 = {}
+
+
+def _config4_batch():
+    """The first 12 samples of the 64-sample sweep (all four meshes, their own
+    fields and seeds), RK4 h = 50 fs with 4th-order extrapolation, 100
+    graph-replayed steps in one batch."""
+    import torch
+
+    import paper_2107_06729_amd as llgx
+    if not _CONFIG4:
+        samples = workloads.batch_samples(64)[:12]
+        stream = torch.cuda.Stream()
+        bt = llgx.Batch([p for p, _ in samples], "f32", stream=stream)
+        assert bt.info()["groups"] == 4
+        bt.precompute_demag()
+        M0s = [f32_round(workloads.random_m(p["n"], p["Ms"], seed)) for p, seed in samples]
+        with torch.cuda.stream(stream):
+            for i, M0 in enumerate(M0s):
+                bt.set_m(i, to_dev(M0, "f32"))
+        bt.run_fixed(llgx.make_stepper("RK4", extrap=4, h=5e-14), 100, use_graph=True)
+        torch.cuda.synchronize()
+        _CONFIG4.update(samples=samples, M0s=M0s, got=[to_host(bt.get_m(i)) for i in range(len(samples))])
+        bt.close()
+    return _CONFIG4
+
+
+@pytest.mark.parametrize("shape", workloads.BATCH_SHAPES, ids=["x".join(map(str, n)) for n in workloads.BATCH_SHAPES])
+def test_config4_batch_against_oracle_100_steps(shape):
+    """Each mesh of the batched sweep: the first sample of that mesh after 100
+    batched steps is within 1e-5 Ms of the oracle (FP64 tensor, FP64
+    arithmetic) run from the same FP32-rounded state."""
+    import bench
+    c = _config4_batch()
+    i = next(k for k, (p, _) in enumerate(c["samples"]) if tuple(p["n"]) == tuple(shape))
+    p = c["samples"][i][0]
+    log(f"config4 oracle {shape} sample {i}")
+    ora = integrate.Integrator(p, c["M0s"][i], method="RK4", h=5e-14, adaptive=False, extrap=4,
+                               Nfull=newell.tensor_full(p["n"], p["cell"]), workers=bench.host_cores())
+    for _ in range(100):
+        ora.step()
+    err = np.max(np.abs(c["got"][i] - ora.M)) / p["Ms"]
+    log(f"config4 {shape}: max |dM|/Ms after 100 steps = {err:.3e}")
+    assert err <= 1e-5

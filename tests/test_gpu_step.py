@@ -43,8 +43,8 @@ def test_fixed_steps_fp64(method, extrap):
     assert (c["exact"], c["extrap"]) == (ora.stats["exact"], ora.stats["extrap"])
 
 
-@pytest.mark.parametrize("extrap", [None, 4], ids=["full", "p4"])
-@pytest.mark.parametrize("method", ["RK4", "RKDP54", "RKF56"])
+@pytest.mark.parametrize("extrap", [None, 4, "matched"], ids=["full", "p4", "matched"])
+@pytest.mark.parametrize("method", METHODS)
 def test_fixed_steps_fp32(method, extrap):
     log(f"fixed fp32 {method} {extrap}")
     p = film(N_SMALL, CELL_SMALL)
@@ -86,6 +86,62 @@ def test_adaptive_steps_fp64(method, extrap):
     assert rej > 0
     got = to_host(s.get_m())
     assert np.max(np.abs(got - ora.M)) <= 1e-11 * p["Ms"]
+
+
+def _replay(ora, ig):
+    """Oracle step at the GPU's accepted h (schedule replay)."""
+    return ora.step(ig["h_used"])
+
+
+@pytest.mark.parametrize("extrap", [None, "matched"], ids=["full", "matched"])
+@pytest.mark.parametrize("method", ["RKF45", "RKCK45", "RKDP54", "HEUN", "RK23", "RKF56"])
+def test_adaptive_steps_fp32_schedule_replay(method, extrap):
+    """FP32 adaptive runs: the oracle replays the GPU's accepted step sizes
+    (the controller's decisions rest on FP32 error estimates, so the schedule
+    is the GPU's), and every state stays within 1e-5 Ms of the oracle's; each
+    step's error estimate agrees to the FP32 noise of its difference of
+    stage derivatives."""
+    log(f"adaptive fp32 replay {method} {extrap}")
+    p = film(N_SMALL, CELL_SMALL, alpha=0.1)
+    Nf = newell.tensor_full(N_SMALL, CELL_SMALL)
+    M0 = f32_round(workloads.uniform_m(N_SMALL, p["Ms"], (1.0, 0.25, 0.1))
+                   + 0.05 * workloads.random_m(N_SMALL, p["Ms"], 43))
+    ora = integrate.Integrator(p, M0, method=method, h=1e-13, adaptive=False, extrap=extrap, Nfull=Nf)
+    s = sim(p, "f32", tensor=Nf)
+    s.set_m(to_dev(M0, "f32"))
+    st = _stepper(method, extrap, 1e-13, adaptive=True)
+    for k in range(14):
+        ig = s.step(st)
+        io = _replay(ora, ig)
+        assert abs(ig["err"] - io["err"]) <= 1e-2 * io["err"] + 1e-9, (k, ig["err"], io["err"])
+        got = to_host(s.get_m())
+        assert np.max(np.abs(got - ora.M)) <= 1e-5 * p["Ms"], k
+    c = s.counters()
+    assert (c["exact"], c["extrap"]) == (ora.stats["exact"], ora.stats["extrap"]) or c["rejected"] > 0
+
+
+def test_film_256x64x1_rkdp54_p4_fp32_schedule_replay():
+    """The 256x64x1 film (5x5x3 nm, 25 mT at 170 deg), Dormand-Prince
+    adaptive at e_max 1e-6 with 4th-order extrapolation, FP32 with the GPU's
+    own tensor: the oracle (FP64 tensor and arithmetic) replays the GPU's
+    accepted steps; every state within 1e-5 Ms."""
+    p = workloads.FILM_256x64x1
+    n = p["n"]
+    Nf = newell.tensor_full(n, p["cell"])
+    M0 = workloads.uniform_m(n, p["Ms"], workloads.FILM_256x64x1_DIR)
+    ora = integrate.Integrator(p, M0, method="RKDP54", h=1e-13, adaptive=False, extrap=4, Nfull=Nf)
+    s = sim(p, "f32")
+    s.set_m(to_dev(M0, "f32"))
+    st = _stepper("RKDP54", 4, 1e-13, adaptive=True, e_max=1e-6)
+    worst = 0.0
+    for k in range(40):
+        ig = s.step(st)
+        _replay(ora, ig)
+        got = to_host(s.get_m())
+        worst = max(worst, np.max(np.abs(got - ora.M)) / p["Ms"])
+        assert worst <= 1e-5, k
+    log(f"film 256x64x1 rkdp54 p4 fp32: 40 steps to t = {ora.t:.3e} s, max |dM|/Ms = {worst:.3e}")
+    assert s.counters()["extrap"] > 0
 
 
 def test_config1_film_rk4_200_steps_fp64():
@@ -287,3 +343,86 @@ def test_anisotropic_slab_fp32_fields_along_matched_runs(method):
         assert np.max(np.abs(np.linalg.norm(M, axis=0) / p["Ms"] - 1.0)) <= 1e-3
     c = s.counters()
     assert c["extrap"] > 0  # the last steps ran extrapolated
+
+
+@pytest.mark.parametrize("first,second", [(("RK4", None), ("RK4", 0)), (("RK4", 4), ("RKF45", 4)),
+                                          (("RKF45", 4), ("RK4", 4)), (("RK4", 2), ("RK4", 3))],
+                         ids=["rk4full-rk4p0", "rk4p4-rkf45p4", "rkf45p4-rk4p4", "rk4p2-rk4p3"])
+def test_graph_cache_follows_method_and_order(first, second):
+    """Graph replay on one handle after a change of method or extrapolation
+    order at the same h: the second run equals, bitwise, a fresh handle that
+    runs only the second stepper from the same state (a replayed graph of the
+    first stepper would not)."""
+    import torch
+    log(f"graph cache {first} -> {second}")
+    p = film((32, 24, 4), (5e-9, 5e-9, 5e-9))
+    M0 = workloads.random_m(p["n"], p["Ms"], 37)
+    stream = torch.cuda.Stream()
+    h = 2e-14
+    a = sim(p, "f32", stream=stream)
+    with torch.cuda.stream(stream):
+        a.set_m(to_dev(M0, "f32"))
+        a.run_fixed(_stepper(first[0], first[1], h), 9, use_graph=True)
+        M1 = a.get_m().clone()
+        a.run_fixed(_stepper(second[0], second[1], h), 9, use_graph=True)
+        ma = to_host(a.get_m())
+    b = sim(p, "f32", stream=stream)
+    with torch.cuda.stream(stream):
+        b.set_m(M1)
+        b.run_fixed(_stepper(second[0], second[1], h), 9, use_graph=False)
+        mb = to_host(b.get_m())
+    assert np.array_equal(ma, mb)
+
+
+def test_graph_cache_follows_tensor():
+    """A new tensor (llgx_set_demag_tensor) between graph-replayed runs at the
+    same h: the run after it equals, bitwise, a fresh handle with that tensor
+    from the same state (N00 and the folded kernel are the new ones)."""
+    import torch
+    log("graph cache tensor")
+    n, cell = (24, 20, 3), (5e-9, 5e-9, 3e-9)
+    p = film(n, cell)
+    Nf = newell.tensor_full(n, cell)
+    Nf2 = 0.5 * Nf
+    M0 = workloads.random_m(n, p["Ms"], 38)
+    stream = torch.cuda.Stream()
+    st = _stepper("RK4", 4, 2e-14)
+    a = sim(p, "f32", tensor=Nf, stream=stream)
+    with torch.cuda.stream(stream):
+        a.set_m(to_dev(M0, "f32"))
+        a.run_fixed(st, 9, use_graph=True)
+        M1 = a.get_m().clone()
+    a.set_demag_tensor(Nf2)
+    with torch.cuda.stream(stream):
+        a.run_fixed(st, 9, use_graph=True)
+        ma = to_host(a.get_m())
+    b = sim(p, "f32", tensor=Nf2, stream=stream)
+    with torch.cuda.stream(stream):
+        b.set_m(M1)
+        b.run_fixed(st, 9, use_graph=False)
+        mb = to_host(b.get_m())
+    assert np.array_equal(ma, mb)
+
+
+def test_calls_outside_the_handle_stream_are_ordered():
+    """A handle on its own stream, called from torch's default stream with
+    fresh tensors: the binding orders each call after the work that made its
+    inputs and before the work that reads its outputs, so the fields equal
+    those of calls made inside the handle's stream."""
+    import torch
+    log("stream ordering")
+    n, cell = (40, 33, 9), (2e-9, 2e-9, 2e-9)
+    p = film(n, cell)
+    M0 = workloads.random_m(n, p["Ms"], 39)
+    stream = torch.cuda.Stream()
+    s = sim(p, "f32", stream=stream)
+    with torch.cuda.stream(stream):
+        want = to_host(s.rhs(to_dev(M0, "f32")))
+    for _ in range(3):
+        Md = to_dev(M0, "f32") * 1.0  # made on the default stream just before the call
+        F = s.rhs(Md)
+        del Md
+        junk = torch.empty(F.numel() * 4, device="cuda:0").fill_(7.0)  # may reuse freed memory
+        got = F.cpu().double().numpy()
+        assert np.array_equal(got, want)
+        del junk

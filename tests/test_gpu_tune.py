@@ -12,9 +12,8 @@ from tests.gpu_util import film, log, sim, to_dev, to_host
 pytestmark = pytest.mark.gpu
 
 N, CELL = (40, 36, 6), (5e-9, 5e-9, 3e-9)
-# odd row length (no paired loads) and 819 row groups in the x passes with a
-# ragged last one: more groups than the persistent x-forward variants launch
-# workgroups, so their workgroups take several groups each
+# odd row length (no paired loads), 819 row groups in the x passes with a
+# ragged last one, and z length 128
 N_MANY = (7, 97, 45)
 
 

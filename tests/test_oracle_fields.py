@@ -45,6 +45,54 @@ def test_anisotropy_along_axis():
     assert np.allclose(H[:, 0, 0, 0], ref, rtol=1e-14)
 
 
+def test_anisotropy_vanishes_perpendicular_to_axis():
+    """M perpendicular to the easy axis: (M.u) = 0, so no anisotropy field
+    (a formula without the projection, 2K/(mu0 Ms) u, would fail here)."""
+    u = np.array([0.0, 0.6, 0.8])
+    M = workloads.uniform_m((3, 2, 2), 1.1e6, (1.0, 0.0, 0.0))
+    H = fields.anisotropy_field(M, 1.1e6, 5e5, u)
+    assert np.max(np.abs(H)) == 0.0
+    M = workloads.uniform_m((3, 2, 2), 1.1e6, (0.0, 0.8, -0.6))
+    H = fields.anisotropy_field(M, 1.1e6, 5e5, u)
+    assert np.max(np.abs(H)) <= 1e-9 * 2 * 5e5 / (MU0 * 1.1e6)
+
+
+@pytest.mark.parametrize("theta", [0.3, 1.0, 2.2, math.pi])
+def test_anisotropy_at_angle_closed_form(theta):
+    """M at angle theta from the axis u: H_an = 2K/(mu0 Ms) cos(theta) u,
+    along u whatever the direction of M's perpendicular part."""
+    Ms, K = 8e5, 3e4
+    u = np.array([1.0, 2.0, -2.0]) / 3.0
+    w = np.array([2.0, 1.0, 2.0]) / 3.0  # unit, perpendicular to u
+    d = math.cos(theta) * u + math.sin(theta) * w
+    M = workloads.uniform_m((2, 3, 1), Ms, d)
+    H = fields.anisotropy_field(M, Ms, K, u)
+    ref = 2 * K / (MU0 * Ms) * math.cos(theta) * u
+    assert np.max(np.abs(H[:, 0, 1, 1] - ref)) <= 1e-12 * 2 * K / (MU0 * Ms)
+
+
+def test_anisotropy_field_is_minus_energy_gradient():
+    """H_an = -(1/(mu0 V)) dE_an/dM per cell, with E_an = V K (1 - (M.u)^2/Ms^2)
+    summed over cells (the anisotropy term of the oracle's energy): central
+    differences at a random state with a tilted axis."""
+    Ms, K = 1.1e6, 5e5
+    cell = (2e-9, 3e-9, 4e-9)
+    V = cell[0] * cell[1] * cell[2]
+    p = workloads.problem((3, 2, 2), cell, Ms, 0.0, 0.1, K=K, easy=(0.3, -0.5, 0.8), Ha=(0.0, 0.0, 0.0))
+    pa = fields.problem_arrays(p)
+    M = workloads.random_m(p["n"], Ms, 11)
+    Hd = np.zeros_like(M)
+    H = fields.anisotropy_field(M, Ms, K, pa["u"])
+    step = 1e-3 * Ms
+    for idx in [(0, 0, 0, 0), (1, 1, 0, 2), (2, 0, 1, 1), (1, 0, 1, 0)]:
+        Mp, Mm = M.copy(), M.copy()
+        Mp[idx] += step
+        Mm[idx] -= step
+        dE = (fields.energy(Mp, Hd, pa) - fields.energy(Mm, Hd, pa)) / (2 * step)
+        # E is quadratic in M: the central difference is exact up to rounding
+        assert abs(-dE / (MU0 * V) - H[idx]) <= 1e-7 * 2 * K / (MU0 * Ms), idx
+
+
 def test_rhs_is_orthogonal_to_m_and_satisfies_gilbert_form():
     Ms, alpha, gamma = 8e5, 0.3, 2.211e5
     M = workloads.random_m((5, 4, 3), Ms, 7)

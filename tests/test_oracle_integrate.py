@@ -97,6 +97,27 @@ def test_energy_decreases_under_damping():
     assert E[-1] < E[0]
 
 
+def test_energy_decreases_under_damping_with_anisotropy():
+    """The same with uniaxial anisotropy along a tilted axis (K = 5e5 J/m^3,
+    the slab's material): the anisotropy term joins the energy balance."""
+    p = workloads.problem((8, 8, 2), (2e-9, 2e-9, 2e-9), 1.1e6, 2e-11, 0.5, K=5e5, easy=(0.2, -0.3, 0.9),
+                          Ha=(-20e3, 1e3, 0.0))
+    pa = fields.problem_arrays(p)
+    M0 = workloads.random_m(p["n"], p["Ms"], 6)
+    it = integrate.Integrator(p, M0, method="RK4", h=1e-15, renormalize=True)
+    E = [fields.energy(it.M, it.demag(it.M), pa)]
+    for _ in range(40):
+        it.step()
+        E.append(fields.energy(it.M, it.demag(it.M), pa))
+    dE = np.diff(E)
+    assert np.all(dE <= 1e-9 * abs(E[0]))
+    assert E[-1] < E[0]
+    # the anisotropy energy changes along the run (the term is exercised)
+    u = pa["u"]
+    ani = lambda M: np.sum(1 - (np.einsum("i...,i->...", M, u) / p["Ms"]) ** 2)
+    assert abs(ani(it.M) - ani(M0)) > 1e-3 * ani(M0)
+
+
 def test_magnetization_length():
     p = _film()
     M0 = workloads.random_m(p["n"], p["Ms"], 5)

@@ -4,6 +4,7 @@ import json
 import os
 
 import numpy as np
+import pytest
 
 import workloads
 from oracle import integrate, metrics
@@ -18,6 +19,12 @@ def test_epsilon_identity_and_uniform_offset():
     assert abs(metrics.epsilon_map(M + d, M, 8e5) - 5e3 / 8e5) < 1e-15
     s = np.random.default_rng(0).standard_normal((10, 3))
     assert abs(metrics.epsilon_series(s + np.array([0, 0, 2.0]), s, 4.0) - 0.5) < 1e-15
+
+
+def test_epsilon_series_refuses_series_of_different_length():
+    s = np.zeros((10, 3))
+    with pytest.raises(ValueError):
+        metrics.epsilon_series(s[:9], s, 1.0)
 
 
 def test_controller_constants_match_paper():
