@@ -21,10 +21,16 @@ all terms with total moment order <= 2K are kept.  Taylor coefficients of 1/r
 come from the Cartesian recurrence (obtained from r^2 = x.x by Leibniz' rule)
 |k| r^2 a_k = -(2|k|-1) sum_i x_i a_{k-e_i} - (|k|-1) sum_i a_{k-2e_i}.
 
-The switch between the two forms (``R >= R_SWITCH * max(dx,dy,dz)`` uses the
-expansion) and its order ``K_ORDER`` are this implementation's reading, not the
-paper's, chosen so that each form is used where its float64 error is ~1e-10
-of V/(4 pi R^3) or better.
+The switch between the two forms and the order ``K_ORDER`` are this
+implementation's reading, not the paper's.  The expansion is used when
+R >= min(R_SWITCH_SIDE * max(dx,dy,dz), R_SWITCH_VOL * (dx dy dz)^(1/3)).
+The float64 error of the exact form grows with R measured in the cube root
+of the cell volume (its second differences take steps of the cell sides, so
+a flat or elongated cell cancels more at the same R than a cube of its
+longest side); the expansion's truncation error falls with R measured in the
+longest side.  With these constants and order, both stay within ~1.1e-10 of
+V/(4 pi R^3) on either side of the switch for cubes and for cells with side
+ratios up to 10:3 (checked against 50-digit values of the exact form).
 
 Pins (tests/test_oracle_newell.py): self term vs Aharoni's closed-form prism
 factor, trace 1, 1/3 for a cube, parity symmetries, 4-D Gauss-Legendre
@@ -37,8 +43,9 @@ derivatives of 1/r.
 import math
 import numpy as np
 
-R_SWITCH = 6.0   # expansion used when R >= R_SWITCH * max cell side
-K_ORDER = 6      # moment expansion kept through total order 2*K_ORDER
+R_SWITCH_SIDE = 6.0  # expansion used when R >= R_SWITCH_SIDE * longest cell side ...
+R_SWITCH_VOL = 7.0   # ... or when R >= R_SWITCH_VOL * (cell volume)^(1/3)
+K_ORDER = 7          # moment expansion kept through total order 2*K_ORDER
 
 COMPONENTS = ("xx", "yy", "zz", "xy", "xz", "yz")
 # parity of each component under x->-x, y->-y, z->-z (True = odd)
@@ -169,13 +176,18 @@ def newell_asymptotic(X, Y, Z, dx, dy, dz, K=K_ORDER):
     return np.stack(out, axis=-1)
 
 
-def tensor_at(X, Y, Z, dx, dy, dz, r_switch=R_SWITCH, K=K_ORDER):
+def switch_radius(dx, dy, dz):
+    """Offset length (metres) from which the moment expansion replaces the exact form."""
+    return min(R_SWITCH_SIDE * max(dx, dy, dz), R_SWITCH_VOL * (dx * dy * dz) ** (1.0 / 3.0))
+
+
+def tensor_at(X, Y, Z, dx, dy, dz, K=K_ORDER):
     """Tensor at offsets (arrays, metres): exact Newell near, moment expansion far; (..., 6)."""
     X, Y, Z = np.broadcast_arrays(*(np.asarray(v, dtype=np.float64) for v in (X, Y, Z)))
     shape = X.shape
     X, Y, Z = X.ravel(), Y.ravel(), Z.ravel()
     R = np.sqrt(X * X + Y * Y + Z * Z)
-    far = R >= r_switch * max(dx, dy, dz)
+    far = R >= switch_radius(dx, dy, dz)
     out = np.zeros((X.size, 6))
     near = ~far
     if near.any():

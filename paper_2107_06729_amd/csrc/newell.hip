@@ -80,9 +80,16 @@ __device__ void newell_exact(double X, double Y, double Z, double dx, double dy,
 // with D^k(1/r) = k! a_k and the Taylor coefficients a_k of 1/r generated
 // layer by layer (|k| = n) from
 //   n r^2 a_k = -(2n-1) sum_i x_i a_{k-e_i} - (n-1) sum_i a_{k-2e_i}.
-constexpr int FAR_K = 6;
+// The far form is used from R >= min(6 max(dx,dy,dz), 7 (dx dy dz)^(1/3)):
+// the float64 cancellation of the exact form grows with R in units of the
+// cube root of the cell volume, the truncation error of the expansion falls
+// with R in units of the longest side; with total moment order 14 both stay
+// near 1e-10 of V/(4 pi R^3) at the switch for cubes and for flat or
+// elongated cells.
+constexpr int FAR_K = 7;
 constexpr int FAR_N = 2 * FAR_K + 2;
-constexpr double FAR_SWITCH = 6.0;  // far form for R >= FAR_SWITCH * max(dx,dy,dz)
+constexpr double FAR_SWITCH_SIDE = 6.0;
+constexpr double FAR_SWITCH_VOL = 7.0;
 
 __device__ __forceinline__ int lidx(int n, int i, int j) { return i * (n + 1) - (i * (i - 1)) / 2 + j; }
 
@@ -156,8 +163,9 @@ __global__ void k_newell_octant(int nx, int ny, int nz, double dx, double dy, do
     const double ux = dx / s, uy = dy / s, uz = dz / s;
     const double X = ix * ux, Y = iy * uy, Z = iz * uz;
     const double R = sqrt(X * X + Y * Y + Z * Z);
+    const double Rs = fmin(FAR_SWITCH_SIDE, FAR_SWITCH_VOL * cbrt(ux * uy * uz));  // longest side = 1
     double N[6];
-    if (R >= FAR_SWITCH)
+    if (R >= Rs)
         newell_far(X, Y, Z, ux, uy, uz, N);
     else
         newell_exact(X, Y, Z, ux, uy, uz, N);

@@ -3,8 +3,9 @@ the LLG right-hand side, against the CPU FP64 oracle on the same seeded inputs.
 
 Tolerances: FP64 1e-12 relative (max norm) with the oracle's tensor uploaded
 to both sides; FP32 1e-5 Ms on fields; the GPU's own Newell tensor within
-5e-10 of V/(4 pi R^3) of the oracle's (both are float64 evaluations of the
-same definition whose cancellation error is ~1e-10 at the far-field switch).
+5e-10 of V/(4 pi R^3) of the oracle's and of 50-digit values of the exact
+form on both sides of the far-field switch (both sides are float64
+evaluations of the same definition, whose error is ~1e-10 at the switch).
 """
 
 import math
@@ -29,6 +30,8 @@ MESHES = [
     ((24, 20, 3), (5e-9, 5e-9, 3e-9)),
     ((40, 33, 9), (2e-9, 2e-9, 2e-9)),
     ((256, 64, 1), (5e-9, 5e-9, 3e-9)),
+    # a flat cell (side ratio 10:3) with offsets past the far-field switch on every axis
+    ((12, 10, 24), (1e-9, 1e-9, 0.3e-9)),
     # the largest padded lengths: 2048 along x and y, 1024 along z
     ((1024, 3, 2), (2e-9, 3e-9, 2e-9)),
     ((3, 1024, 2), (3e-9, 2e-9, 2e-9)),
@@ -65,24 +68,24 @@ def test_newell_tensor_on_gpu(n, cell):
     ref = newell.tensor_octant(n, cell)
     s = sim(film(n, cell), "f64")
     got = s.get_demag_tensor()
-    # The float64 exact form just inside the far-field switch cancels more
-    # for elongated cells: for a 3x2x1 cell the oracle is 5.9e-10 of
-    # V/(4 pi R^3) away from the 50-digit form at offset (0, 0, 17), and the
-    # GPU's own float64 evaluation carries an error of the same size.
-    elongated = max(cell) / min(cell) > 2
-    assert scaled_tensor_error(got, ref, cell) < (1.5e-9 if elongated else 5e-10)
-    if elongated:
-        import mpmath as mp
-        from tests.test_oracle_newell import _newell_mp
-        V = cell[0] * cell[1] * cell[2]
-        for off in [(0, 0, 17), (2, 0, 16), (0, 1, 17)]:
-            if any(o >= m for o, m in zip(off, n)):
+    assert scaled_tensor_error(got, ref, cell) < 5e-10
+    # spot values against the 50-digit exact form, near the far-field switch
+    import mpmath as mp
+    from tests.test_oracle_newell import _newell_mp
+    V = cell[0] * cell[1] * cell[2]
+    Rs = newell.switch_radius(*cell)
+    for d in [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 1)]:
+        step = math.sqrt(sum((a * c) ** 2 for a, c in zip(d, cell)))
+        m = int(Rs / step)  # the last offset inside the switch along d, and the first outside
+        for mm in (m, m + 1):
+            off = tuple(mm * a for a in d)
+            if mm < 1 or any(o >= k for o, k in zip(off, n)):
                 continue
-            R = [o * d for o, d in zip(off, cell)]
+            R = [o * c for o, c in zip(off, cell)]
             with mp.workdps(50):
                 exact = _newell_mp(*R, *cell)
             scale = V / (4 * math.pi * max(math.sqrt(sum(r * r for r in R)), max(cell)) ** 3)
-            assert np.max(np.abs(got[:, off[2], off[1], off[0]] - exact)) / scale < 1e-9, off
+            assert np.max(np.abs(got[:, off[2], off[1], off[0]] - exact)) / scale < 5e-10, off
     n00 = s.self_tensor()
     assert np.allclose(n00, newell.aharoni_prism(*cell), rtol=0, atol=1e-14)
     # the GPU's own kernel gives the oracle's field to the tensor's accuracy

@@ -98,9 +98,10 @@ def _replay(ora, ig):
 def test_adaptive_steps_fp32_schedule_replay(method, extrap):
     """FP32 adaptive runs: the oracle replays the GPU's accepted step sizes
     (the controller's decisions rest on FP32 error estimates, so the schedule
-    is the GPU's), and every state stays within 1e-5 Ms of the oracle's; each
-    step's error estimate agrees to the FP32 noise of its difference of
-    stage derivatives."""
+    is the GPU's), and every state stays within 1e-5 Ms of the oracle's.  Each
+    step's error estimate e = max |h sum (b - b^) F| / Ms agrees within 1 % plus
+    what an FP32 field error dH moves it: h sum |b - b^| g' (1 + alpha) dH,
+    with dH = 1e-6 Ms (the FP32 fields here are within ~3e-7 Ms)."""
     log(f"adaptive fp32 replay {method} {extrap}")
     p = film(N_SMALL, CELL_SMALL, alpha=0.1)
     Nf = newell.tensor_full(N_SMALL, CELL_SMALL)
@@ -110,10 +111,13 @@ def test_adaptive_steps_fp32_schedule_replay(method, extrap):
     s = sim(p, "f32", tensor=Nf)
     s.set_m(to_dev(M0, "f32"))
     st = _stepper(method, extrap, 1e-13, adaptive=True)
+    gp = p["gamma"] / (1 + p["alpha"] ** 2)
+    sdb = sum(abs(v) for v in ora.db)
     for k in range(14):
         ig = s.step(st)
         io = _replay(ora, ig)
-        assert abs(ig["err"] - io["err"]) <= 1e-2 * io["err"] + 1e-9, (k, ig["err"], io["err"])
+        floor = ig["h_used"] * sdb * gp * (1 + p["alpha"]) * 1e-6 * p["Ms"]
+        assert abs(ig["err"] - io["err"]) <= 1e-2 * io["err"] + floor, (k, ig["err"], io["err"], floor)
         got = to_host(s.get_m())
         assert np.max(np.abs(got - ora.M)) <= 1e-5 * p["Ms"], k
     c = s.counters()

@@ -206,17 +206,45 @@ def _newell_mp(X, Y, Z, dx, dy, dz):
         st(_g_mp), st(lambda a, b, c: _g_mp(a, c, b)), st(lambda a, b, c: _g_mp(b, c, a)))])
 
 
-@pytest.mark.parametrize("cell", [(1.0, 1.0, 1.0), (5.0, 5.0, 3.0), (1.0, 1.0, 0.3)])
-@pytest.mark.parametrize("off", [(1, 1, 0), (3, 2, 1), (5, 0, 0), (4, 3, 2), (6, 0, 0), (5, 4, 1),
-                                 (7, 5, 2), (12, 3, 1), (20, 11, 3), (0, 0, 9)])
-def test_tensor_vs_50_digit_exact_form(cell, off):
+def _err_vs_50_digits(cell, off):
     with mp.workdps(50):
         R = tuple(o * d for o, d in zip(off, cell))
         ref = _newell_mp(*R, *cell)
     got = newell.tensor_at(*R, *cell)
     V = cell[0] * cell[1] * cell[2]
     Rn = max(math.sqrt(sum(r * r for r in R)), max(cell))
-    assert np.max(np.abs(got - ref)) / (V / (4 * math.pi * Rn ** 3)) < 5e-10
+    return np.max(np.abs(got - ref)) / (V / (4 * math.pi * Rn ** 3))
+
+
+@pytest.mark.parametrize("cell", [(1.0, 1.0, 1.0), (5.0, 5.0, 3.0), (1.0, 1.0, 0.3), (3.0, 2.0, 1.0)])
+@pytest.mark.parametrize("off", [(1, 1, 0), (3, 2, 1), (5, 0, 0), (4, 3, 2), (6, 0, 0), (5, 4, 1),
+                                 (7, 5, 2), (12, 3, 1), (20, 11, 3), (0, 0, 9), (0, 0, 17), (2, 0, 16)])
+def test_tensor_vs_50_digit_exact_form(cell, off):
+    assert _err_vs_50_digits(cell, off) < 2e-10
+
+
+_SWITCH_CELLS = [(1.0, 1.0, 1.0), (5.0, 5.0, 3.0), (3.0, 2.0, 1.0), (1.0, 1.0, 0.3), (2.0, 3.0, 2.5), (1.0, 2.0, 1.0),
+                 (1.0, 0.4, 1.0)]
+
+
+@pytest.mark.parametrize("cell", _SWITCH_CELLS, ids=["x".join(map(str, c)) for c in _SWITCH_CELLS])
+def test_tensor_on_both_sides_of_the_switch_vs_50_digits(cell):
+    """Offsets along the axes, face and body diagonals whose length lies
+    within 15 % of the switch radius, on both sides: the exact form just
+    inside it and the moment expansion just outside it are both within
+    2e-10 of V/(4 pi R^3) of the 50-digit exact form, for cubes and for
+    flat or elongated cells (side ratios up to 10:3)."""
+    Rs = newell.switch_radius(*cell)
+    offs = []
+    for d in [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (0, 1, 1), (1, 1, 1), (2, 1, 0), (1, 0, 2)]:
+        step = math.sqrt(sum((a * c) ** 2 for a, c in zip(d, cell)))
+        for m in range(1, 200):
+            if 0.85 * Rs <= m * step <= 1.15 * Rs:
+                offs.append(tuple(m * a for a in d))
+    inside = [o for o in offs if math.sqrt(sum((a * c) ** 2 for a, c in zip(o, cell))) < Rs]
+    assert inside and len(inside) < len(offs)  # both forms are exercised
+    worst = max(_err_vs_50_digits(cell, o) for o in offs)
+    assert worst < 2e-10, worst
 
 
 def test_inverse_r_taylor_recurrence_vs_sympy():
