@@ -171,6 +171,30 @@ llgx_status llgx_heff(llgx_handle h, const void* M_dev, void* H_dev);
 /* F(t, M) of Eq. (1) in explicit Landau-Lifshitz form, exact demag. */
 llgx_status llgx_rhs(llgx_handle h, const void* M_dev, void* F_dev);
 
+/* ---- Field evaluation that allocates nothing ---------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * llgx_demag_noalloc computes exactly what llgx_demag computes (the same
+ * kernels and launch variants, so the same bits), but its FFT spectra and
+ * its empty-cell flag live in a static device array of the library of
+ * LLGX_NOALLOC_SCRATCH_BYTES, one per GPU the library runs on, held until
+ * the process ends (not in the handle's workspace).  The call allocates and
+ * frees nothing, issues no hipMemset, and enqueues kernels only.
+ * The mesh must fit: 256 + round_up(SA, 256) + SB bytes, with
+ *   SA = 3 nz ny SX c, SB = 3 nz Py SX c (0 when ny = 1),
+ *   Px/Py = next power of two >= 2 nx - 1 / 2 ny - 1 (1 for nx/ny = 1),
+ *   SX = round_up(Px/2 + 1, 16), c = bytes per stored complex value
+ *   (16 FP64, 8 FP32, 4 with 16-bit spectra); e.g. FP32 256x256x16 needs
+ *   80.2 MB.  A larger mesh gives LLGX_E_ARG and enqueues nothing.
+ * Every call on one GPU uses that GPU's one array: calls whose work overlaps
+ * on a GPU (other streams, other host threads) race and must be ordered by
+ * the caller.  The array keeps the last call's contents; the flag is cleared
+ * by a kernel at every call and the spectra are fully rewritten before they
+ * are read (their padding columns, never read into a result, are left).
+ * Errors as llgx_demag (LLGX_E_STATE before llgx_precompute_demag). */
+#define LLGX_NOALLOC_SCRATCH_BYTES (128u << 20)
+llgx_status llgx_demag_noalloc(llgx_handle h, const void* M_dev, void* H_dev);
+
 /* One accepted step of Eq. (3)-(4) from the handle's (t, M).  With
  * s->adaptive the Eq. (5) controller repeats rejected attempts and the next
  * call starts from info->h_next; otherwise s->h is used.  A change of method

@@ -73,6 +73,7 @@ _sig = {
     "llgx_demag": (_S, [_H, _P, _P]),
     "llgx_heff": (_S, [_H, _P, _P]),
     "llgx_rhs": (_S, [_H, _P, _P]),
+    "llgx_demag_noalloc": (_S, [_H, _P, _P]),
     "llgx_step": (_S, [_H, ctypes.POINTER(Stepper), ctypes.POINTER(StepInfo)]),
     "llgx_run_fixed": (_S, [_H, ctypes.POINTER(Stepper), ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(StepInfo)]),
     "llgx_run": (_S, [_H, ctypes.POINTER(Stepper), ctypes.c_double, ctypes.c_double, _P, ctypes.c_int64,
@@ -281,6 +282,21 @@ class Sim:
 
     def demag(self, M):
         return self._field(_lib.llgx_demag, M)
+
+    def demag_noalloc(self, M, out=None):
+        """llgx_demag with the library's static scratch instead of the handle's
+        spectra; with out given (a contiguous tensor of M's shape and dtype on
+        the handle's device) the call itself allocates nothing."""
+        M = self._dev(M)
+        if out is None:
+            out = self.torch.empty_like(M)
+        elif tuple(out.shape) != self.shape or out.dtype != self.dtype or not out.is_contiguous():
+            raise ValueError("out must be a contiguous tensor of the field's shape and dtype")
+        with _Ordered(self, M, out):
+            _check(_lib.llgx_demag_noalloc(self._h, ctypes.c_void_p(M.data_ptr()), ctypes.c_void_p(out.data_ptr())),
+                   self._h)
+        self._keep = M
+        return out
 
     def heff(self, M):
         return self._field(_lib.llgx_heff, M)

@@ -202,6 +202,8 @@ template <typename T>
 hipError_t launch_detect_empty(hipStream_t s, long ncell, int nb, const T* M, int* flag);
 template <typename T>
 hipError_t launch_renorm(hipStream_t s, long ncell, int nb, T* M, double Ms);
+// p[0..n) = v by a kernel (no hipMemsetAsync)
+hipError_t launch_fill_int(hipStream_t s, int* p, int n, int v);
 template <typename T>
 hipError_t launch_mean(hipStream_t s, long ncell, const T* M, double* parts, int nparts);
 hipError_t launch_reduce_sum3(hipStream_t s, const double* parts, int nparts, double* out);

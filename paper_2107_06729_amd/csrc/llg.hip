@@ -355,6 +355,13 @@ __global__ __launch_bounds__(NTS) void k_detect_empty(long ncell, int nb, const 
     }
 }
 
+// p[0..n) = v: clears flags without hipMemsetAsync (callers may capture the
+// stream into a graph)
+__global__ __launch_bounds__(NTS) void k_fill_int(int* __restrict__ p, int n, int v) {
+    const int i = blockIdx.x * NTS + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 template <typename T>
 __global__ __launch_bounds__(NTS) void k_mean(long ncell, const T* __restrict__ M, double* __restrict__ parts) {
     __shared__ double red[3][NTS];
@@ -533,6 +540,12 @@ hipError_t launch_renorm(hipStream_t s, long ncell, int nb, T* M, double Ms) {
 template <typename T>
 hipError_t launch_detect_empty(hipStream_t s, long ncell, int nb, const T* M, int* flag) {
     k_detect_empty<T><<<grid_for(ncell * nb), NTS, 0, s>>>(ncell, nb, M, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_int(hipStream_t s, int* p, int n, int v) {
+    if (n < 1) return hipSuccess;
+    k_fill_int<<<(unsigned)((n + NTS - 1) / NTS), NTS, 0, s>>>(p, n, v);
     return hipGetLastError();
 }
 

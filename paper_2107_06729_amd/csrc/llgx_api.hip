@@ -23,6 +23,13 @@ namespace llgx {
 
 static thread_local std::string g_create_error;
 
+// Scratch of llgx_demag_noalloc: one copy per device, held until the process
+// ends.  Host code never uses this name as an address: create_ctx resolves
+// the device's own address with hipGetSymbolAddress once per device.
+static __device__ __align__(256) unsigned char scratch[LLGX_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_dev;  // device ordinal -> device address of `scratch`
+
 static int next_pow2(long v) {
     int p = 1;
     while (p < v) p <<= 1;
@@ -86,6 +93,9 @@ struct Ctx {
     int* empty_flag = nullptr;  // device: [0] some cell of M has M = 0; [1] the same for the
                                 // input of a field call (llgx_demag / heff / rhs)
     bool field_input = false;   // phys() reads flag [1] (during a field call)
+    const int* empty_use = nullptr;  // when set, phys() reads this flag instead
+    void* spec_use[2] = {nullptr, nullptr};  // when set, the spectra A and B of the passes
+    void* noalloc = nullptr;    // device address of this device's llgx_demag_noalloc scratch
     double* octant = nullptr;   // real-space tensor for offsets 0..n-1 (double)
     bool have_kernel = false;
     long kernel_gen = 0;        // bumped whenever the tensor (and N00) changes
@@ -235,7 +245,7 @@ static Phys<T> phys(const Ctx* c) {
     ph.nz = c->nz;
     ph.nb = c->nb;
     ph.hab = (const T*)c->hab;
-    ph.empty = c->empty_flag + (c->field_input ? 1 : 0);
+    ph.empty = c->empty_use ? c->empty_use : c->empty_flag + (c->field_input ? 1 : 0);
     return ph;
 }
 
@@ -284,8 +294,8 @@ static bool pass_exists(const Ctx* c, int kind) {
 template <typename T, typename S>
 static llgx_status run_pass(Ctx* c, int kind, const EvalArgs<T>& a) {
     hipStream_t s = c->stream;
-    void* A = c->specA;
-    void* B = c->specB;
+    void* A = c->spec_use[0] ? c->spec_use[0] : c->specA;
+    void* B = c->spec_use[1] ? c->spec_use[1] : c->specB;
     const cx<T>* twL = table<T>(c, c->LX, false);
     const cx<T>* twP = table<T>(c, c->Px, false);
     const bool native = std::is_same<T, S>::value;
@@ -1239,6 +1249,23 @@ static llgx_status tune_ctx(Ctx* c, int reps, double us_out[5]) {
     return LLGX_OK;
 }
 
+// Device address of this device's `scratch`, resolved once per device with
+// that device current (the one the handle is created on).
+static llgx_status scratch_address(Ctx* c) {
+    int dev = -1;
+    HIPCHK(c, hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_dev.find(dev);
+    if (it == g_scratch_dev.end()) {
+        void* ptr = nullptr;
+        HIPCHK(c, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return c->fail(LLGX_E_HIP, "hipGetSymbolAddress gave no address for the scratch array");
+        it = g_scratch_dev.emplace(dev, ptr).first;
+    }
+    c->noalloc = it->second;
+    return LLGX_OK;
+}
+
 static llgx_status create_ctx(const llgx_problem* p, int nb, const double* ha_list, int32_t precision,
                               int32_t spectral, void* hip_stream, Ctx** out, std::string& err) {
     *out = nullptr;
@@ -1330,6 +1357,13 @@ static llgx_status create_ctx(const llgx_problem* p, int nb, const double* ha_li
             st = c->prec == LLGX_F32 ? make_table<float>(c, c->tw_work, L) : make_table<double>(c, c->tw_work, L);
         }
     }
+    if (st != LLGX_OK) {
+        err = c->err;
+        release(c);
+        delete c;
+        return st;
+    }
+    if (st == LLGX_OK) st = scratch_address(c);
     if (st != LLGX_OK) {
         err = c->err;
         release(c);
@@ -1761,6 +1795,40 @@ static llgx_status field_call(llgx_handle h, const void* M_dev, void* out_dev, i
 llgx_status llgx_demag(llgx_handle h, const void* M_dev, void* H_dev) { return field_call(h, M_dev, H_dev, XINV_DEMAG); }
 llgx_status llgx_heff(llgx_handle h, const void* M_dev, void* H_dev) { return field_call(h, M_dev, H_dev, XINV_HEFF); }
 llgx_status llgx_rhs(llgx_handle h, const void* M_dev, void* F_dev) { return field_call(h, M_dev, F_dev, XINV_RHS); }
+
+llgx_status llgx_demag_noalloc(llgx_handle h, const void* M_dev, void* H_dev) {
+    if (!h) return LLGX_E_ARG;
+    Ctx* c = (Ctx*)h;
+    if (!M_dev || !H_dev) return c->fail(LLGX_E_ARG, "null pointer");
+    if (!c->have_kernel) return c->fail(LLGX_E_STATE, "demag kernel not computed (llgx_precompute_demag)");
+    if (!c->noalloc) return c->fail(LLGX_E_STATE, "no scratch address on this device");
+    // layout: [0, 256) the empty-cell flag, then spectrum A, then spectrum B
+    const size_t cbytes = c->spectral == LLGX_SPEC_NATIVE ? 2 * c->tsz : 4;
+    const size_t bytesA = 3 * (size_t)c->nz * c->ny * c->SX * cbytes * c->nb;
+    const size_t bytesB = c->Py > 1 ? 3 * (size_t)c->nz * c->Py * c->SX * cbytes * c->nb : 0;
+    const size_t offA = 256, offB = offA + (bytesA + 255) / 256 * 256;
+    const size_t need = offB + bytesB;
+    if (need > (size_t)LLGX_NOALLOC_SCRATCH_BYTES)
+        return c->fail(LLGX_E_ARG, "mesh needs %zu bytes of scratch; llgx_demag_noalloc has %zu", need,
+                       (size_t)LLGX_NOALLOC_SCRATCH_BYTES);
+    char* base = (char*)c->noalloc;
+    int* flag = (int*)base;
+    HIPCHK(c, launch_fill_int(c->stream, flag, 1, 0));
+    if (c->prec == LLGX_F32)
+        HIPCHK(c, launch_detect_empty<float>(c->stream, c->ncell, c->nb, (const float*)M_dev, flag));
+    else
+        HIPCHK(c, launch_detect_empty<double>(c->stream, c->ncell, c->nb, (const double*)M_dev, flag));
+    c->empty_use = flag;
+    c->spec_use[0] = base + offA;
+    c->spec_use[1] = bytesB ? base + offB : nullptr;
+    XinvOut out{H_dev, nullptr, nullptr};
+    llgx_status st = c->prec == LLGX_F32
+                         ? eval_exact<float>(c, plain<float>(M_dev), nullptr, XINV_DEMAG, (const float*)M_dev, out)
+                         : eval_exact<double>(c, plain<double>(M_dev), nullptr, XINV_DEMAG, (const double*)M_dev, out);
+    c->empty_use = nullptr;
+    c->spec_use[0] = c->spec_use[1] = nullptr;
+    return st;
+}
 
 llgx_status llgx_step(llgx_handle h, const llgx_stepper* s, llgx_step_info* info) {
     if (!h) return LLGX_E_ARG;
