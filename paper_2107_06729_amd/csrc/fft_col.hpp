@@ -21,6 +21,12 @@
 // loaded once per row for all PN columns.  Groups >= ng (inactive) and packs
 // starting at a column >= ncol are neither read (they transform zeros) nor
 // written.
+//
+// HALF_IN: the caller guarantees that input rows >= L/2 are zero (a zero
+// padded forward transform: n_in <= L/2), so stage 0 neither loads them nor
+// transforms them (its radix-R0 butterflies take R0/2 non-zero inputs).
+// HALF_OUT: only output rows < L/2 are wanted (n_out <= L/2), so the last
+// stage forms only the first half of its radix-8 outputs.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -44,7 +50,8 @@ struct Base1 {
 __device__ __forceinline__ unsigned row_off(int j, long gs) { return __umul24((unsigned)j, (unsigned)gs); }
 inline bool row_off_ok(int L, long gs) { return gs >= 0 && gs < (1L << 24) && (long)(L / 2) * gs < (1L << 32); }
 
-template <typename T, typename S, int L, bool INV, int TK, int NG, int NT>
+template <typename T, typename S, int L, bool INV, int TK, int NG, int NT, bool HALF_IN = false,
+          bool HALF_OUT = false>
 struct ColFFT {
     using C = cx<T>;
     using E = typename Spec<T, S>::elem;
@@ -71,25 +78,42 @@ struct ColFFT {
 
     struct Regs {
         PU v[U0][R0];
+        bool ok[U0][R0];  // the pack holds data (else it reads as zero)
     };
 
-    // issue the global loads of stage 0 (group rows at bases(g) + i * gs)
+    // issue the global loads of stage 0 (group rows at bases(g) + i * gs).
+    // Every load is issued, from an address clamped into the tile's data
+    // (group 0, the last pack that starts below ncol, the last input row),
+    // so a wave keeps all of them in flight at once; a load under a branch
+    // would be waited for at the branch's end.  Inactive units, packs past
+    // ncol and rows past n_in read as zero where the values are used.
     template <typename Bases>
     static __device__ __forceinline__ void load_first(Regs& rg, const Bases& bases, long gs, int n_in, int ncol,
                                                       int ng) {
 #pragma unroll
         for (int m = 0; m < U0; ++m) {
             const int u = threadIdx.x + m * NT;
-            const Unit t = unit(u);
-            const bool on = (NU0 % NT == 0 || u < NU0) && t.g < ng && t.p * PN < ncol;
-            const E* gp = bases(t.g) + t.p * PN + row_off(t.j, gs);
+            const bool live = NU0 % NT == 0 || u < NU0;
+            const Unit t = unit(live ? u : NU0 - 1);
+            const bool on = live && t.g < ng && t.p * PN < ncol;
+            const int pc = t.p * PN < ncol ? t.p : (ncol - 1) / PN;
+            const E* gp = bases(t.g < ng ? t.g : 0) + pc * PN;
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
-                const int row = t.j + r * (L / R0);
+                rg.ok[m][r] = false;
                 rg.v[m][r].raw = {};
-                if (on && row < n_in) rg.v[m][r].raw = *(const RW*)(gp + (long)(r * (L / R0)) * gs);
+                if (HALF_IN && 2 * r >= R0) continue;  // rows >= L/2: zero
+                const int row = t.j + r * (L / R0);
+                const int rowc = row < n_in ? row : n_in - 1;
+                rg.v[m][r].raw = *(const RW*)(gp + (long)rowc * gs);
+                rg.ok[m][r] = on && row < n_in;
             }
         }
+    }
+
+    static __device__ __forceinline__ C first_value(const Regs& rg, int m, int r, int q) {
+        const C v = Spec<T, S>::get(rg.v[m][r].e[q]);
+        return rg.ok[m][r] ? v : C{T(0), T(0)};
     }
 
     // stage 0 arithmetic on the loaded packs, outputs to LDS rows j R0 + r
@@ -104,7 +128,8 @@ struct ColFFT {
                 for (int q = 0; q < PN; ++q) {
                     C x[R0];
 #pragma unroll
-                    for (int r = 0; r < R0; ++r) x[r] = Spec<T, S>::get(rg.v[m][r].e[q]);
+                    for (int r = 0; r < R0; ++r)
+                        x[r] = (HALF_IN && 2 * r >= R0) ? C{T(0), T(0)} : first_value(rg, m, r, q);
                     dft_r<R0, INV>(x);
 #pragma unroll
                     for (int r = 0; r < R0; ++r) col[(t.j * R0 + r) * W + q] = x[r];
@@ -238,6 +263,7 @@ struct ColFFT {
 #pragma unroll
                     for (int r = 0; r < 8; ++r) {
                         const int row = t.j + r * NS;
+                        if (HALF_OUT && r >= 4) continue;  // rows >= L/2: not wanted
                         if (row < n_out) {
                             PU o;
 #pragma unroll
@@ -285,7 +311,8 @@ struct ColFFT {
 #pragma unroll
                 for (int q = 0; q < PN; ++q) {
 #pragma unroll
-                    for (int r = 0; r < R0; ++r) x[q][r] = Spec<T, S>::get(rg.v[m][r].e[q]);
+                    for (int r = 0; r < R0; ++r)
+                        x[q][r] = (HALF_IN && 2 * r >= R0) ? C{T(0), T(0)} : first_value(rg, m, r, q);
                     dft_r<R0, INV>(x[q]);
                 }
                 if (t.g < ng && t.p * PN < ncol) {

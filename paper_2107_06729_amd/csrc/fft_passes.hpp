@@ -77,7 +77,7 @@ __device__ __forceinline__ T combo_at(const Combo<T>& c, long i) {
 // A real sequence of length P = 2 LX is packed as z[j] = x[2j] + i x[2j+1],
 // transformed with a length-LX complex FFT and split with
 //   X[k] = (Z[k] + Z*[LX-k])/2 - i e^{-2 pi i k/P} (Z[k] - Z*[LX-k])/2.
-template <typename T, typename S, int LX, int ROWS>
+template <typename T, typename S, int LX, int ROWS, bool HALF>
 __global__ __launch_bounds__(NT) void k_xfwd(Combo<T> in, T* __restrict__ mk_out, int nin, long nrows,
                                              typename Spec<T, S>::elem* __restrict__ spec, int SX,
                                              const cx<T>* __restrict__ twL, const cx<T>* __restrict__ twP,
@@ -95,7 +95,9 @@ __global__ __launch_bounds__(NT) void k_xfwd(Combo<T> in, T* __restrict__ mk_out
         }
         return;
     } else {
-        using F = RowFFT<T, LX, false, ROWS, NT>;
+        // HALF (nin <= LX, a mesh row): packed inputs z[i] = x[2i] + i x[2i+1]
+        // with i >= LX/2 lie in the zero padding
+        using F = RowFFT<T, LX, false, ROWS, NT, HALF, false>;
         __shared__ C buf[F::LDS_ELEMS];
         __shared__ C twl[LX];
         __shared__ C twp[LX + 1];
@@ -124,28 +126,32 @@ __global__ __launch_bounds__(NT) void k_xfwd(Combo<T> in, T* __restrict__ mk_out
             }
         }
         const bool pairs = (nin & 1) == 0;  // rows start 8/16-byte aligned: load both reals at once
+        // every load is issued, from a clamped offset (element 0 for an empty
+        // slot), so a wave keeps all of them in flight; a load under a branch
+        // would be waited for at the branch's end.  Empty slots and the
+        // missing odd element of a row are zeroed after the combination.
         auto load2 = [&](const T* __restrict__ p, int m, int q) -> C {
-            C w{T(0), T(0)};
-            if (ok[m][q]) {
-                if (pairs) {
-                    w = *(const C*)(p + off[m][q]);
-                } else {
-                    w.x = p[off[m][q]];
-                    if (two[m][q]) w.y = p[off[m][q] + 1];
-                }
+            const long o = ok[m][q] ? off[m][q] : 0;
+            C w;
+            if (pairs) {
+                w = *(const C*)(p + o);
+            } else {
+                w.x = p[o];
+                w.y = p[two[m][q] ? o + 1 : o];
             }
             return w;
         };
+        constexpr int QN = HALF ? F::R0 / 2 : F::R0;  // inputs q >= QN lie in the zero half
 #pragma unroll
         for (int m = 0; m < F::U0; ++m)
 #pragma unroll
-            for (int q = 0; q < F::R0; ++q) v[m][q] = load2(in.base, m, q);
+            for (int q = 0; q < F::R0; ++q) v[m][q] = q < QN ? load2(in.base, m, q) : C{T(0), T(0)};
         for (int l = 0; l < in.nf; ++l) {
             C w[F::U0][F::R0];
 #pragma unroll
             for (int m = 0; m < F::U0; ++m)
 #pragma unroll
-                for (int q = 0; q < F::R0; ++q) w[m][q] = load2(in.f[l], m, q);
+                for (int q = 0; q < F::R0; ++q) w[m][q] = q < QN ? load2(in.f[l], m, q) : C{T(0), T(0)};
             const T cf = in.coef[l];
 #pragma unroll
             for (int m = 0; m < F::U0; ++m)
@@ -155,6 +161,13 @@ __global__ __launch_bounds__(NT) void k_xfwd(Combo<T> in, T* __restrict__ mk_out
                     v[m][q].y += cf * w[m][q].y;
                 }
         }
+#pragma unroll
+        for (int m = 0; m < F::U0; ++m)
+#pragma unroll
+            for (int q = 0; q < QN; ++q) {
+                if (!ok[m][q]) v[m][q] = C{T(0), T(0)};
+                if (!two[m][q]) v[m][q].y = T(0);
+            }
 #pragma unroll
         for (int m = 0; m < F::U0; ++m)
 #pragma unroll
@@ -200,7 +213,8 @@ __global__ __launch_bounds__(NT) void k_xinv(const typename Spec<T, S>::elem* __
                                              T hscale) {
     using C = cx<T>;
     constexpr int LXE = LX > 0 ? LX : 2;
-    using F = RowFFT<T, LXE, true, 3 * ROWS, NT>;
+    // only x < nx <= LX is kept: packed outputs z[j] with j < LX/2
+    using F = RowFFT<T, LXE, true, 3 * ROWS, NT, false, true>;
     constexpr int RS = LX > 0 ? F::RS : 1;
     __shared__ C buf[3 * ROWS * RS];
     __shared__ C twl[LXE];
@@ -329,14 +343,16 @@ __global__ __launch_bounds__(NT) void k_xinv(const typename Spec<T, S>::elem* __
 
 // ------------------------------------------------------------------------
 // strided column FFT: element (comp, outer, i, kx) at comp*cs + outer*os + i*is + kx
-template <typename T, typename S, int L, bool INV, int TK>
+// HALF: the forward transform's input rows >= L/2 are zero (n_in <= L/2) or
+// the inverse transform keeps only rows < L/2 (n_out <= L/2)
+template <typename T, typename S, int L, bool INV, int TK, bool HALF>
 __global__ __launch_bounds__(NT) void k_colfft(const typename Spec<T, S>::elem* __restrict__ src, long s_cs,
                                                long s_os, long s_is, int n_in,
                                                typename Spec<T, S>::elem* __restrict__ dst, long d_cs, long d_os,
                                                long d_is, int n_out, int Kx, const cx<T>* __restrict__ tw,
                                                T scale) {
     using C = cx<T>;
-    using F = ColFFT<T, S, L, INV, TK, 1, NT>;
+    using F = ColFFT<T, S, L, INV, TK, 1, NT, !INV && HALF, INV && HALF>;
     using E = typename Spec<T, S>::elem;
     // each XCD takes a contiguous run of tiles (xcd_run): when a tile row is
     // shorter than a 128-byte line, the neighbouring tiles that share its
@@ -528,8 +544,10 @@ __global__ __launch_bounds__(NT) void k_zmul(typename Spec<T, S>::elem* __restri
     using E = typename Spec<T, S>::elem;
     constexpr int L = LZ > 1 ? LZ : 2;  // LZ = 1 uses no transform
     constexpr int KZF = LZ / 2 + 1;
-    using Ff = ColFFT<T, S, L, false, TK, 6, NT>;
-    using Fi = ColFFT<T, S, L, true, TK, 6, NT>;
+    // rows z >= nz of the forward input are the zero padding and only rows
+    // z < nz of the inverse output are kept; nz <= Pz/2 always
+    using Ff = ColFFT<T, S, L, false, TK, 6, NT, true, false>;
+    using Fi = ColFFT<T, S, L, true, TK, 6, NT, false, true>;
     __shared__ C lb[LZ * 6 * TK];
     __shared__ T kl[LZ == 1 ? KZF * 6 * TK : 1];
     __shared__ C twl[L];

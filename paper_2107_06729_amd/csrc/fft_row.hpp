@@ -11,6 +11,10 @@
 // unit's row, unit u = threadIdx.x + m NT), so a caller can load them straight
 // from global memory (coalesced along the row) and fuse any pre-processing.
 // The last stage runs in place in LDS (each unit rewrites its own elements).
+// HALF_IN: elements >= L/2 of every row are zero (a zero padded forward
+// transform), so stage 0 drops them at compile time.  HALF_OUT: only
+// elements < L/2 are read afterwards, so the last stage forms only the first
+// half of its radix-8 outputs.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -18,7 +22,7 @@
 
 namespace llgx {
 
-template <typename T, int L, bool INV, int NR, int NT>
+template <typename T, int L, bool INV, int NR, int NT, bool HALF_IN = false, bool HALF_OUT = false>
 struct RowFFT {
     using C = cx<T>;
     static constexpr int R0 = first_radix(L);
@@ -55,6 +59,10 @@ struct RowFFT {
             if (live0(u)) {
                 int row, j;
                 unit<R0>(u, row, j);
+                if constexpr (HALF_IN) {
+#pragma unroll
+                    for (int q = R0 / 2; q < R0; ++q) x[m][q] = C{T(0), T(0)};
+                }
                 dft_r<R0, INV>(x[m]);
                 C* rb = buf + row * RS;
 #pragma unroll
@@ -130,7 +138,7 @@ struct RowFFT {
                     }
                     dft_r<8, INV>(x);
 #pragma unroll
-                    for (int r = 0; r < 8; ++r) rb[P(j + r * NS)] = x[r];
+                    for (int r = 0; r < (HALF_OUT ? 4 : 8); ++r) rb[P(j + r * NS)] = x[r];
                 }
             }
             __syncthreads();

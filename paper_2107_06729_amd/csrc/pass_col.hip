@@ -13,15 +13,26 @@ hipError_t launch_colfft(hipStream_t s, int L, bool inv, SpecPtr src, long s_cs,
     E* dp = (E*)dst;
     if (variant < 0 || variant >= NVAR_COL) return hipErrorInvalidValue;
     if (!row_off_ok(L, s_is) || !row_off_ok(L, d_is)) return hipErrorInvalidValue;
-#define CF_T(LL, TK)                                                                                             \
-    {                                                                                                            \
-        dim3 g((unsigned)((Kx + TK - 1) / TK), (unsigned)nouter, (unsigned)ncomp);                               \
-        if (inv)                                                                                                 \
-            k_colfft<T, S, LL, true, TK><<<g, NT, 0, s>>>(sp, s_cs, s_os, s_is, n_in, dp, d_cs, d_os, d_is, n_out, \
-                                                          Kx, tw, scale);                                        \
-        else                                                                                                     \
-            k_colfft<T, S, LL, false, TK><<<g, NT, 0, s>>>(sp, s_cs, s_os, s_is, n_in, dp, d_cs, d_os, d_is,     \
-                                                           n_out, Kx, tw, scale);                                \
+    // the mesh's own transforms pad or truncate by at least half (the y passes);
+    // the tensor setup transforms whole padded columns
+    const bool half = inv ? 2 * n_out <= L : 2 * n_in <= L;
+#define CF_H(LL, TK, INV, H)                                                                                 \
+    k_colfft<T, S, LL, INV, TK, H><<<g, NT, 0, s>>>(sp, s_cs, s_os, s_is, n_in, dp, d_cs, d_os, d_is, n_out, Kx, \
+                                                    tw, scale)
+#define CF_T(LL, TK)                                                                   \
+    {                                                                                  \
+        dim3 g((unsigned)((Kx + TK - 1) / TK), (unsigned)nouter, (unsigned)ncomp);     \
+        if (inv) {                                                                     \
+            if (half)                                                                  \
+                CF_H(LL, TK, true, true);                                              \
+            else                                                                       \
+                CF_H(LL, TK, true, false);                                             \
+        } else {                                                                       \
+            if (half)                                                                  \
+                CF_H(LL, TK, false, true);                                             \
+            else                                                                       \
+                CF_H(LL, TK, false, false);                                            \
+        }                                                                              \
     }
 #define CF(LL)                                          \
     case LL: {                                          \
@@ -44,6 +55,7 @@ hipError_t launch_colfft(hipStream_t s, int L, bool inv, SpecPtr src, long s_cs,
     }
 #undef CF
 #undef CF_T
+#undef CF_H
     return hipGetLastError();
 }
 

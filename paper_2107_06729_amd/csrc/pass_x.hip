@@ -11,9 +11,18 @@ hipError_t launch_xfwd(hipStream_t s, int LX, const Combo<T>& in, T* mk_out, int
     using E = typename Spec<T, S>::elem;
     E* sp = (E*)spec;
     if (variant < 0 || variant >= NVAR_XFWD) return hipErrorInvalidValue;
+    // mesh rows (nin <= LX) have a zero upper half; the tensor setup
+    // transforms whole padded rows (nin = 2 LX)
+    const bool half = nin <= LX;
 #define XF_R(L, R)                                                                                                \
-    k_xfwd<T, S, L, R><<<(unsigned)((nrows + R - 1) / R), NT, 0, s>>>(in, mk_out, nin, nrows, sp, SX, twL, twP, \
-                                                                      fscale)
+    do {                                                                                                          \
+        if (half)                                                                                                 \
+            k_xfwd<T, S, L, R, true><<<(unsigned)((nrows + R - 1) / R), NT, 0, s>>>(in, mk_out, nin, nrows, sp,  \
+                                                                                    SX, twL, twP, fscale);        \
+        else                                                                                                      \
+            k_xfwd<T, S, L, R, false><<<(unsigned)((nrows + R - 1) / R), NT, 0, s>>>(in, mk_out, nin, nrows, sp, \
+                                                                                     SX, twL, twP, fscale);       \
+    } while (0)
 #define XF(L)                                      \
     case L: {                                      \
         if (variant == 0)                          \
