@@ -120,11 +120,15 @@ __global__ __launch_bounds__(NTS) void k_epoly(long npack, EPoly<T> ep) {
     const long stride = (long)gridDim.x * NTS;
     for (long i0 = (long)blockIdx.x * NTS + threadIdx.x; i0 < npack; i0 += 2 * stride) {
         const bool two = i0 + stride < npack;
+        // the second pack is loaded whether it exists or not (from pack i0
+        // when it does not), so no load sits under a branch and all 2 NG
+        // loads are in flight together
+        const long i1 = two ? i0 + stride : i0;
         V g[2][NG];
 #pragma unroll
         for (int k = 0; k < NG; ++k) {
             g[0][k] = nt_load<T>(ep.g[k], i0);
-            if (two) g[1][k] = nt_load<T>(ep.g[k], i0 + stride);
+            g[1][k] = nt_load<T>(ep.g[k], i1);
         }
         for (int j = 0; j < ep.nd; ++j) {
 #pragma unroll
@@ -160,8 +164,11 @@ __global__ __launch_bounds__(NTS) void k_epoly_scalar(long n, EPoly<T> ep) {
 }
 
 // ---------------------------------------------------------------------------
-// per-cell sub-step kernels on a 2-D grid: blockDim (TX, RY), blockIdx.x over
-// row groups (row = y + ny z), blockIdx.y over x segments
+// per-cell sub-step kernels on a 2-D grid: blocks of tx x ry threads,
+// blockIdx.x over row groups (row = y + ny z), blockIdx.y over x segments.
+// The block shape comes in as a kernel argument: reading blockDim costs a
+// vector load from the dispatch packet that every wave waits for before its
+// first stencil load.
 struct CellIdx {
     int x, y, z, b;   // cell coordinates and sample
     long cell;        // cell index within the sample
@@ -170,13 +177,13 @@ struct CellIdx {
 };
 
 template <typename T>
-__device__ __forceinline__ CellIdx cell_index(const Phys<T>& ph) {
+__device__ __forceinline__ CellIdx cell_index(const Phys<T>& ph, int tx, int ry) {
     CellIdx c;
-    c.x = blockIdx.y * blockDim.x + threadIdx.x;
-    const int gy = (ph.ny + blockDim.y - 1) / blockDim.y;
+    c.x = blockIdx.y * tx + threadIdx.x;
+    const int gy = (ph.ny + ry - 1) / ry;
     int plane, yg;
     yslab(xcd_run(blockIdx.x, gridDim.x), gy, ph.nz * ph.nb, plane, yg);
-    c.y = yg * blockDim.y + threadIdx.y;
+    c.y = yg * ry + threadIdx.y;
     c.ok = c.x < ph.nx && c.y < ph.ny;
     c.b = plane / ph.nz;
     c.z = plane - c.b * ph.nz;
@@ -204,9 +211,9 @@ __device__ __forceinline__ void stage_rhs(const Combo<T>& mk, const Extrap<T>& e
 
 template <typename T>
 __global__ __launch_bounds__(NTS) void k_stage(Combo<T> mk, Extrap<T> ex, Phys<T> ph, T* __restrict__ F,
-                                               NextStage<T> nx) {
+                                               NextStage<T> nx, int tx, int ry) {
     const long N = (long)ph.nx * ph.ny * ph.nz;
-    const CellIdx ci = cell_index(ph);
+    const CellIdx ci = cell_index(ph, tx, ry);
     if (!ci.ok) return;
     // M0 of the chained output is loaded with the stencil, not after it
     T m0[3] = {T(0), T(0), T(0)};
@@ -230,10 +237,10 @@ __global__ __launch_bounds__(NTS) void k_stage(Combo<T> mk, Extrap<T> ex, Phys<T
 template <typename T, int NF>
 __global__ __launch_bounds__(NTS) void k_stage_final(Combo<T> mk, Extrap<T> ex, Phys<T> ph, const T* __restrict__ M0,
                                                      Final<T> fs, double inv_ms, T* __restrict__ mnew,
-                                                     double* __restrict__ parts) {
+                                                     double* __restrict__ parts, int tx, int ry) {
     const long N = (long)ph.nx * ph.ny * ph.nz;
-    const CellIdx ci = cell_index(ph);
-    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const CellIdx ci = cell_index(ph, tx, ry);
+    const int tid = threadIdx.y * tx + threadIdx.x;
     double emax = 0.0;
     if (ci.ok) {
         // M0 and the stored stage derivatives are loaded with the stencil
@@ -488,7 +495,7 @@ hipError_t launch_extrap_rhs(hipStream_t s, const Combo<T>& mk, const Extrap<T>&
                              const NextStage<T>& nx) {
     const CellGrid cg = cell_grid(ph.nx, ph.ny, ph.nz, ph.nb);
     if (ex.n != 1 || mk.nf != 0) return hipErrorInvalidValue;
-    k_stage<T><<<cg.grid, cg.block, 0, s>>>(mk, ex, ph, F, nx);
+    k_stage<T><<<cg.grid, cg.block, 0, s>>>(mk, ex, ph, F, nx, (int)cg.block.x, (int)cg.block.y);
     return hipGetLastError();
 }
 
@@ -499,7 +506,10 @@ hipError_t launch_stage_final(hipStream_t s, const Combo<T>& mk, const Extrap<T>
     if (ex.n != 1 || mk.nf != 0) return hipErrorInvalidValue;
     switch (fs.n) {
 #define SF(K)                                                                                                   \
-    case K: k_stage_final<T, K><<<cg.grid, cg.block, 0, s>>>(mk, ex, ph, M0, fs, inv_ms, mnew, parts); break;
+    case K:                                                                                                    \
+        k_stage_final<T, K><<<cg.grid, cg.block, 0, s>>>(mk, ex, ph, M0, fs, inv_ms, mnew, parts, (int)cg.block.x, \
+                                                         (int)cg.block.y);                                       \
+        break;
         SF(1) SF(2) SF(3) SF(4) SF(5) SF(6) SF(7) SF(8)
 #undef SF
         default: return hipErrorInvalidValue;
