@@ -233,10 +233,12 @@ __global__ __launch_bounds__(NTS) void k_stage(Combo<T> mk, Extrap<T> ex, Phys<T
 
 // last sub-step fused with Eq. (3): fs lists the stage derivatives used by
 // the update or the estimate; its final entry (index fs.n - 1) is this
-// stage's own F_S, which is taken from registers and never stored
+// stage's own F_S, which is taken from registers and never stored.  mnew may
+// be M0 itself (fixed steps): each cell's M0 is read before its update is
+// written, and no other cell's update reads it.
 template <typename T, int NF>
-__global__ __launch_bounds__(NTS) void k_stage_final(Combo<T> mk, Extrap<T> ex, Phys<T> ph, const T* __restrict__ M0,
-                                                     Final<T> fs, double inv_ms, T* __restrict__ mnew,
+__global__ __launch_bounds__(NTS) void k_stage_final(Combo<T> mk, Extrap<T> ex, Phys<T> ph, const T* M0,
+                                                     Final<T> fs, double inv_ms, T* mnew,
                                                      double* __restrict__ parts, int tx, int ry) {
     const long N = (long)ph.nx * ph.ny * ph.nz;
     const CellIdx ci = cell_index(ph, tx, ry);
@@ -277,8 +279,8 @@ __global__ __launch_bounds__(NTS) void k_stage_final(Combo<T> mk, Extrap<T> ex, 
 }
 
 template <typename T, int NF>
-__global__ __launch_bounds__(NTS) void k_final(long ncell, int nb, const T* __restrict__ base, Final<T> fs,
-                                               double inv_ms, T* __restrict__ mnew, double* __restrict__ parts) {
+__global__ __launch_bounds__(NTS) void k_final(long ncell, int nb, const T* base, Final<T> fs, double inv_ms,
+                                               T* mnew, double* __restrict__ parts) {
     double emax = 0.0;
     for (long ic = (long)blockIdx.x * NTS + threadIdx.x; ic < ncell * nb; ic += (long)gridDim.x * NTS) {
         const long b = ic / ncell, cell = ic - b * ncell;
