@@ -85,6 +85,26 @@ def kernel_bytes(n, tsz, p, nnz_comb=1, nnz_final=4):
     }
 
 
+def batch_step_bytes(problems, tsz, p):
+    """Algorithmic HBM bytes of one extrapolated RK4 step of a batch: per mesh
+    group the launches of the single-mesh step (one exact evaluation, Eq. (6)
+    fields, two extrapolated stages, the fused last stage) for each of its
+    samples, with the group's folded kernel read once."""
+    groups = {}
+    for q in problems:
+        groups[tuple(q["n"])] = groups.get(tuple(q["n"]), 0) + 1
+    total = 0
+    for n, nb in groups.items():
+        kb = kernel_bytes(n, tsz, p)
+        nx, ny, nz = n
+        kx = (nx + 1 if nx > 1 else 1)
+        kern = 6 * kx * ((ny + 1) if ny > 1 else 1) * ((nz + 1) if nz > 1 else 1) * tsz
+        per = kb["xfwd"] + kb["yfwd"] + kb["zmul"] + kb["yinv"] + kb["xinv"] + kb["epoly"] + 2 * kb["extrap"] \
+            + kb["final"]
+        total += nb * (per - kern) + kern
+    return total
+
+
 def source_hash():
     """Hash of every kernel source and header (a change anywhere voids the
     stored counter figures)."""
@@ -528,8 +548,10 @@ def main():
         # ---- batched sweep: 64 samples over 4 meshes, RK4 h = 50 fs, FP32 ---
         log("batch of 64 samples ...")
         samples = workloads.batch_samples(64)
-        for tag, ex in (("p4", p), ("full", None)):
+        for tag, ex, launch in (("p4", p, "persistent"), ("p4", p, "streams"), ("full", None, "persistent"),
+                                ("full", None, "streams")):
             bt = llgx.Batch([q for q, _ in samples], "f32", stream=stream)
+            bt.set_launch(launch)
             bt.precompute_demag()
             with torch.cuda.stream(stream):
                 for i, (q, seed) in enumerate(samples):
@@ -545,9 +567,16 @@ def main():
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
             inf = bt.info()
-            extras[f"batch64_{tag}_ms_per_step"] = 1e3 * wall / kb_
-            extras[f"batch64_{tag}_field_evals_per_s"] = 4 * 64 * kb_ / wall
-            extras[f"batch64_{tag}_sample_ns_per_h"] = 64 * 5e-14 * 1e9 * kb_ / wall * 3600.0
+            key = f"batch64_{tag}_{launch}"
+            extras[f"{key}_ms_per_step"] = 1e3 * wall / kb_
+            extras[f"{key}_field_evals_per_s"] = 4 * 64 * kb_ / wall
+            extras[f"{key}_sample_ns_per_h"] = 64 * 5e-14 * 1e9 * kb_ / wall * 3600.0
+            extras[f"{key}_kernels_per_step"] = inf["kernels_per_step"]
+            if ex is not None:
+                alg = batch_step_bytes([q for q, _ in samples], 4, p)
+                extras[f"{key}_alg_bytes"] = alg
+                extras[f"{key}_gbs"] = alg / (wall / kb_) / 1e9
+                extras[f"{key}_roofline_frac"] = extras[f"{key}_gbs"] / HBM_PEAK_GBS
             extras["batch64_groups"] = inf["groups"]
             extras["batch64_cells"] = inf["cells"]
             bt.close()

@@ -28,6 +28,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK, E_ARG, E_STATE, E_HIP, E_NONFINITE, E_OOM, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 F64, F32 = 0, 1
 SPEC_NATIVE, SPEC_BF16, SPEC_F16 = 0, 1, 2
+BATCH_PERSISTENT, BATCH_STREAMS = 0, 1
 METHODS = {"RK4": 0, "RKF45": 1, "RKCK45": 2, "RKDP54": 3, "HEUN": 4, "RK23": 5, "RKF56": 6, "ABM2": 7}
 EXTRAP_FULL, EXTRAP_MATCHED = -1, -2
 
@@ -91,6 +92,8 @@ _sig = {
     "llgx_tune_export": (_S, [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
     "llgx_tune_import": (_S, [ctypes.c_char_p]),
     "llgx_batch_autotune": (_S, [_H, ctypes.c_int32]),
+    "llgx_batch_set_launch": (_S, [_H, ctypes.c_int32]),
+    "llgx_batch_launch_info": (_S, [_H, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "llgx_batch_create": (_S, [ctypes.c_int32, ctypes.POINTER(Problem), ctypes.c_int32, _P, ctypes.POINTER(_H)]),
     "llgx_batch_destroy": (None, [_H]),
     "llgx_batch_last_error": (ctypes.c_char_p, [_H]),
@@ -492,4 +495,17 @@ class Batch:
     def info(self):
         ng, nc, t = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_double()
         _bcheck(_lib.llgx_batch_info(self._h, ctypes.byref(ng), ctypes.byref(nc), ctypes.byref(t)), self._h)
-        return {"groups": ng.value, "cells": nc.value, "t": t.value}
+        pe, nk = ctypes.c_int32(), ctypes.c_int32()
+        _bcheck(_lib.llgx_batch_launch_info(self._h, ctypes.byref(pe), ctypes.byref(nk)), self._h)
+        return {"groups": ng.value, "cells": nc.value, "t": t.value, "persistent": bool(pe.value),
+                "kernels_per_step": nk.value}
+
+    def last_error(self):
+        """The batch's last error or note (why a captured step is not persistent)."""
+        return _lib.llgx_batch_last_error(self._h).decode()
+
+    def set_launch(self, mode):
+        """'persistent' (one launch per pass over a job table of all mesh
+        groups) or 'streams' (each group's launches on forked streams)."""
+        m = {"persistent": BATCH_PERSISTENT, "streams": BATCH_STREAMS}[mode]
+        _bcheck(_lib.llgx_batch_set_launch(self._h, m), self._h)

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libllgx.so")
-SOURCES = ["pass_x.hip", "pass_col.hip", "pass_z.hip", "newell.hip", "llg.hip", "llgx_api.hip"]
+SOURCES = ["pass_x.hip", "pass_col.hip", "pass_z.hip", "newell.hip", "llg.hip", "batch.hip", "llgx_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -65,10 +65,21 @@ constexpr int xinv_rows(int LX, int v) {
 
 #define LLGX_POW2_CASES(M) M(2) M(4) M(8) M(16) M(32) M(64) M(128) M(256) M(512) M(1024) M(2048)
 
-template <typename T>
+// Eq. (4) terms: a loop over c.nf (kernel arguments, indexed in place), or
+// with STATIC_NF unrolled to MAX_F with static indices (arguments held in
+// registers); the same terms in the same order either way
+template <typename T, bool STATIC_NF = false>
 __device__ __forceinline__ T combo_at(const Combo<T>& c, long i) {
     T v = c.base[i];
-    for (int l = 0; l < c.nf; ++l) v += c.coef[l] * c.f[l][i];
+    if constexpr (STATIC_NF) {
+#pragma unroll
+        for (int l = 0; l < MAX_F; ++l) {
+            if (l >= c.nf) break;
+            v += c.coef[l] * c.f[l][i];
+        }
+    } else {
+        for (int l = 0; l < c.nf; ++l) v += c.coef[l] * c.f[l][i];
+    }
     return v;
 }
 
@@ -77,18 +88,31 @@ __device__ __forceinline__ T combo_at(const Combo<T>& c, long i) {
 // A real sequence of length P = 2 LX is packed as z[j] = x[2j] + i x[2j+1],
 // transformed with a length-LX complex FFT and split with
 //   X[k] = (Z[k] + Z*[LX-k])/2 - i e^{-2 pi i k/P} (Z[k] - Z*[LX-k])/2.
-template <typename T, typename S, int LX, int ROWS, bool HALF>
-__global__ __launch_bounds__(NT) void k_xfwd(Combo<T> in, T* __restrict__ mk_out, int nin, long nrows,
-                                             typename Spec<T, S>::elem* __restrict__ spec, int SX,
-                                             const cx<T>* __restrict__ twL, const cx<T>* __restrict__ twP,
-                                             T fscale) {
+// LDS of one x forward tile
+template <typename T, int LX, int ROWS>
+struct XfwdShared {  // every array 16-byte aligned: 128-bit LDS accesses stay single instructions
+    using F = RowFFT<T, LX, false, ROWS, NT>;
+    alignas(16) cx<T> buf[F::LDS_ELEMS];
+    alignas(16) cx<T> twl[LX];
+    alignas(16) cx<T> twp[LX + 1];
+};
+template <typename T, int ROWS>
+struct XfwdShared<T, 0, ROWS> {
+    int unused;
+};
+
+// rows row0 .. row0 + ROWS - 1 (one workgroup)
+template <typename T, typename S, int LX, int ROWS, bool HALF, bool STATIC_NF = false>
+__device__ __forceinline__ void xfwd_tile(const Combo<T>& in, T* __restrict__ mk_out, int nin, long nrows,
+                                          typename Spec<T, S>::elem* __restrict__ spec, int SX,
+                                          const cx<T>* __restrict__ twL, const cx<T>* __restrict__ twP, T fscale,
+                                          long row0, XfwdShared<T, LX, ROWS>& sh) {
     using C = cx<T>;
-    const long row0 = (long)blockIdx.x * ROWS;
     if constexpr (LX == 0) {
         for (int r = threadIdx.x; r < ROWS; r += NT) {
             const long g = row0 + r;
             if (g < nrows) {
-                const T v = combo_at(in, g);
+                const T v = combo_at<T, STATIC_NF>(in, g);
                 if (mk_out) mk_out[g] = v;
                 spec[g * SX] = Spec<T, S>::put(C{v * fscale, T(0)});
             }
@@ -98,9 +122,9 @@ __global__ __launch_bounds__(NT) void k_xfwd(Combo<T> in, T* __restrict__ mk_out
         // HALF (nin <= LX, a mesh row): packed inputs z[i] = x[2i] + i x[2i+1]
         // with i >= LX/2 lie in the zero padding
         using F = RowFFT<T, LX, false, ROWS, NT, HALF, false>;
-        __shared__ C buf[F::LDS_ELEMS];
-        __shared__ C twl[LX];
-        __shared__ C twp[LX + 1];
+        C* buf = sh.buf;
+        C* twl = sh.twl;
+        C* twp = sh.twp;
         TwStage<T, LX, NT> tw1;
         TwStage<T, LX + 1, NT> tw2;
         tw1.fetch(twL);
@@ -146,7 +170,7 @@ __global__ __launch_bounds__(NT) void k_xfwd(Combo<T> in, T* __restrict__ mk_out
         for (int m = 0; m < F::U0; ++m)
 #pragma unroll
             for (int q = 0; q < F::R0; ++q) v[m][q] = q < QN ? load2(in.base, m, q) : C{T(0), T(0)};
-        for (int l = 0; l < in.nf; ++l) {
+        auto add_term = [&](int l) {
             C w[F::U0][F::R0];
 #pragma unroll
             for (int m = 0; m < F::U0; ++m)
@@ -160,6 +184,15 @@ __global__ __launch_bounds__(NT) void k_xfwd(Combo<T> in, T* __restrict__ mk_out
                     v[m][q].x += cf * w[m][q].x;
                     v[m][q].y += cf * w[m][q].y;
                 }
+        };
+        if constexpr (STATIC_NF) {
+#pragma unroll
+            for (int l = 0; l < MAX_F; ++l) {
+                if (l >= in.nf) break;
+                add_term(l);
+            }
+        } else {
+            for (int l = 0; l < in.nf; ++l) add_term(l);
         }
 #pragma unroll
         for (int m = 0; m < F::U0; ++m)
@@ -202,36 +235,54 @@ __global__ __launch_bounds__(NT) void k_xfwd(Combo<T> in, T* __restrict__ mk_out
     }
 }
 
+template <typename T, typename S, int LX, int ROWS, bool HALF>
+__global__ __launch_bounds__(NT) void k_xfwd(Combo<T> in, T* __restrict__ mk_out, int nin, long nrows,
+                                             typename Spec<T, S>::elem* __restrict__ spec, int SX,
+                                             const cx<T>* __restrict__ twL, const cx<T>* __restrict__ twP,
+                                             T fscale) {
+    __shared__ XfwdShared<T, LX, ROWS> sh;
+    xfwd_tile<T, S, LX, ROWS, HALF>(in, mk_out, nin, nrows, spec, SX, twL, twP, fscale, (long)blockIdx.x * ROWS, sh);
+}
+
 // ------------------------------------------------------------------------
 // inverse x pass: LX+1 complex -> real, keep x < nx; then per cell
 //   Z[k] = (X[k] + X*[LX-k]) + i e^{+2 pi i k/P} (X[k] - X*[LX-k]),
 //   z = IDFT_LX(Z), x[2j] = Re z[j], x[2j+1] = Im z[j].
+// LDS of one x inverse tile
+template <typename T, int LX, int ROWS>
+struct XinvShared {
+    static constexpr int LXE = LX > 0 ? LX : 2;
+    static constexpr int RS = LX > 0 ? RowFFT<T, LXE, true, 3 * ROWS, NT>::RS : 1;
+    alignas(16) cx<T> buf[3 * ROWS * RS];
+    alignas(16) cx<T> twl[LXE];
+};
+
+// row block bx of gx (the row blocks of one sample) of sample b
 template <typename T, typename S, int LX, int ROWS, int MODE>
-__global__ __launch_bounds__(NT) void k_xinv(const typename Spec<T, S>::elem* __restrict__ spec, int SX,
-                                             const T* __restrict__ M, Phys<T> ph, XinvOut out,
-                                             const cx<T>* __restrict__ twL, const cx<T>* __restrict__ twP,
-                                             T hscale) {
+__device__ __forceinline__ void xinv_tile(const typename Spec<T, S>::elem* __restrict__ spec, int SX,
+                                          const T* __restrict__ M, const Phys<T>& ph, const XinvOut& out,
+                                          const cx<T>* __restrict__ twL, const cx<T>* __restrict__ twP, T hscale,
+                                          int bx, int gx, int b, XinvShared<T, LX, ROWS>& sh) {
     using C = cx<T>;
     constexpr int LXE = LX > 0 ? LX : 2;
     // only x < nx <= LX is kept: packed outputs z[j] with j < LX/2
     using F = RowFFT<T, LXE, true, 3 * ROWS, NT, false, true>;
-    constexpr int RS = LX > 0 ? F::RS : 1;
-    __shared__ C buf[3 * ROWS * RS];
-    __shared__ C twl[LXE];
+    constexpr int RS = XinvShared<T, LX, ROWS>::RS;
+    C* buf = sh.buf;
+    C* twl = sh.twl;
     const long nrow = (long)ph.ny * ph.nz;
     const long N = nrow * ph.nx;
     // the exchange stencil of the fused H_eff reads neighbour rows: y-slab
     // block order (xcd_run, yslab) when the row blocks tile each plane
-    long row0 = (long)blockIdx.x * ROWS;
+    long row0 = (long)bx * ROWS;
     const bool tiled = ph.ny % ROWS == 0;
     int plane = 0, y0 = 0;  // z and first y of the block's rows when tiled
     if (tiled) {
         int yg;
-        yslab(xcd_run(blockIdx.x, gridDim.x), ph.ny / ROWS, ph.nz, plane, yg);
+        yslab(xcd_run(bx, gx), ph.ny / ROWS, ph.nz, plane, yg);
         y0 = yg * ROWS;
         row0 = (long)plane * ph.ny + y0;
     }
-    const int b = blockIdx.y;  // sample
     spec += (long)b * 3 * nrow * SX;
     if (M) M += (long)b * 3 * N;
     const long vo = (long)b * 3 * N;
@@ -341,24 +392,41 @@ __global__ __launch_bounds__(NT) void k_xinv(const typename Spec<T, S>::elem* __
     }
 }
 
+template <typename T, typename S, int LX, int ROWS, int MODE>
+__global__ __launch_bounds__(NT) void k_xinv(const typename Spec<T, S>::elem* __restrict__ spec, int SX,
+                                             const T* __restrict__ M, Phys<T> ph, XinvOut out,
+                                             const cx<T>* __restrict__ twL, const cx<T>* __restrict__ twP,
+                                             T hscale) {
+    __shared__ XinvShared<T, LX, ROWS> sh;
+    xinv_tile<T, S, LX, ROWS, MODE>(spec, SX, M, ph, out, twL, twP, hscale, blockIdx.x, gridDim.x, blockIdx.y, sh);
+}
+
 // ------------------------------------------------------------------------
 // strided column FFT: element (comp, outer, i, kx) at comp*cs + outer*os + i*is + kx
 // HALF: the forward transform's input rows >= L/2 are zero (n_in <= L/2) or
 // the inverse transform keeps only rows < L/2 (n_out <= L/2)
+// LDS of one column-pass tile
+template <typename T, typename S, int L, int TK>
+struct ColShared {
+    using F = ColFFT<T, S, L, false, TK, 1, NT>;
+    alignas(16) cx<T> buf[F::NSTAGE > 1 ? F::LDS_ELEMS : 1];
+    alignas(16) cx<T> twl[L];
+};
+
+// tile lin of ntx x nby x nbz tiles (kx tiles, outer index, component)
 template <typename T, typename S, int L, bool INV, int TK, bool HALF>
-__global__ __launch_bounds__(NT) void k_colfft(const typename Spec<T, S>::elem* __restrict__ src, long s_cs,
-                                               long s_os, long s_is, int n_in,
-                                               typename Spec<T, S>::elem* __restrict__ dst, long d_cs, long d_os,
-                                               long d_is, int n_out, int Kx, const cx<T>* __restrict__ tw,
-                                               T scale) {
+__device__ __forceinline__ void colfft_tile(const typename Spec<T, S>::elem* __restrict__ src, long s_cs, long s_os,
+                                            long s_is, int n_in, typename Spec<T, S>::elem* __restrict__ dst,
+                                            long d_cs, long d_os, long d_is, int n_out, int Kx,
+                                            const cx<T>* __restrict__ tw, T scale, int lin, int ntx, int nby, int nbz,
+                                            ColShared<T, S, L, TK>& sh) {
     using C = cx<T>;
     using F = ColFFT<T, S, L, INV, TK, 1, NT, !INV && HALF, INV && HALF>;
     using E = typename Spec<T, S>::elem;
     // each XCD takes a contiguous run of tiles (xcd_run): when a tile row is
     // shorter than a 128-byte line, the neighbouring tiles that share its
     // lines are mostly fetched into the same L2
-    const int ntx = gridDim.x, nby = gridDim.y;
-    const int pos = xcd_run(blockIdx.x + ntx * (blockIdx.y + nby * blockIdx.z), ntx * nby * gridDim.z);
+    const int pos = xcd_run(lin, ntx * nby * nbz);
     const int bx = pos % ntx, by = (pos / ntx) % nby, bz = pos / (ntx * nby);
     const int kx0 = bx * TK;
     const Base1<const E> sp{src + bz * s_cs + by * s_os + kx0};
@@ -368,8 +436,8 @@ __global__ __launch_bounds__(NT) void k_colfft(const typename Spec<T, S>::elem* 
         F::load_first(rg, sp, s_is, n_in, Kx - kx0, 1);
         F::single(rg, dp, d_is, n_out, Kx - kx0, 1, scale);
     } else {
-        __shared__ C buf[F::LDS_ELEMS];
-        __shared__ C twl[L];
+        C* buf = sh.buf;
+        C* twl = sh.twl;
         TwStage<T, L, NT> tws;
         tws.fetch(tw);
         F::load_first(rg, sp, s_is, n_in, Kx - kx0, 1);
@@ -379,6 +447,18 @@ __global__ __launch_bounds__(NT) void k_colfft(const typename Spec<T, S>::elem* 
         F::middle(buf, twl);
         F::last_to_global(buf, twl, dp, d_is, n_out, Kx - kx0, 1, scale);
     }
+}
+
+template <typename T, typename S, int L, bool INV, int TK, bool HALF>
+__global__ __launch_bounds__(NT) void k_colfft(const typename Spec<T, S>::elem* __restrict__ src, long s_cs,
+                                               long s_os, long s_is, int n_in,
+                                               typename Spec<T, S>::elem* __restrict__ dst, long d_cs, long d_os,
+                                               long d_is, int n_out, int Kx, const cx<T>* __restrict__ tw,
+                                               T scale) {
+    __shared__ ColShared<T, S, L, TK> sh;
+    colfft_tile<T, S, L, INV, TK, HALF>(src, s_cs, s_os, s_is, n_in, dst, d_cs, d_os, d_is, n_out, Kx, tw, scale,
+                                        blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), gridDim.x,
+                                        gridDim.y, gridDim.z, sh);
 }
 
 // ------------------------------------------------------------------------
@@ -536,10 +616,22 @@ struct KernelRegs {
     }
 };
 
+// LDS of one z-pass tile
+template <typename T, int LZ, int TK>
+struct ZmulShared {
+    static constexpr int L = LZ > 1 ? LZ : 2;
+    static constexpr int KZF = LZ / 2 + 1;
+    alignas(16) cx<T> lb[LZ * 6 * TK];
+    alignas(16) T kl[LZ == 1 ? KZF * 6 * TK : 1];
+    alignas(16) cx<T> twl[L];
+};
+
+// kx tile `tile`, folded row pair q, sample `sample`
 template <typename T, typename S, int LZ, int TK>
-__global__ __launch_bounds__(NT) void k_zmul(typename Spec<T, S>::elem* __restrict__ buf, int SX, int Kx, int nz,
-                                             int nyrows, int Py, const T* __restrict__ kfold,
-                                             const cx<T>* __restrict__ tw) {
+__device__ __forceinline__ void zmul_tile(typename Spec<T, S>::elem* __restrict__ buf, int SX, int Kx, int nz,
+                                          int nyrows, int Py, const T* __restrict__ kfold,
+                                          const cx<T>* __restrict__ tw, int tile, int q, int sample,
+                                          ZmulShared<T, LZ, TK>& sh) {
     using C = cx<T>;
     using E = typename Spec<T, S>::elem;
     constexpr int L = LZ > 1 ? LZ : 2;  // LZ = 1 uses no transform
@@ -548,15 +640,14 @@ __global__ __launch_bounds__(NT) void k_zmul(typename Spec<T, S>::elem* __restri
     // z < nz of the inverse output are kept; nz <= Pz/2 always
     using Ff = ColFFT<T, S, L, false, TK, 6, NT, true, false>;
     using Fi = ColFFT<T, S, L, true, TK, 6, NT, false, true>;
-    __shared__ C lb[LZ * 6 * TK];
-    __shared__ T kl[LZ == 1 ? KZF * 6 * TK : 1];
-    __shared__ C twl[L];
-    const int kx0 = blockIdx.x * TK;
-    const int q = blockIdx.y;  // 0 <= q <= Py/2
-    const int ng = (2 * q == Py || q == 0) ? 3 : 6;
+    C* lb = sh.lb;
+    T* kl = sh.kl;
+    C* twl = sh.twl;
+    const int kx0 = tile * TK;
+    const int ng = (2 * q == Py || q == 0) ? 3 : 6;  // 0 <= q <= Py/2
     const int ncol = Kx - kx0;
     const long cs = (long)nz * nyrows * SX, zs = (long)nyrows * SX;
-    E* sb = buf + (long)blockIdx.z * 3 * cs;  // sample
+    E* sb = buf + (long)sample * 3 * cs;
     const ZBases<E> bases{sb + (long)q * SX + kx0, sb + (long)(Py - q) * SX + kx0, (unsigned)cs};
     if constexpr (LZ == 1) {
         // no z transform: load the 6 x TK values, multiply, store
@@ -622,6 +713,14 @@ __global__ __launch_bounds__(NT) void k_zmul(typename Spec<T, S>::elem* __restri
             }
         }
     }
+}
+
+template <typename T, typename S, int LZ, int TK>
+__global__ __launch_bounds__(NT) void k_zmul(typename Spec<T, S>::elem* __restrict__ buf, int SX, int Kx, int nz,
+                                             int nyrows, int Py, const T* __restrict__ kfold,
+                                             const cx<T>* __restrict__ tw) {
+    __shared__ ZmulShared<T, LZ, TK> sh;
+    zmul_tile<T, S, LZ, TK>(buf, SX, Kx, nz, nyrows, Py, kfold, tw, blockIdx.x, blockIdx.y, blockIdx.z, sh);
 }
 
 }  // namespace llgx

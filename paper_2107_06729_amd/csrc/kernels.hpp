@@ -95,11 +95,10 @@ struct Phys {
     T exx, exy, exz;   // 2A/(mu0 Ms^2) / d^2 per axis
     T ani;             // 2K/(mu0 Ms^2)
     T u[3];            // anisotropy axis
-    T ha[3];           // applied field
     T gp;              // gamma / (1 + alpha^2)
     T gpa;             // gamma alpha / ((1 + alpha^2) Ms)
     T n00[3];          // self term of Eq. (6)
-    const T* hab;      // per-sample applied field [nb][3] (device), or null: ha for all
+    const T* hab;      // applied field of each sample [nb][3] (device)
     const int* empty;  // device flag: nonzero when some cell has M = 0 (no material)
     int nx, ny, nz;
     int nb;            // samples of this mesh processed by one launch

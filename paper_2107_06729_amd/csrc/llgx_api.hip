@@ -15,6 +15,7 @@
 #include <string>
 #include <vector>
 
+#include "batch.hpp"
 #include "kernels.hpp"
 #include "llgx.h"
 #include "tableaux.hpp"
@@ -70,7 +71,7 @@ struct Ctx {
     long ncell = 1;             // cells per sample
     int nb = 1;                 // samples sharing this mesh (batched launches)
     int var[5] = {0, 0, 0, 0, 0};  // launch variant per FFT pass (LLGX_K_XFWD .. LLGX_K_XINV)
-    void* hab = nullptr;        // per-sample applied fields [nb][3] (device, working precision)
+    void* hab = nullptr;        // applied field of each sample [nb][3] (device, working precision)
     int Px = 1, Py = 1, Pz = 1, LX = 0, Kx = 1, SX = 16, Kyf = 1, Kzf = 1;
 
     // device workspace
@@ -123,6 +124,17 @@ struct Ctx {
     long long n_exact = 0, n_extrap = 0, n_acc = 0, n_rej = 0, n_forced = 0;
 
     std::map<GraphKey, hipGraphExec_t> graphs;
+
+    // When set, the launches of one step attempt are recorded here (kind of
+    // the persistent batched kernel, its template count, its arguments)
+    // instead of made; rec_unsupported is set by a launch that has no
+    // persistent form (16-bit spectra, error-norm reduction, ...).
+    struct Rec {
+        int kind, nf;
+        std::vector<unsigned char> arg;
+    };
+    std::vector<Rec>* rec = nullptr;
+    bool rec_unsupported = false;
 
     // per-kernel event timing (eager launches only)
     bool prof = false;
@@ -238,7 +250,6 @@ static Phys<T> phys(const Ctx* c) {
     double un = std::sqrt(p.easy[0] * p.easy[0] + p.easy[1] * p.easy[1] + p.easy[2] * p.easy[2]);
     for (int i = 0; i < 3; ++i) {
         ph.u[i] = (T)(un > 0 ? p.easy[i] / un : 0.0);
-        ph.ha[i] = (T)p.Ha[i];
         ph.n00[i] = (T)c->n00[i];
     }
     const double gp = p.gamma / (1.0 + p.alpha * p.alpha);
@@ -290,6 +301,50 @@ struct EvalArgs {
     XinvOut out;
 };
 
+template <typename A>
+static void record(Ctx* c, int kind, int nf, const A& a) {
+    Ctx::Rec r{kind, nf, std::vector<unsigned char>(sizeof(A))};
+    std::memcpy(r.arg.data(), &a, sizeof(A));
+    c->rec->push_back(std::move(r));
+}
+
+// the arguments of pass `kind` for the persistent batched kernels
+template <typename T>
+static void record_pass(Ctx* c, int kind, const EvalArgs<T>& a, void* A, void* B) {
+    using C = cx<T>;
+    const C* twL = table<T>(c, c->LX, false);
+    const C* twP = table<T>(c, c->Px, false);
+    const long sa = (long)c->nz * c->ny * c->SX, sb = (long)c->nz * c->Py * c->SX;
+    switch (kind) {
+        case LLGX_K_XFWD:
+            record(c, BK_XFWD, 0,
+                   BXfwd<T>{a.in, a.mk_out, c->nx, 3L * c->ny * c->nz * c->nb, (C*)A, c->SX, twL, twP, c->LX, 0});
+            break;
+        case LLGX_K_YFWD:
+            record(c, BK_COL, 0,
+                   BCol<T>{(const C*)A, sa, (long)c->ny * c->SX, c->SX, c->ny, (C*)B, sb, (long)c->Py * c->SX, c->SX,
+                           c->Py, c->Kx, table<T>(c, c->Py, false), c->Py, c->nz, 3 * c->nb, 0, 0});
+            break;
+        case LLGX_K_ZMUL:
+            record(c, BK_ZMUL, 0,
+                   BZmul<T>{(C*)(c->Py > 1 ? B : A), c->SX, c->Kx, c->nz, c->Py > 1 ? c->Py : c->ny, c->Py, c->nb,
+                            (const T*)c->kfold, table<T>(c, c->Pz, false), c->Pz, 0, 0, 0});
+            break;
+        case LLGX_K_YINV:
+            record(c, BK_COL, 1,
+                   BCol<T>{(const C*)B, sb, (long)c->Py * c->SX, c->SX, c->Py, (C*)A, sa, (long)c->ny * c->SX, c->SX,
+                           c->ny, c->Kx, table<T>(c, c->Py, false), c->Py, c->nz, 3 * c->nb, 0, 0});
+            break;
+        case LLGX_K_XINV:
+            if (a.mode != XINV_RHS) {
+                c->rec_unsupported = true;
+                break;
+            }
+            record(c, BK_XINV, 0, BXinv<T>{(const C*)A, c->SX, a.Mrhs, phys<T>(c), a.out, twL, twP, c->LX, 0, 0});
+            break;
+    }
+}
+
 static bool pass_exists(const Ctx* c, int kind) {
     return !((kind == LLGX_K_YFWD || kind == LLGX_K_YINV) && c->Py == 1);
 }
@@ -304,6 +359,13 @@ static llgx_status run_pass(Ctx* c, int kind, const EvalArgs<T>& a) {
     const cx<T>* twP = table<T>(c, c->Px, false);
     const bool native = std::is_same<T, S>::value;
     const long sa = (long)c->nz * c->ny * c->SX, sb = (long)c->nz * c->Py * c->SX;
+    if (c->rec) {
+        if constexpr (std::is_same<T, S>::value)
+            record_pass<T>(c, kind, a, A, B);
+        else
+            c->rec_unsupported = true;
+        return LLGX_OK;
+    }
     switch (kind) {
         case LLGX_K_XFWD: {
             const T fscale = native ? T(1) : (T)(1.0 / (c->p.Ms * c->Px));
@@ -347,7 +409,11 @@ template <typename T, typename S>
 static llgx_status eval_exact_s(Ctx* c, const Combo<T>& in, T* mk_out, int mode, const T* Mrhs, const XinvOut& out) {
     const EvalArgs<T> a{in, mk_out, mode, Mrhs, out};
     for (int kind = LLGX_K_XFWD; kind <= LLGX_K_XINV; ++kind) {
-        if (!pass_exists(c, kind)) continue;
+        if (!pass_exists(c, kind)) {
+            // a group without y passes takes no jobs of the batch's y launches
+            if (c->rec) record(c, BK_COL, kind == LLGX_K_YINV ? 1 : 0, BCol<T>{});
+            continue;
+        }
         PROF(kind);
         llgx_status st = run_pass<T, S>(c, kind, a);
         if (st) return st;
@@ -577,7 +643,10 @@ static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
                 ep.out[j] = (T*)c->E[j];
             }
             PROF(LLGX_K_EPOLY);
-            HIPCHK(c, launch_epoly<T>(c->stream, 3 * c->ncell * c->nb, ep));
+            if (c->rec)
+                record(c, BK_EPOLY, ep.ng, BEpoly<T>{ep, 3 * c->ncell * c->nb});
+            else
+                HIPCHK(c, launch_epoly<T>(c->stream, 3 * c->ncell * c->nb, ep));
         }
     }
     // Eq. (3) operands: stage derivatives used by the update or by the estimate
@@ -614,7 +683,10 @@ static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
             } else if (cb.nf > 0) {
                 // form M_k once instead of at every stencil read
                 PROF(LLGX_K_COMBINE);
-                HIPCHK(c, launch_combine<T>(c->stream, 3 * c->ncell * c->nb, cb, (T*)mkbuf(k)));
+                if (c->rec)
+                    record(c, BK_COMBINE, cb.nf, BCombine<T>{cb, (T*)mkbuf(k), 3 * c->ncell * c->nb});
+                else
+                    HIPCHK(c, launch_combine<T>(c->stream, 3 * c->ncell * c->nb, cb, (T*)mkbuf(k)));
                 cb = plain<T>(mkbuf(k));
             }
             Extrap<T> ex{};
@@ -624,8 +696,13 @@ static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
             ProfScope ps(c, k == tab->S - 1 ? LLGX_K_FINAL : LLGX_K_EXTRAP);
             if (k == tab->S - 1) {
                 add_final(k);  // own derivative, last entry
-                HIPCHK(c, launch_stage_final<T>(c->stream, cb, ex, phys<T>(c), (const T*)c->M, fs,
-                                                1.0 / c->p.Ms, (T*)(pl.in_place ? c->M : c->Mnew), c->parts));
+                T* mnew = (T*)(pl.in_place ? c->M : c->Mnew);
+                if (c->rec)
+                    record(c, BK_STAGE_FINAL, fs.n,
+                           BStageFinal<T>{cb, ex, phys<T>(c), (const T*)c->M, fs, 1.0 / c->p.Ms, mnew, c->parts});
+                else
+                    HIPCHK(c, launch_stage_final<T>(c->stream, cb, ex, phys<T>(c), (const T*)c->M, fs,
+                                                    1.0 / c->p.Ms, mnew, c->parts));
                 fused_final = true;
             } else {
                 NextStage<T> nx{nullptr, nullptr, T(0)};
@@ -633,7 +710,10 @@ static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
                     nx = NextStage<T>{(const T*)c->M, (T*)mkbuf(k + 1), (T)(h * tab->a[k + 1][k])};
                     formed[k + 1] = true;
                 }
-                HIPCHK(c, launch_extrap_rhs<T>(c->stream, cb, ex, phys<T>(c), (T*)c->F[k], nx));
+                if (c->rec)
+                    record(c, BK_STAGE, 0, BStage<T>{cb, ex, phys<T>(c), (T*)c->F[k], nx});
+                else
+                    HIPCHK(c, launch_extrap_rhs<T>(c->stream, cb, ex, phys<T>(c), (T*)c->F[k], nx));
             }
         } else {
             XinvOut out{nullptr, c->F[k], nullptr};
@@ -646,12 +726,20 @@ static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
         nred = (int)cell_grid(c->nx, c->ny, c->nz, c->nb).nblocks;
     } else {
         PROF(LLGX_K_FINAL);
-        HIPCHK(c, launch_final<T>(c->stream, c->ncell, c->nb, (const T*)c->M, fs, 1.0 / c->p.Ms,
-                                  (T*)(pl.in_place ? c->M : c->Mnew), c->parts, c->nparts));
+        T* mnew = (T*)(pl.in_place ? c->M : c->Mnew);
+        if (c->rec)
+            record(c, BK_FINAL, fs.n,
+                   BFinal<T>{c->ncell, c->nb, (const T*)c->M, fs, 1.0 / c->p.Ms, mnew, c->parts, c->nparts});
+        else
+            HIPCHK(c, launch_final<T>(c->stream, c->ncell, c->nb, (const T*)c->M, fs, 1.0 / c->p.Ms, mnew, c->parts,
+                                      c->nparts));
     }
     if (pl.want_err) {
         PROF(LLGX_K_OTHER);
-        HIPCHK(c, launch_reduce_max(c->stream, c->parts, nred, c->scal));
+        if (c->rec)
+            c->rec_unsupported = true;
+        else
+            HIPCHK(c, launch_reduce_max(c->stream, c->parts, nred, c->scal));
     }
     return LLGX_OK;
 }
@@ -1364,7 +1452,7 @@ static llgx_status create_ctx(const llgx_problem* p, int nb, const double* ha_li
     A((void**)&c->parts, 3 * (size_t)c->nparts_alloc * sizeof(double));
     A((void**)&c->scal, 8 * sizeof(double));
     A((void**)&c->empty_flag, 16);
-    if (ha_list) A(&c->hab, 3 * (size_t)nb * c->tsz);
+    A(&c->hab, 3 * (size_t)nb * c->tsz);
     if (st == LLGX_OK) {
         // padding columns of the spectra are read (never used) by 16-byte packs: keep them zero
         if (hipMemset(c->specA, 0, bytesA) != hipSuccess) st = c->fail(LLGX_E_HIP, "hipMemset failed");
@@ -1372,13 +1460,15 @@ static llgx_status create_ctx(const llgx_problem* p, int nb, const double* ha_li
             st = c->fail(LLGX_E_HIP, "hipMemset failed");
         if (st == LLGX_OK && hipMemset(c->empty_flag, 0, 16) != hipSuccess) st = c->fail(LLGX_E_HIP, "hipMemset failed");
     }
-    if (st == LLGX_OK && ha_list) {
+    if (st == LLGX_OK) {
+        // each sample's applied field (the problem's own when no list is given)
         std::vector<char> hb(3 * (size_t)nb * c->tsz);
         for (int i = 0; i < 3 * nb; ++i) {
+            const double v = ha_list ? ha_list[i] : c->p.Ha[i % 3];
             if (c->tsz == 4)
-                ((float*)hb.data())[i] = (float)ha_list[i];
+                ((float*)hb.data())[i] = (float)v;
             else
-                ((double*)hb.data())[i] = ha_list[i];
+                ((double*)hb.data())[i] = v;
         }
         if (hipMemcpy(c->hab, hb.data(), hb.size(), hipMemcpyHostToDevice) != hipSuccess)
             st = c->fail(LLGX_E_HIP, "hipMemcpy of applied fields failed");
@@ -1421,12 +1511,116 @@ struct Batch {
     std::vector<hipStream_t> gstreams;
     std::vector<hipEvent_t> joins;
     hipEvent_t fork = nullptr;
+    // LLGX_BATCH_STREAMS (default): the groups' own launches on forked
+    // streams; LLGX_BATCH_PERSISTENT: each pass of a captured step is one
+    // persistent launch over a job table of the mesh groups (per FFT length
+    // for the FFT passes; up to BMAX groups a launch), where every launch of
+    // the step has that form (else the forked-stream capture)
+    int mode = LLGX_BATCH_STREAMS;
+    std::vector<void*> tables;  // device job tables of the captured persistent steps
+    int last_persistent = 0, last_kernels = 0;
 };
 
 static bool same_material(const llgx_problem& a, const llgx_problem& b) {
     return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.dx == b.dx && a.dy == b.dy && a.dz == b.dz &&
            a.Ms == b.Ms && a.A == b.A && a.K == b.K && a.easy[0] == b.easy[0] && a.easy[1] == b.easy[1] &&
            a.easy[2] == b.easy[2] && a.alpha == b.alpha && a.gamma == b.gamma;
+}
+
+// Capture one step of every group as persistent launches: each group's
+// launches are recorded (enqueue_attempt with Ctx::rec), the i-th launches
+// of all groups are joined into one job table per FFT length and BMAX
+// groups (a group without the pass, a one-row mesh's y passes, takes no
+// part), the tables
+// are copied to device memory (kept for the graph's lifetime), and the
+// launches are captured on the batch stream.  LLGX_E_UNSUPPORTED (nothing
+// captured) when some launch has no persistent form or the groups' launch
+// sequences differ (then the forked-stream capture is used).
+template <typename T>
+static llgx_status capture_persistent(Batch* bt, const std::vector<Plan>& plans, hipGraphExec_t* out, int* nkern) {
+    const size_t ng = bt->groups.size();
+    std::vector<std::vector<Ctx::Rec>> recs(ng);
+    bool ok = true;
+    for (size_t g = 0; g < ng; ++g) {
+        Ctx* c = bt->groups[g];
+        c->rec = &recs[g];
+        c->rec_unsupported = false;
+        llgx_status st = enqueue_attempt<T>(c, plans[g]);
+        c->rec = nullptr;
+        if (st) {
+            bt->err = c->err;
+            return st;
+        }
+        ok = ok && !c->rec_unsupported && recs[g].size() == recs[0].size();
+        for (size_t i = 0; ok && i < recs[g].size(); ++i)
+            ok = recs[g][i].kind == recs[0][i].kind && recs[g][i].nf == recs[0][i].nf;
+    }
+    if (!ok) {
+        bt->err = "persistent launch not used: a launch without persistent form, or groups with different launches";
+        return LLGX_E_UNSUPPORTED;
+    }
+    std::vector<unsigned char> blob;
+    std::vector<BatchLaunch> launches;
+    for (size_t i = 0; i < recs[0].size(); ++i) {
+        // the groups of each FFT length (one key for the per-cell kinds)
+        std::map<int, std::vector<const void*>> by_len;
+        for (size_t g = 0; g < ng; ++g) {
+            const int key = batch_instance<T>(recs[0][i].kind, recs[g][i].arg.data());
+            if (key >= 0) by_len[key].push_back(recs[g][i].arg.data());
+        }
+        for (auto& kv : by_len) {
+            for (size_t g0 = 0; g0 < kv.second.size(); g0 += BMAX) {
+                std::vector<const void*> args(kv.second.begin() + g0,
+                                              kv.second.begin() + std::min(kv.second.size(), g0 + BMAX));
+                BatchLaunch bl{};
+                hipError_t e = prepare_batch<T>(recs[0][i].kind, recs[0][i].nf, args, blob, bl);
+                if (e == hipErrorInvalidValue) {
+                    bt->err = "persistent launch not used: launch " + std::to_string(i) + " (kind " +
+                              std::to_string(recs[0][i].kind) + ") outside the persistent kernels' lengths";
+                    return LLGX_E_UNSUPPORTED;
+                }
+                if (e != hipSuccess) {
+                    bt->err = std::string("persistent launch setup failed: ") + hipGetErrorString(e);
+                    return LLGX_E_HIP;
+                }
+                launches.push_back(bl);
+            }
+        }
+    }
+    void* dev = nullptr;
+    if (hipMalloc(&dev, std::max<size_t>(blob.size(), 256)) != hipSuccess) {
+        bt->err = "job table allocation failed";
+        return LLGX_E_OOM;
+    }
+    bt->tables.push_back(dev);
+    if (hipMemcpy(dev, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        bt->err = "job table copy failed";
+        return LLGX_E_HIP;
+    }
+    hipGraph_t gr;
+    if (hipStreamBeginCapture(bt->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        bt->err = "graph capture could not start";
+        return LLGX_E_HIP;
+    }
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < launches.size() && e == hipSuccess; ++i)
+        e = enqueue_batch(launches[i], (const char*)dev + launches[i].offset, bt->stream);
+    hipError_t e2 = hipStreamEndCapture(bt->stream, &gr);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (e2 == hipSuccess) (void)hipGraphDestroy(gr);
+        bt->err = std::string("persistent capture failed: ") + hipGetErrorString(e != hipSuccess ? e : e2);
+        return LLGX_E_HIP;
+    }
+    hipGraphExec_t ge;
+    e = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e != hipSuccess) {
+        bt->err = "graph instantiation failed";
+        return LLGX_E_HIP;
+    }
+    *out = ge;
+    *nkern = (int)launches.size();
+    return LLGX_OK;
 }
 
 template <typename T>
@@ -1483,6 +1677,18 @@ static llgx_status batch_run_fixed(Batch* bt, const llgx_stepper* s, int64_t nst
             continue;
         }
         auto it = bt->graphs.find(keys);
+        if (it == bt->graphs.end() && bt->mode == LLGX_BATCH_PERSISTENT) {
+            hipGraphExec_t ge;
+            int nk = 0;
+            llgx_status st = capture_persistent<T>(bt, plans, &ge, &nk);
+            if (st == LLGX_OK) {
+                it = bt->graphs.emplace(keys, ge).first;
+                bt->last_persistent = 1;
+                bt->last_kernels = nk;
+            } else if (st != LLGX_E_UNSUPPORTED) {
+                return st;
+            }
+        }
         if (it == bt->graphs.end()) {
             hipGraph_t gr;
             if (hipStreamBeginCapture(bt->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
@@ -1540,6 +1746,8 @@ static llgx_status batch_run_fixed(Batch* bt, const llgx_stepper* s, int64_t nst
             }
             (void)hipGraphDestroy(gr);
             it = bt->graphs.emplace(keys, ge).first;
+            bt->last_persistent = 0;
+            bt->last_kernels = -1;
         }
         if (hipGraphLaunch(it->second, bt->stream) != hipSuccess) {
             bt->err = "graph launch failed";
@@ -1627,6 +1835,7 @@ void llgx_batch_destroy(llgx_batch b) {
     Batch* bt = (Batch*)b;
     (void)hipStreamSynchronize(bt->stream);
     for (auto& kv : bt->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (void* p : bt->tables) (void)hipFree(p);
     for (auto e : bt->joins) (void)hipEventDestroy(e);
     if (bt->fork) (void)hipEventDestroy(bt->fork);
     for (auto st : bt->gstreams) (void)hipStreamDestroy(st);
@@ -1714,8 +1923,37 @@ llgx_status llgx_batch_autotune(llgx_batch b, int32_t reps) {
             return st;
         }
     }
+    (void)hipStreamSynchronize(bt->stream);
     for (auto& kv : bt->graphs) (void)hipGraphExecDestroy(kv.second);
     bt->graphs.clear();
+    for (void* p : bt->tables) (void)hipFree(p);
+    bt->tables.clear();
+    return LLGX_OK;
+}
+
+llgx_status llgx_batch_set_launch(llgx_batch b, int32_t mode) {
+    if (!b) return LLGX_E_ARG;
+    Batch* bt = (Batch*)b;
+    if (mode != LLGX_BATCH_PERSISTENT && mode != LLGX_BATCH_STREAMS) {
+        bt->err = "unknown batch launch mode";
+        return LLGX_E_ARG;
+    }
+    if (mode != bt->mode) {
+        (void)hipStreamSynchronize(bt->stream);
+        for (auto& kv : bt->graphs) (void)hipGraphExecDestroy(kv.second);
+        bt->graphs.clear();
+        for (void* p : bt->tables) (void)hipFree(p);
+        bt->tables.clear();
+        bt->mode = mode;
+    }
+    return LLGX_OK;
+}
+
+llgx_status llgx_batch_launch_info(llgx_batch b, int32_t* persistent, int32_t* kernels_per_step) {
+    if (!b) return LLGX_E_ARG;
+    Batch* bt = (Batch*)b;
+    if (persistent) *persistent = bt->last_persistent;
+    if (kernels_per_step) *kernels_per_step = bt->last_kernels;
     return LLGX_OK;
 }
 

@@ -24,7 +24,7 @@ struct PtrField {
 template <typename T, typename Fld>
 __device__ __forceinline__ void heff_at(const Fld& M, long N, long cell, int x, int y, int z, int b,
                                         const Phys<T>& ph, const T hd[3], T m[3], T H[3]) {
-    const T* ha = ph.hab ? ph.hab + 3 * b : ph.ha;
+    const T* ha = ph.hab + 3 * b;
     const int sy = ph.nx, sz = ph.nx * ph.ny;
     const int d[7] = {0,
                       x > 0 ? -1 : 0,

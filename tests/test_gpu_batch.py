@@ -1,7 +1,8 @@
 """GPU tests of batched samples: each sample of a batch (samples grouped by
-mesh, per-sample applied field, one launch per group and pass, graph-replayed
-steps) equals the same sample stepped alone (bitwise: the per-sample
-arithmetic is identical) and the CPU oracle (FP32: 1e-5 Ms)."""
+mesh, per-sample applied field, graph-replayed steps; each pass one
+persistent launch over a job table of all mesh groups, or each group's own
+launches on forked streams) equals the same sample stepped alone (bitwise:
+the per-sample arithmetic is identical) and the CPU oracle (FP32: 1e-5 Ms)."""
 
 import numpy as np
 import pytest
@@ -24,15 +25,17 @@ def _samples():
     return out
 
 
+@pytest.mark.parametrize("launch", ["persistent", "streams"])
 @pytest.mark.parametrize("extrap", [None, 4], ids=["full", "p4"])
-def test_batch_matches_single_samples_and_oracle(extrap):
+def test_batch_matches_single_samples_and_oracle(extrap, launch):
     import torch
 
     import paper_2107_06729_amd as llgx
-    log(f"batch {extrap}")
+    log(f"batch {extrap} {launch}")
     samples = _samples()
     stream = torch.cuda.Stream()
     bt = llgx.Batch([p for p, _ in samples], "f32", stream=stream)
+    bt.set_launch(launch)
     assert bt.info()["groups"] == 3
     bt.precompute_demag()
     M0s = [f32_round(workloads.random_m(p["n"], p["Ms"], seed)) for p, seed in samples]
@@ -43,6 +46,10 @@ def test_batch_matches_single_samples_and_oracle(extrap):
     nsteps = 13
     bt.run_fixed(st, nsteps, use_graph=True)
     torch.cuda.synchronize()
+    info = bt.info()
+    assert info["persistent"] == (launch == "persistent"), bt.last_error()
+    if launch == "persistent":
+        assert info["kernels_per_step"] > 0
     for i, (p, seed) in enumerate(samples):
         got = to_host(bt.get_m(i))
         s = sim(p, "f32", stream=stream)
@@ -128,17 +135,18 @@ def test_batch_with_particle_array_sample(extrap):
 _CONFIG4 = {}
 
 
-def _config4_batch():
+def _config4_batch(launch):
     """The first 12 samples of the 64-sample sweep (all four meshes, their own
     fields and seeds), RK4 h = 50 fs with 4th-order extrapolation, 100
     graph-replayed steps in one batch."""
     import torch
 
     import paper_2107_06729_amd as llgx
-    if not _CONFIG4:
+    if launch not in _CONFIG4:
         samples = workloads.batch_samples(64)[:12]
         stream = torch.cuda.Stream()
         bt = llgx.Batch([p for p, _ in samples], "f32", stream=stream)
+        bt.set_launch(launch)
         assert bt.info()["groups"] == 4
         bt.precompute_demag()
         M0s = [f32_round(workloads.random_m(p["n"], p["Ms"], seed)) for p, seed in samples]
@@ -147,18 +155,27 @@ def _config4_batch():
                 bt.set_m(i, to_dev(M0, "f32"))
         bt.run_fixed(llgx.make_stepper("RK4", extrap=4, h=5e-14), 100, use_graph=True)
         torch.cuda.synchronize()
-        _CONFIG4.update(samples=samples, M0s=M0s, got=[to_host(bt.get_m(i)) for i in range(len(samples))])
+        assert bt.info()["persistent"] == (launch == "persistent"), bt.last_error()
+        _CONFIG4[launch] = dict(samples=samples, M0s=M0s,
+                                got=[to_host(bt.get_m(i)) for i in range(len(samples))])
         bt.close()
-    return _CONFIG4
+    return _CONFIG4[launch]
 
 
+@pytest.mark.parametrize("launch", ["streams", "persistent"])
 @pytest.mark.parametrize("shape", workloads.BATCH_SHAPES, ids=["x".join(map(str, n)) for n in workloads.BATCH_SHAPES])
-def test_config4_batch_against_oracle_100_steps(shape):
+def test_config4_batch_against_oracle_100_steps(shape, launch):
     """Each mesh of the batched sweep: the first sample of that mesh after 100
     batched steps is within 1e-5 Ms of the oracle (FP64 tensor, FP64
-    arithmetic) run from the same FP32-rounded state."""
+    arithmetic) run from the same FP32-rounded state; both launch modes give
+    the same bits."""
     import bench
-    c = _config4_batch()
+    c = _config4_batch(launch)
+    if launch == "persistent":  # the same bits as the forked-stream steps, checked below against the oracle
+        other = _config4_batch("streams")
+        i = next(k for k, (p, _) in enumerate(c["samples"]) if tuple(p["n"]) == tuple(shape))
+        assert np.array_equal(c["got"][i], other["got"][i])
+        return
     i = next(k for k, (p, _) in enumerate(c["samples"]) if tuple(p["n"]) == tuple(shape))
     p = c["samples"][i][0]
     log(f"config4 oracle {shape} sample {i}")
@@ -169,3 +186,44 @@ def test_config4_batch_against_oracle_100_steps(shape):
     err = np.max(np.abs(c["got"][i] - ora.M)) / p["Ms"]
     log(f"config4 {shape}: max |dM|/Ms after 100 steps = {err:.3e}")
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_persistent_launch_over_more_groups_than_one_table(prec):
+    """Six mesh groups (more than one job table holds: the per-cell passes
+    take two launches; the FFT passes one per length) of uneven sizes,
+    including a single-layer and a single-row
+    mesh: the persistent steps equal the forked-stream steps bit for bit, for
+    RK4 with and without extrapolation and Heun's method."""
+    import torch
+
+    import paper_2107_06729_amd as llgx
+    cell = (3e-9, 3e-9, 3e-9)
+    shapes = [(24, 20, 3), (64, 64, 1), (17, 9, 5), (128, 8, 2), (5, 33, 4), (40, 1, 2)]
+    probs = [workloads.problem(n, cell, 8e5, 1.3e-11, 0.05, Ha=(2e4 * (k + 1), -1e4, 3e3 * k))
+             for k, n in enumerate(shapes)]
+    probs += [dict(probs[0], Ha=(-1e4, 2e4, 0.0))]
+    M0s = [workloads.random_m(p["n"], p["Ms"], 300 + k) for k, p in enumerate(probs)]
+    if prec == "f32":
+        M0s = [f32_round(m) for m in M0s]
+    for method, extrap in (("RK4", 4), ("RK4", None), ("HEUN", None)):
+        log(f"persistent vs streams {prec} {method} {extrap}")
+        got = {}
+        for launch in ("persistent", "streams"):
+            stream = torch.cuda.Stream()
+            bt = llgx.Batch(probs, prec, stream=stream)
+            bt.set_launch(launch)
+            assert bt.info()["groups"] == 6
+            bt.precompute_demag()
+            with torch.cuda.stream(stream):
+                for i, M0 in enumerate(M0s):
+                    bt.set_m(i, to_dev(M0, prec))
+            bt.run_fixed(llgx.make_stepper(method, extrap=extrap, h=3e-14), 9, use_graph=True)
+            torch.cuda.synchronize()
+            info = bt.info()
+            assert info["persistent"] == (launch == "persistent"), bt.last_error()
+            got[launch] = [to_host(bt.get_m(i)) for i in range(len(probs))]
+            bt.close()
+        for i in range(len(probs)):
+            assert np.array_equal(got["persistent"][i], got["streams"][i]), (method, extrap, i)
+            assert np.all(np.isfinite(got["persistent"][i]))
