@@ -45,6 +45,14 @@ KIND_PATTERNS = (
 CALIB_PATTERN = r"neg_kernel"
 CALIB_BYTES = 256 << 20
 STATS_MD = os.path.join(ROOT, "profiles", "rk4_p4_f32_256x256x16_kernel_stats.md")
+PMC_MD = os.path.join(ROOT, "profiles", "k_xfwd_k_zmul_f32_256x256x16_counters.md")
+# counter passes of the occupancy / wait / instruction-mix summary (each
+# within one pass's limits: 8 SQ and 2 GRBM counters)
+PMC_PASSES = ("SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_WAIT_INST_LDS "
+              "SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS GRBM_GUI_ACTIVE",
+              "SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_LDS_BANK_CONFLICT "
+              "SQ_ACTIVE_INST_VMEM SQ_INSTS_SALU SQ_ACTIVE_INST_ANY GRBM_GUI_ACTIVE")
+N_CU, SIMD_PER_CU, CLOCK_HZ = 256, 4, 2.4e9
 
 
 def log(msg):
@@ -137,6 +145,76 @@ def _kind_of(name):
         if re.search(pat, name):
             return kind
     return None
+
+
+def summarize_pmc(dir_a, dir_b, cmd_a, cmd_b):
+    """Occupancy, waits and instruction mix of the x-forward and z passes of
+    the step from two rocprofv3 --pmc runs of this script (PMC_PASSES), as a
+    markdown table: per kernel (the instantiation with most dispatches) the
+    median over its dispatches of each counter."""
+    import csv
+    import re
+    per = {}
+    for d in (dir_a, dir_b):
+        for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
+            kind = _kind_of(r["Kernel_Name"])
+            if kind not in ("xfwd", "zmul"):
+                continue
+            e = per.setdefault(kind, {}).setdefault(r["Kernel_Name"], {"meta": r, "c": {}, "t": []})
+            e["c"].setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+            if d == dir_a and r["Counter_Name"] == "SQ_WAVES":
+                e["t"].append((float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) * 1e-9)
+
+    def med(xs):
+        xs = sorted(xs)
+        return xs[len(xs) // 2]
+
+    out = ["# Occupancy, waits and instruction mix: x forward and z pass, RK4 + p=4, FP32, 256x256x16", "",
+           "Commands (from the repository root, R = its path; one counter pass each):", "", "```", cmd_a, cmd_b,
+           "```", "",
+           "Per kernel, the median over its dispatches.  SQ counters are summed over all CUs; the SQ cycle",
+           "counters count quad-cycles (4 clocks).  t = the dispatch's own duration in the first pass.",
+           "Mean waves/SIMD = 4 SQ_WAVE_CYCLES / (t f 1024 SIMDs), VALU busy = 4 SQ_ACTIVE_INST_VALU /",
+           "(t f 1024), f = 2.4 GHz.  Wait shares are fractions of SQ_WAVE_CYCLES (wave-resident time):",
+           "SQ_WAIT_INST_ANY (a wave waits at s_waitcnt for memory or LDS results), SQ_WAIT_INST_LDS (for",
+           "LDS results), SQ_WAIT_ANY (any wait, barriers included).  LDS limit: waves/SIMD that the",
+           "workgroups' LDS allows (160 KiB per CU; the hardware holds at most 8).", "",
+           "| | " + " | ".join(f"`{re.sub(r'[(].*', '', max(v, key=lambda n: len(v[n]['t'])).replace('void llgx::', ''))}`"
+                                for k, v in sorted(per.items())) + " |",
+           "|---|" + "---:|" * len(per)]
+    rows = {}
+    for kind, v in sorted(per.items()):
+        name = max(v, key=lambda n: len(v[n]["t"]))
+        e = v[name]
+        c = {k: med(x) for k, x in e["c"].items()}
+        m = e["meta"]
+        t = med(e["t"])
+        simd_cycles = t * CLOCK_HZ * N_CU * SIMD_PER_CU
+        lds = int(m["LDS_Block_Size"])
+        wg_waves = max(1, int(m["Workgroup_Size"]) // 64)
+        occ_l = min(8.0, (160 * 1024 // lds) * wg_waves / SIMD_PER_CU) if lds > 0 else 8.0
+        waves = c["SQ_WAVES"]
+        rows.setdefault("dispatches", []).append(f"{len(e['t'])}")
+        rows.setdefault("waves per dispatch", []).append(f"{waves:.0f}")
+        rows.setdefault("t (us, median)", []).append(f"{t * 1e6:.2f}")
+        rows.setdefault("LDS bytes per workgroup", []).append(f"{lds}")
+        rows.setdefault("LDS limit, waves/SIMD", []).append(f"{occ_l:g}")
+        rows.setdefault("mean waves/SIMD resident", []).append(f"{4 * c['SQ_WAVE_CYCLES'] / simd_cycles:.2f}")
+        rows.setdefault("VALU busy", []).append(f"{4 * c['SQ_ACTIVE_INST_VALU'] / simd_cycles:.1%}")
+        rows.setdefault("wait share: s_waitcnt (memory or LDS)", []).append(
+            f"{c['SQ_WAIT_INST_ANY'] / c['SQ_WAVE_CYCLES']:.1%}")
+        rows.setdefault("wait share: LDS results", []).append(f"{c['SQ_WAIT_INST_LDS'] / c['SQ_WAVE_CYCLES']:.1%}")
+        rows.setdefault("wait share: any (barriers included)", []).append(
+            f"{c['SQ_WAIT_ANY'] / c['SQ_WAVE_CYCLES']:.1%}")
+        for k, lab in (("SQ_INSTS_VALU", "VALU"), ("SQ_INSTS_SALU", "SALU"), ("SQ_INSTS_LDS", "LDS"),
+                       ("SQ_INSTS_VMEM_RD", "global loads"), ("SQ_INSTS_VMEM_WR", "global stores")):
+            rows.setdefault(f"{lab} instructions per wave", []).append(f"{c[k] / waves:.1f}")
+        rows.setdefault("LDS bank-conflict cycles per LDS instruction", []).append(
+            f"{c['SQ_LDS_BANK_CONFLICT'] / max(1.0, c['SQ_INSTS_LDS']):.2f}")
+    for k, v in rows.items():
+        out.append(f"| {k} | " + " | ".join(v) + " |")
+    with open(PMC_MD, "w") as f:
+        f.write("\n".join(out) + "\n")
 
 
 def summarize(stats_dir, fetch_dir, write_dir, cmd_stats, cmd_fetch, cmd_write):
@@ -263,9 +341,14 @@ def main():
     ap.add_argument("--summarize", nargs=6, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR", "CMD_STATS",
                                                      "CMD_FETCH", "CMD_WRITE"),
                     help="write the profiles/ summaries from rocprofv3 output of this script (no GPU)")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("DIR_A", "DIR_B", "CMD_A", "CMD_B"),
+                    help="write the occupancy / wait counter summary from two rocprofv3 --pmc runs (no GPU)")
     args = ap.parse_args()
     if args.summarize:
         summarize(*args.summarize)
+        return
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
