@@ -33,10 +33,10 @@ KIND_PATTERNS = (
     ("xfwd", r"k_xfwd<float, float,"),
     ("yfwd", r"k_colfft<float, float, \d+, false,"),
     ("yinv", r"k_colfft<float, float, \d+, true,"),
-    ("zmul", r"k_zmul(_reg)?<float, float,"),
+    ("zmul", r"k_zmul<float, float,"),
     ("xinv", r"k_xinv<float, float,"),
     ("combine", r"k_combine<float,"),
-    ("extrap", r"k_stage<float,"),
+    ("extrap", r"k_stage<float>"),
     ("final", r"k_stage_final<float,"),
     ("epoly", r"k_epoly<float,"),
 )
