@@ -1,5 +1,7 @@
 // Streaming kernels of one explicit step (Eq. (3)-(4)) and of the
-// extrapolated sub-steps (Eq. (6)), for gfx950.
+// extrapolated sub-steps (Eq. (6)), for gfx950.  The per-block work of the
+// first five is in cells.hpp (shared with the persistent batched kernels);
+// here are the kernels over their own grids and the launchers.
 //
 // * k_combine    : M_k = M0 + sum_l (h b_kl) F_l                        (Eq. 4)
 // * k_epoly      : E_j = sum_i L_i(t_j) G_i for every distinct sub-step time
