@@ -114,15 +114,20 @@ def batch_step_bytes(problems, tsz, p):
 
 
 def source_hash():
-    """Hash of every kernel source and header (a change anywhere voids the
-    stored counter figures)."""
+    """Hash of the code of every kernel source and header, comments and
+    blank lines left out (a change of code anywhere voids the stored counter
+    figures; a comment does not)."""
+    import re
     d = os.path.join(ROOT, "paper_2107_06729_amd", "csrc")
     h = hashlib.sha256()
     for f in sorted(os.listdir(d)):
         if f.endswith((".hip", ".hpp")):
             h.update(f.encode())
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+            with open(os.path.join(d, f)) as fh:
+                for line in fh:
+                    code = re.sub(r"//.*", "", line).rstrip()
+                    if code:
+                        h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 
