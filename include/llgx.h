@@ -298,12 +298,15 @@ llgx_status llgx_load_state(llgx_handle h, const void* host_buf, size_t len);
  * for Ha share one set of kernels: every launch covers all of them (FFT
  * passes over all their rows, per-sample applied fields).  With use_graph,
  * one steady-state step of all samples is captured into a HIP graph (one per
- * history phase) and replayed.  Fixed step only; all samples share the
- * stepper and the time.  llgx_batch_set_m on any sample restarts priming of
- * its group.  Per-sample M is [3][nz][ny][nx] of the batch precision. */
+ * history phase) and replayed.  Fixed step only: all samples share the
+ * stepper and the time, so an adaptive step would have to take the smallest
+ * step any sample accepts.  spectral: the spectra's storage, as for
+ * llgx_create (16-bit storage requires LLGX_F32).  llgx_batch_set_m on any
+ * sample restarts priming of its group.  Per-sample M is [3][nz][ny][nx] of
+ * the batch precision. */
 typedef struct llgx_batch_s* llgx_batch;
-llgx_status llgx_batch_create(int32_t n, const llgx_problem* problems, int32_t precision, void* hip_stream,
-                              llgx_batch* out);
+llgx_status llgx_batch_create(int32_t n, const llgx_problem* problems, int32_t precision, int32_t spectral,
+                              void* hip_stream, llgx_batch* out);
 void llgx_batch_destroy(llgx_batch b);
 const char* llgx_batch_last_error(llgx_batch b);
 llgx_status llgx_batch_precompute_demag(llgx_batch b);

@@ -94,7 +94,8 @@ _sig = {
     "llgx_batch_autotune": (_S, [_H, ctypes.c_int32]),
     "llgx_batch_set_launch": (_S, [_H, ctypes.c_int32]),
     "llgx_batch_launch_info": (_S, [_H, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
-    "llgx_batch_create": (_S, [ctypes.c_int32, ctypes.POINTER(Problem), ctypes.c_int32, _P, ctypes.POINTER(_H)]),
+    "llgx_batch_create": (_S, [ctypes.c_int32, ctypes.POINTER(Problem), ctypes.c_int32, ctypes.c_int32, _P,
+                               ctypes.POINTER(_H)]),
     "llgx_batch_destroy": (None, [_H]),
     "llgx_batch_last_error": (ctypes.c_char_p, [_H]),
     "llgx_batch_precompute_demag": (_S, [_H]),
@@ -437,7 +438,7 @@ def _bcheck(code, handle):
 class Batch:
     """Independent samples (list of problem dicts) stepped together."""
 
-    def __init__(self, problems, precision="f32", stream=None, device="cuda:0"):
+    def __init__(self, problems, precision="f32", stream=None, device="cuda:0", spectral=SPEC_NATIVE):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -448,8 +449,8 @@ class Batch:
         with torch.cuda.device(self.device):
             self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
             self._h = _H()
-            _bcheck(_lib.llgx_batch_create(len(self.problems), arr, self.prec, _stream_ptr(self._stream),
-                                           ctypes.byref(self._h)), None)
+            _bcheck(_lib.llgx_batch_create(len(self.problems), arr, self.prec, int(spectral),
+                                           _stream_ptr(self._stream), ctypes.byref(self._h)), None)
         self._keep = []
 
     def shape(self, i):

@@ -1787,8 +1787,8 @@ llgx_status llgx_create(const llgx_problem* p, int32_t precision, int32_t spectr
     return st;
 }
 
-llgx_status llgx_batch_create(int32_t n, const llgx_problem* problems, int32_t precision, void* hip_stream,
-                              llgx_batch* out) {
+llgx_status llgx_batch_create(int32_t n, const llgx_problem* problems, int32_t precision, int32_t spectral,
+                              void* hip_stream, llgx_batch* out) {
     g_create_error.clear();
     if (!problems || !out || n < 1) {
         g_create_error = "null argument or n < 1";
@@ -1814,7 +1814,7 @@ llgx_status llgx_batch_create(int32_t n, const llgx_problem* problems, int32_t p
         for (int i : mem)
             for (int c = 0; c < 3; ++c) ha.push_back(problems[i].Ha[c]);
         Ctx* c = nullptr;
-        llgx_status st = create_ctx(&problems[mem[0]], (int)mem.size(), ha.data(), precision, LLGX_SPEC_NATIVE,
+        llgx_status st = create_ctx(&problems[mem[0]], (int)mem.size(), ha.data(), precision, spectral,
                                     hip_stream, &c, g_create_error);
         if (st) {
             for (Ctx* q : bt->groups) {

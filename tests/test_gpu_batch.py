@@ -227,3 +227,34 @@ def test_persistent_launch_over_more_groups_than_one_table(prec):
         for i in range(len(probs)):
             assert np.array_equal(got["persistent"][i], got["streams"][i]), (method, extrap, i)
             assert np.all(np.isfinite(got["persistent"][i]))
+
+
+def test_batch_with_16bit_spectra_matches_single_samples():
+    """A batch with BF16 spectra (the persistent form does not cover 16-bit
+    storage: its steps are captured on forked streams, and the batch says
+    why) gives each sample the bits it gets alone with BF16 spectra."""
+    import torch
+
+    import paper_2107_06729_amd as llgx
+    samples = _samples()[:4]
+    stream = torch.cuda.Stream()
+    bt = llgx.Batch([p for p, _ in samples], "f32", stream=stream, spectral=llgx.SPEC_BF16)
+    bt.set_launch("persistent")
+    bt.precompute_demag()
+    M0s = [f32_round(workloads.random_m(p["n"], p["Ms"], seed)) for p, seed in samples]
+    with torch.cuda.stream(stream):
+        for i, M0 in enumerate(M0s):
+            bt.set_m(i, to_dev(M0, "f32"))
+    st = llgx.make_stepper("RK4", extrap=4, h=2e-14)
+    bt.run_fixed(st, 9, use_graph=True)
+    torch.cuda.synchronize()
+    assert not bt.info()["persistent"]
+    assert "persistent launch not used" in bt.last_error()
+    for i, (p, _) in enumerate(samples):
+        s = llgx.Sim(p, "f32", spectral=llgx.SPEC_BF16, stream=stream)
+        s.precompute_demag()
+        with torch.cuda.stream(stream):
+            s.set_m(to_dev(M0s[i], "f32"))
+        for _ in range(9):
+            s.step(st)
+        assert np.array_equal(to_host(bt.get_m(i)), to_host(s.get_m())), i
