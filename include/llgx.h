@@ -298,9 +298,8 @@ llgx_status llgx_load_state(llgx_handle h, const void* host_buf, size_t len);
  * for Ha share one set of kernels: every launch covers all of them (FFT
  * passes over all their rows, per-sample applied fields).  With use_graph,
  * one steady-state step of all samples is captured into a HIP graph (one per
- * history phase) and replayed.  Fixed step only: all samples share the
- * stepper and the time, so an adaptive step would have to take the smallest
- * step any sample accepts.  spectral: the spectra's storage, as for
+ * history phase) and replayed.  All samples share the stepper and the
+ * time: adaptive steps (llgx_batch_step) take one h for all.  spectral: the spectra's storage, as for
  * llgx_create (16-bit storage requires LLGX_F32).  llgx_batch_set_m on any
  * sample restarts priming of its group.  Per-sample M is [3][nz][ny][nx] of
  * the batch precision. */
@@ -313,6 +312,14 @@ llgx_status llgx_batch_precompute_demag(llgx_batch b);
 llgx_status llgx_batch_set_m(llgx_batch b, int32_t i, const void* M_dev);
 llgx_status llgx_batch_get_m(llgx_batch b, int32_t i, void* M_dev);
 llgx_status llgx_batch_run_fixed(llgx_batch b, const llgx_stepper* s, int64_t nsteps, int32_t use_graph);
+/* One accepted step of every sample (Eq. (3)-(6)) with one h for all.  With
+ * s->adaptive the error norm e of an attempt is the largest over all samples
+ * and the Eq. (5) controller accepts or rejects it for all of them together
+ * (info->err is that e; a rejected attempt reuses every group's stage 1).
+ * Fixed steps take s->h.  Eager launches, one host synchronisation per
+ * adaptive attempt.  info may be NULL; its evaluation counts are those of
+ * the first group; max_dmdt is -1.  ABM2: LLGX_E_UNSUPPORTED. */
+llgx_status llgx_batch_step(llgx_batch b, const llgx_stepper* s, llgx_step_info* info);
 /* Autotune every mesh group of the batch (llgx_autotune on each). */
 llgx_status llgx_batch_autotune(llgx_batch b, int32_t reps);
 llgx_status llgx_batch_info(llgx_batch b, int32_t* ngroups, int64_t* total_cells, double* t);

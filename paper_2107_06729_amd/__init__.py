@@ -93,6 +93,7 @@ _sig = {
     "llgx_tune_import": (_S, [ctypes.c_char_p]),
     "llgx_batch_autotune": (_S, [_H, ctypes.c_int32]),
     "llgx_batch_set_launch": (_S, [_H, ctypes.c_int32]),
+    "llgx_batch_step": (_S, [_H, ctypes.POINTER(Stepper), ctypes.POINTER(StepInfo)]),
     "llgx_batch_launch_info": (_S, [_H, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "llgx_batch_create": (_S, [ctypes.c_int32, ctypes.POINTER(Problem), ctypes.c_int32, ctypes.c_int32, _P,
                                ctypes.POINTER(_H)]),
@@ -487,6 +488,14 @@ class Batch:
         with _Ordered(self, out):
             _bcheck(_lib.llgx_batch_get_m(self._h, int(i), ctypes.c_void_p(out.data_ptr())), self._h)
         return out
+
+    def step(self, stepper):
+        """One accepted step of every sample with one h (adaptive: the
+        error norm is the largest over all samples)."""
+        info = StepInfo()
+        _bcheck(_lib.llgx_batch_step(self._h, ctypes.byref(stepper), ctypes.byref(info)), self._h)
+        self._keep = []
+        return info.as_dict()
 
     def run_fixed(self, stepper, nsteps, use_graph=True):
         _bcheck(_lib.llgx_batch_run_fixed(self._h, ctypes.byref(stepper), int(nsteps), int(bool(use_graph))),

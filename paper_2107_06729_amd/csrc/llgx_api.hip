@@ -1623,6 +1623,130 @@ static llgx_status capture_persistent(Batch* bt, const std::vector<Plan>& plans,
     return LLGX_OK;
 }
 
+// One accepted step of every sample with one h for all: each group runs its
+// attempt (Eq. (3)-(6)), the error norm of the attempt is the maximum of the
+// groups' norms (each the maximum over its samples' cells), and the Eq. (5)
+// controller of Sec. II accepts or rejects the attempt for all samples
+// together.  Each group keeps its own priming and history.
+template <typename T>
+static llgx_status batch_step(Batch* bt, const llgx_stepper* s, llgx_step_info* info) {
+    if (!s) {
+        bt->err = "null stepper";
+        return LLGX_E_ARG;
+    }
+    const size_t ng = bt->groups.size();
+    std::vector<Plan> plans(ng);
+    const Tableau* tab = nullptr;
+    for (size_t g = 0; g < ng; ++g) {
+        Ctx* c = bt->groups[g];
+        int p;
+        llgx_status st = check_stepper(c, s, &tab, &p);
+        if (st) {
+            bt->err = c->err;
+            return st;
+        }
+        if (tab->multistep) {
+            bt->err = "ABM2 is stepped per handle, not in batches";
+            return LLGX_E_UNSUPPORTED;
+        }
+        Plan& pl = plans[g];
+        pl.tab = tab;
+        pl.p = p;
+        pl.extrap = p >= 0 && (int)c->hist.size() == p;
+        pl.stage1 = !c->fsal_valid;
+        pl.slot0 = free_slot(c);
+        pl.want_err = s->adaptive != 0;
+        pl.in_place = s->adaptive == 0;  // a rejected attempt restarts from M0
+    }
+    Ctx* c0 = bt->groups[0];
+    double h = s->h;
+    if (s->adaptive) {
+        if (c0->h_next > 0) h = c0->h_next;
+        h = std::min(std::max(h, s->h_min), s->h_max);
+    }
+    const int q = s->exponent_mode == 1 ? tab->order
+                                        : std::min(tab->order, tab->order_hat > 0 ? tab->order_hat : tab->order);
+    const long long ex0 = c0->n_exact, xt0 = c0->n_extrap;
+    int rejected = 0;
+    bool forced = false;
+    double err = -1.0, h_next = h;
+    std::vector<double> errs(ng, 0.0);
+    for (;;) {
+        for (size_t g = 0; g < ng; ++g) {
+            Ctx* c = bt->groups[g];
+            Plan& pl = plans[g];
+            pl.h = h;
+            llgx_status st = enqueue_attempt<T>(c, pl);
+            if (st) {
+                bt->err = c->err;
+                return st;
+            }
+            if (pl.stage1) c->n_exact++;
+            if (pl.extrap)
+                c->n_extrap += tab->S - 1;
+            else
+                c->n_exact += tab->S - 1;
+            if (s->adaptive &&
+                hipMemcpyAsync(&errs[g], c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess) {
+                bt->err = "error-norm copy failed";
+                return LLGX_E_HIP;
+            }
+        }
+        if (!s->adaptive) break;
+        if (hipStreamSynchronize(bt->stream) != hipSuccess) {
+            bt->err = "synchronisation failed";
+            return LLGX_E_HIP;
+        }
+        err = 0.0;
+        for (double e : errs) err = std::isfinite(e) && std::isfinite(err) ? std::max(err, e) : NAN;
+        if (!std::isfinite(err)) {
+            bt->err = "non-finite error estimate";
+            return LLGX_E_NONFINITE;
+        }
+        const double cf =
+            err <= 0.0 ? s->c_max
+                       : std::min(std::max(std::pow(0.8 * s->e_max / err, 1.0 / (q + 1)), s->c_min), s->c_max);
+        if (err > s->e_max) {
+            if (h > s->h_min) {
+                rejected++;
+                h = std::min(std::max(h * cf, s->h_min), s->h_max);
+                for (Plan& pl : plans) pl.stage1 = false;  // stage 1 does not depend on h: reuse it
+                continue;
+            }
+            forced = true;
+        }
+        h_next = std::min(std::max(h * cf, s->h_min), s->h_max);
+        break;
+    }
+    for (size_t g = 0; g < ng; ++g) {
+        Ctx* c = bt->groups[g];
+        llgx_status st = commit<T>(c, plans[g], h);
+        if (st) {
+            bt->err = c->err;
+            return st;
+        }
+        if (s->renormalize && launch_renorm<T>(c->stream, c->ncell, c->nb, (T*)c->M, c->p.Ms) != hipSuccess) {
+            bt->err = "renormalisation launch failed";
+            return LLGX_E_HIP;
+        }
+        c->h_next = s->adaptive ? h_next : h;
+        c->n_rej += rejected;
+        c->n_forced += forced;
+    }
+    if (info) {
+        info->t = c0->t;
+        info->h_used = h;
+        info->h_next = c0->h_next;
+        info->err = err;
+        info->rejected = rejected;
+        info->exact_evals = (int)(c0->n_exact - ex0);
+        info->extrap_evals = (int)(c0->n_extrap - xt0);
+        info->forced = forced;
+        info->max_dmdt = -1.0;
+    }
+    return LLGX_OK;
+}
+
 template <typename T>
 static llgx_status batch_run_fixed(Batch* bt, const llgx_stepper* s, int64_t nsteps, int use_graph) {
     if (!s || s->adaptive) {
@@ -1911,6 +2035,13 @@ llgx_status llgx_batch_run_fixed(llgx_batch b, const llgx_stepper* s, int64_t ns
     if (bt->groups.empty()) return LLGX_E_STATE;
     return bt->groups[0]->prec == LLGX_F32 ? batch_run_fixed<float>(bt, s, nsteps, use_graph)
                                            : batch_run_fixed<double>(bt, s, nsteps, use_graph);
+}
+
+llgx_status llgx_batch_step(llgx_batch b, const llgx_stepper* s, llgx_step_info* info) {
+    if (!b) return LLGX_E_ARG;
+    Batch* bt = (Batch*)b;
+    if (bt->groups.empty()) return LLGX_E_STATE;
+    return bt->groups[0]->prec == LLGX_F32 ? batch_step<float>(bt, s, info) : batch_step<double>(bt, s, info);
 }
 
 llgx_status llgx_batch_autotune(llgx_batch b, int32_t reps) {

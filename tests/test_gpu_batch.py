@@ -258,3 +258,48 @@ def test_batch_with_16bit_spectra_matches_single_samples():
         for _ in range(9):
             s.step(st)
         assert np.array_equal(to_host(bt.get_m(i)), to_host(s.get_m())), i
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_adaptive_batch_steps_share_h(prec):
+    """Adaptive RKF45 with 4th-order extrapolation over a batch of three mesh
+    groups: every attempt's error norm is the largest over the samples, one h
+    serves all.  Each sample equals the same sample stepped alone with the
+    batch's accepted steps as fixed steps, bit for bit; in FP64 the first
+    sample also matches the oracle stepped with those h."""
+    import torch
+
+    import paper_2107_06729_amd as llgx
+    samples = _samples()[:4]
+    stream = torch.cuda.Stream()
+    bt = llgx.Batch([p for p, _ in samples], prec, stream=stream)
+    bt.precompute_demag()
+    M0s = [workloads.random_m(p["n"], p["Ms"], seed) for p, seed in samples]
+    if prec == "f32":
+        M0s = [f32_round(m) for m in M0s]
+    with torch.cuda.stream(stream):
+        for i, M0 in enumerate(M0s):
+            bt.set_m(i, to_dev(M0, prec))
+    st = llgx.make_stepper("RKF45", extrap=4, h=2e-14, adaptive=True, e_max=1e-6)
+    hs, rejected = [], 0
+    for _ in range(12):
+        info = bt.step(st)
+        hs.append(info["h_used"])
+        rejected += info["rejected"]
+    torch.cuda.synchronize()
+    log(f"adaptive batch {prec}: h {hs[0]:.3g} .. {hs[-1]:.3g}, {rejected} rejected")
+    assert len(set(hs)) > 1
+    for i, (p, _) in enumerate(samples):
+        s = sim(p, prec, stream=stream)
+        with torch.cuda.stream(stream):
+            s.set_m(to_dev(M0s[i], prec))
+        for h in hs:
+            s.step(llgx.make_stepper("RKF45", extrap=4, h=h))
+        assert np.array_equal(to_host(bt.get_m(i)), to_host(s.get_m())), i
+    if prec == "f64":
+        p = samples[0][0]
+        ora = integrate.Integrator(p, M0s[0], method="RKF45", h=hs[0], adaptive=False, extrap=4,
+                                   Nfull=newell.tensor_full(p["n"], p["cell"]))
+        for h in hs:
+            ora.step(h=h)
+        assert np.max(np.abs(to_host(bt.get_m(0)) - ora.M)) <= 1e-10 * p["Ms"]
