@@ -11,6 +11,8 @@
 //                      fields), H_eff and the LLG right-hand side        (Eq. 6, 1)
 // * stage_final_block: the last sub-step fused with M = M0 + h sum c_k F_k
 //                      and the per-cell error |h sum (c_k - c^_k) F_k| / Ms (Eq. 3)
+// * stage_ep_block   : the first extrapolated sub-step fused with Eq. (6) at
+//                      every distinct sub-step time                     (Eq. 6, 1)
 // * final_blocks     : Eq. (3) update and error when the last stage is exact
 #pragma once
 #include <hip/hip_runtime.h>
@@ -204,21 +206,28 @@ __device__ __forceinline__ CellIdx cell_index(const Phys<T>& ph, const CellBlk& 
     return c;
 }
 
-// F at a sub-step: H_d = g - N00 M_k with g the Eq. (6) field of the stage's
-// time, H_eff and the LLG right-hand side; M_k = mk.base
+// F at a sub-step: H_d = w g - N00 M_k with g the Eq. (6) field of the
+// stage's time (given), H_eff and the LLG right-hand side; M_k = mk.base
 template <typename T>
-__device__ __forceinline__ void stage_rhs(const Combo<T>& mk, const Extrap<T>& ex, const Phys<T>& ph,
-                                          const CellIdx& ci, long N, T m[3], T f[3]) {
+__device__ __forceinline__ void stage_rhs_g(const Combo<T>& mk, const T g[3], T w, const Phys<T>& ph,
+                                            const CellIdx& ci, long N, T m[3], T f[3]) {
     const PtrField<T> M{mk.base + ci.off};
-    T g[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) g[c] = ex.g[0][ci.off + c * N + ci.cell];
     T hd[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) hd[c] = -ph.n00[c] * M(c * N + ci.cell) + ex.w[0] * g[c];
+    for (int c = 0; c < 3; ++c) hd[c] = -ph.n00[c] * M(c * N + ci.cell) + w * g[c];
     T H[3];
     heff_at(M, N, ci.cell, ci.x, ci.y, ci.z, ci.b, ph, hd, m, H);
     llg_at(m, H, ph, f);
+}
+
+// the same with g read from the stored or Eq. (6) field ex.g[0]
+template <typename T>
+__device__ __forceinline__ void stage_rhs(const Combo<T>& mk, const Extrap<T>& ex, const Phys<T>& ph,
+                                          const CellIdx& ci, long N, T m[3], T f[3]) {
+    T g[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g[c] = ex.g[0][ci.off + c * N + ci.cell];
+    stage_rhs_g<T>(mk, g, ex.w[0], ph, ci, N, m, f);
 }
 
 template <typename T>
@@ -240,6 +249,54 @@ __device__ __forceinline__ void stage_block(const Combo<T>& mk, const Extrap<T>&
     if (nx.mnext) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) nx.mnext[ci.off + c * N + ci.cell] = m0[c] + nx.cnext * f[c];
+    }
+}
+
+// The first extrapolated sub-step fused with Eq. (6) at every distinct
+// sub-step time of the step: the NG stored fields are read once per cell,
+// the ND fields E_j = sum_i w[j][i] G_i (the sums of epoly_*, term for
+// term) are written for the later stages, and this stage takes E_jself
+// from registers (jself < 0: its time is t0, its field ex.g[0]).
+template <typename T, int NG, int ND>
+__device__ __forceinline__ void stage_ep_block(const Combo<T>& mk, const Extrap<T>& ex, const EPoly<T>& ep,
+                                               int jself, const Phys<T>& ph, T* __restrict__ F,
+                                               const NextStage<T>& nx, const CellBlk& k) {
+    const long N = (long)ph.nx * ph.ny * ph.nz;
+    const CellIdx ci = cell_index(ph, k);
+    if (!ci.ok) return;
+    const long i0 = ci.off + ci.cell;
+    T m0[3] = {T(0), T(0), T(0)};
+    if (nx.mnext) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) m0[c] = nx.m0[i0 + c * N];
+    }
+    T gk[NG][3];
+#pragma unroll
+    for (int i = 0; i < NG; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gk[i][c] = ep.g[i][i0 + c * N];
+    T g[3] = {T(0), T(0), T(0)};
+    if (jself < 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) g[c] = ex.g[0][i0 + c * N];
+    }
+#pragma unroll
+    for (int j = 0; j < ND; ++j)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T v = T(0);
+#pragma unroll
+            for (int i = 0; i < NG; ++i) v += ep.w[j][i] * gk[i][c];
+            ep.out[j][i0 + c * N] = v;
+            if (j == jself) g[c] = v;
+        }
+    T m[3], f[3];
+    stage_rhs_g<T>(mk, g, ex.w[0], ph, ci, N, m, f);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) F[i0 + c * N] = f[c];
+    if (nx.mnext) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nx.mnext[i0 + c * N] = m0[c] + nx.cnext * f[c];
     }
 }
 

@@ -185,6 +185,12 @@ hipError_t launch_extrap_rhs(hipStream_t s, const Combo<T>& mk, const Extrap<T>&
                              const NextStage<T>& nx);
 template <typename T>
 hipError_t launch_epoly(hipStream_t s, long n, const EPoly<T>& ep);
+// launch_extrap_rhs fused with launch_epoly: writes every ep.out[j] and
+// takes this stage's field from E_jself (jself < 0: ex.g[0]); ep.ng <= 6,
+// ep.nd <= 2 (else hipErrorInvalidValue)
+template <typename T>
+hipError_t launch_stage_ep(hipStream_t s, const Combo<T>& mk, const Extrap<T>& ex, const EPoly<T>& ep, int jself,
+                           const Phys<T>& ph, T* F, const NextStage<T>& nx);
 template <typename T>
 hipError_t launch_stage_final(hipStream_t s, const Combo<T>& mk, const Extrap<T>& ex, const Phys<T>& ph, const T* M0,
                               const Final<T>& fs, double inv_ms, T* mnew, double* parts);

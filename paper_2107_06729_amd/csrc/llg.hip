@@ -9,6 +9,9 @@
 //                  serves all stages                                     (Eq. 6)
 // * k_stage      : H_d = sum_i w_i g_i - N00 M_k (g: stored or E fields),
 //                  H_eff and the LLG right-hand side at a sub-step      (Eq. 6, 1)
+// * k_stage_ep   : k_stage of the first extrapolated sub-step fused with
+//                  k_epoly (the stored fields read once, no read-back of
+//                  its own Eq. (6) field)                               (Eq. 6, 1)
 // * k_stage_final: the last sub-step fused with M = M0 + h sum c_k F_k and
 //                  the per-cell error |h sum (c_k - c^_k) F_k| / Ms      (Eq. 3)
 // * k_final      : Eq. (3) update and error when the last stage is exact
@@ -55,6 +58,14 @@ __global__ __launch_bounds__(NTS) void k_stage(Combo<T> mk, Extrap<T> ex, Phys<T
                                                NextStage<T> nx, int tx, int ry) {
     stage_block<T>(mk, ex, ph, F, nx, CellBlk{tx, ry, (int)blockIdx.x, (int)gridDim.x, (int)blockIdx.y,
                                              (int)threadIdx.x, (int)threadIdx.y});
+}
+
+template <typename T, int NG, int ND>
+__global__ __launch_bounds__(NTS) void k_stage_ep(Combo<T> mk, Extrap<T> ex, EPoly<T> ep, int jself, Phys<T> ph,
+                                                  T* __restrict__ F, NextStage<T> nx, int tx, int ry) {
+    stage_ep_block<T, NG, ND>(mk, ex, ep, jself, ph, F, nx,
+                              CellBlk{tx, ry, (int)blockIdx.x, (int)gridDim.x, (int)blockIdx.y, (int)threadIdx.x,
+                                      (int)threadIdx.y});
 }
 
 template <typename T, int NF>
@@ -260,6 +271,23 @@ hipError_t launch_extrap_rhs(hipStream_t s, const Combo<T>& mk, const Extrap<T>&
 }
 
 template <typename T>
+hipError_t launch_stage_ep(hipStream_t s, const Combo<T>& mk, const Extrap<T>& ex, const EPoly<T>& ep, int jself,
+                           const Phys<T>& ph, T* F, const NextStage<T>& nx) {
+    const CellGrid cg = cell_grid(ph.nx, ph.ny, ph.nz, ph.nb);
+    if (ex.n != 1 || mk.nf != 0 || jself >= ep.nd) return hipErrorInvalidValue;
+    const int tx = (int)cg.block.x, ry = (int)cg.block.y;
+#define EPS(G, D)                                                                                          \
+    if (ep.ng == G && ep.nd == D) {                                                                        \
+        k_stage_ep<T, G, D><<<cg.grid, cg.block, 0, s>>>(mk, ex, ep, jself, ph, F, nx, tx, ry);            \
+        return hipGetLastError();                                                                          \
+    }
+    EPS(1, 1) EPS(2, 1) EPS(3, 1) EPS(4, 1) EPS(5, 1) EPS(6, 1)
+    EPS(1, 2) EPS(2, 2) EPS(3, 2) EPS(4, 2) EPS(5, 2) EPS(6, 2)
+#undef EPS
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
 hipError_t launch_stage_final(hipStream_t s, const Combo<T>& mk, const Extrap<T>& ex, const Phys<T>& ph, const T* M0,
                               const Final<T>& fs, double inv_ms, T* mnew, double* parts) {
     const CellGrid cg = cell_grid(ph.nx, ph.ny, ph.nz, ph.nb);
@@ -341,6 +369,8 @@ hipError_t launch_cast(hipStream_t s, long n, const double* src, T* dst) {
     template hipError_t launch_epoly<T>(hipStream_t, long, const EPoly<T>&);                                     \
     template hipError_t launch_extrap_rhs<T>(hipStream_t, const Combo<T>&, const Extrap<T>&, const Phys<T>&, T*,   \
                                              const NextStage<T>&);                                               \
+    template hipError_t launch_stage_ep<T>(hipStream_t, const Combo<T>&, const Extrap<T>&, const EPoly<T>&, int, \
+                                           const Phys<T>&, T*, const NextStage<T>&);                             \
     template hipError_t launch_stage_final<T>(hipStream_t, const Combo<T>&, const Extrap<T>&, const Phys<T>&,     \
                                               const T*,                                                          \
                                               const Final<T>&, double, T*, double*);                             \

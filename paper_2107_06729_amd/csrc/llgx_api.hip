@@ -614,6 +614,8 @@ static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
     // distinct sub-step times of stages 2..S: field index per stage
     std::vector<double> times;
     std::vector<int> field_of(tab->S, -1);
+    bool fuse_ep = false;
+    EPoly<T> ep_fused{};
     if (pl.extrap) {
         for (auto& hh : c->hist) {
             nodes.push_back(hh.t - c->t);
@@ -642,11 +644,18 @@ static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
                 for (int i = 0; i < ep.ng; ++i) ep.w[j][i] = (T)w[i];
                 ep.out[j] = (T*)c->E[j];
             }
-            PROF(LLGX_K_EPOLY);
-            if (c->rec)
-                record(c, BK_EPOLY, ep.ng, BEpoly<T>{ep, 3 * c->ncell * c->nb});
-            else
-                HIPCHK(c, launch_epoly<T>(c->stream, 3 * c->ncell * c->nb, ep));
+            // with at most two distinct times, the first extrapolated stage
+            // (not the last) forms the Eq. (6) fields itself
+            fuse_ep = !c->rec && ep.nd <= 2 && ep.ng <= 6 && tab->S >= 3;
+            if (fuse_ep) {
+                ep_fused = ep;
+            } else {
+                PROF(LLGX_K_EPOLY);
+                if (c->rec)
+                    record(c, BK_EPOLY, ep.ng, BEpoly<T>{ep, 3 * c->ncell * c->nb});
+                else
+                    HIPCHK(c, launch_epoly<T>(c->stream, 3 * c->ncell * c->nb, ep));
+            }
         }
     }
     // Eq. (3) operands: stage derivatives used by the update or by the estimate
@@ -693,7 +702,8 @@ static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
             ex.n = 1;
             ex.w[0] = T(1);
             ex.g[0] = field_of[k] < 0 ? (const T*)c->G[pl.slot0] : (const T*)c->E[field_of[k]];
-            ProfScope ps(c, k == tab->S - 1 ? LLGX_K_FINAL : LLGX_K_EXTRAP);
+            const bool with_ep = fuse_ep && k == 1;
+            ProfScope ps(c, k == tab->S - 1 ? LLGX_K_FINAL : with_ep ? LLGX_K_EPOLY : LLGX_K_EXTRAP);
             if (k == tab->S - 1) {
                 add_final(k);  // own derivative, last entry
                 T* mnew = (T*)(pl.in_place ? c->M : c->Mnew);
@@ -712,6 +722,9 @@ static llgx_status enqueue_attempt(Ctx* c, const Plan& pl) {
                 }
                 if (c->rec)
                     record(c, BK_STAGE, 0, BStage<T>{cb, ex, phys<T>(c), (T*)c->F[k], nx});
+                else if (with_ep)
+                    HIPCHK(c, launch_stage_ep<T>(c->stream, cb, ex, ep_fused, field_of[k], phys<T>(c), (T*)c->F[k],
+                                                 nx));
                 else
                     HIPCHK(c, launch_extrap_rhs<T>(c->stream, cb, ex, phys<T>(c), (T*)c->F[k], nx));
             }

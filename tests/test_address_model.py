@@ -507,7 +507,7 @@ def stage_pass(pl):
         off = b * 3 * N
         heff_reads(sp, "M", off, N, cell, x, y, z, nx, ny, nz, ok)
         for c in range(3):
-            for buf in ("E", "M0", "F"):
+            for buf in ("E", "M0", "F", "G"):  # G: the stored fields the fused Eq. (6) stage reads
                 sp.add(buf, off + c * N + cell, 1, ok)
         sp.add("parts", by * gx + np.array([0, gx - 1]))  # the partial of workgroup (bx, by), bx < gx
     return sp
