@@ -31,7 +31,6 @@ constexpr int bc_tile(int L) { return col_tile<T>(L, 1); }
 template <typename T>
 constexpr int bz_tile(int LZ) { return zmul_tile<T>(LZ, 0); }
 
-
 // a uniform value of a job table, by a scalar load (the tables are
 // read-only for the kernels)
 template <typename V>
