@@ -132,17 +132,17 @@ def test_batch_with_particle_array_sample(extrap):
     assert np.all(got0[:, mask == 0] == 0)
 
 
-_CONFIG4 = {}
+_SWEEP12 = {}
 
 
-def _config4_batch(launch):
+def _sweep_batch(launch):
     """The first 12 samples of the 64-sample sweep (all four meshes, their own
     fields and seeds), RK4 h = 50 fs with 4th-order extrapolation, 100
     graph-replayed steps in one batch."""
     import torch
 
     import paper_2107_06729_amd as llgx
-    if launch not in _CONFIG4:
+    if launch not in _SWEEP12:
         samples = workloads.batch_samples(64)[:12]
         stream = torch.cuda.Stream()
         bt = llgx.Batch([p for p, _ in samples], "f32", stream=stream)
@@ -156,35 +156,35 @@ def _config4_batch(launch):
         bt.run_fixed(llgx.make_stepper("RK4", extrap=4, h=5e-14), 100, use_graph=True)
         torch.cuda.synchronize()
         assert bt.info()["persistent"] == (launch == "persistent"), bt.last_error()
-        _CONFIG4[launch] = dict(samples=samples, M0s=M0s,
+        _SWEEP12[launch] = dict(samples=samples, M0s=M0s,
                                 got=[to_host(bt.get_m(i)) for i in range(len(samples))])
         bt.close()
-    return _CONFIG4[launch]
+    return _SWEEP12[launch]
 
 
 @pytest.mark.parametrize("launch", ["streams", "persistent"])
 @pytest.mark.parametrize("shape", workloads.BATCH_SHAPES, ids=["x".join(map(str, n)) for n in workloads.BATCH_SHAPES])
-def test_config4_batch_against_oracle_100_steps(shape, launch):
+def test_sweep_batch_against_oracle_100_steps(shape, launch):
     """Each mesh of the batched sweep: the first sample of that mesh after 100
     batched steps is within 1e-5 Ms of the oracle (FP64 tensor, FP64
     arithmetic) run from the same FP32-rounded state; both launch modes give
     the same bits."""
     import bench
-    c = _config4_batch(launch)
+    c = _sweep_batch(launch)
     if launch == "persistent":  # the same bits as the forked-stream steps, checked below against the oracle
-        other = _config4_batch("streams")
+        other = _sweep_batch("streams")
         i = next(k for k, (p, _) in enumerate(c["samples"]) if tuple(p["n"]) == tuple(shape))
         assert np.array_equal(c["got"][i], other["got"][i])
         return
     i = next(k for k, (p, _) in enumerate(c["samples"]) if tuple(p["n"]) == tuple(shape))
     p = c["samples"][i][0]
-    log(f"config4 oracle {shape} sample {i}")
+    log(f"sweep batch oracle {shape} sample {i}")
     ora = integrate.Integrator(p, c["M0s"][i], method="RK4", h=5e-14, adaptive=False, extrap=4,
                                Nfull=newell.tensor_full(p["n"], p["cell"]), workers=bench.host_cores())
     for _ in range(100):
         ora.step()
     err = np.max(np.abs(c["got"][i] - ora.M)) / p["Ms"]
-    log(f"config4 {shape}: max |dM|/Ms after 100 steps = {err:.3e}")
+    log(f"sweep batch {shape}: max |dM|/Ms after 100 steps = {err:.3e}")
     assert err <= 1e-5
 
 

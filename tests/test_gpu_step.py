@@ -148,7 +148,7 @@ def test_film_256x64x1_rkdp54_p4_fp32_schedule_replay():
     assert s.counters()["extrap"] > 0
 
 
-def test_config1_film_rk4_200_steps_fp64():
+def test_film_256x64x1_rk4_200_steps_fp64():
     """32x32x2 thin film, RK4 h = 1e-13 s, 200 steps, full evaluation, FP64."""
     p = workloads.FILM_32x32x2
     n = p["n"]
@@ -162,7 +162,7 @@ def test_config1_film_rk4_200_steps_fp64():
         ora.step()
     s.run_fixed(st, 200, use_graph=False)
     got = to_host(s.get_m())
-    log(f"config1 max rel {np.max(np.abs(got - ora.M)) / p['Ms']:.3e}")
+    log(f"film 256x64x1 max rel {np.max(np.abs(got - ora.M)) / p['Ms']:.3e}")
     assert np.max(np.abs(got - ora.M)) <= 1e-12 * p["Ms"]
     # the same run with the GPU's own tensor stays within the tensor's accuracy
     s2 = sim(p, "f64")
