@@ -45,7 +45,7 @@ KIND_PATTERNS = (
 CALIB_PATTERN = r"neg_kernel"
 CALIB_BYTES = 256 << 20
 STATS_MD = os.path.join(ROOT, "profiles", "rk4_p4_f32_256x256x16_kernel_stats.md")
-PMC_MD = os.path.join(ROOT, "profiles", "k_xfwd_k_zmul_f32_256x256x16_counters.md")
+PMC_MD = os.path.join(ROOT, "profiles", "rk4_p4_f32_256x256x16_step_kernel_counters.md")
 # counter passes of the occupancy / wait / instruction-mix summary (each
 # within one pass's limits: 8 SQ and 2 GRBM counters)
 PMC_PASSES = ("SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_WAIT_INST_LDS "
@@ -158,17 +158,17 @@ def _kind_of(name):
 
 
 def summarize_pmc(dir_a, dir_b, cmd_a, cmd_b):
-    """Occupancy, waits and instruction mix of the x-forward and z passes of
-    the step from two rocprofv3 --pmc runs of this script (PMC_PASSES), as a
-    markdown table: per kernel (the instantiation with most dispatches) the
-    median over its dispatches of each counter."""
+    """Occupancy, waits and instruction mix of every kernel of the step from
+    two rocprofv3 --pmc runs of this script (PMC_PASSES), as a markdown
+    table: per kernel (the instantiation with most dispatches) the median
+    over its dispatches of each counter."""
     import csv
     import re
     per = {}
     for d in (dir_a, dir_b):
         for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
             kind = _kind_of(r["Kernel_Name"])
-            if kind not in ("xfwd", "zmul"):
+            if kind is None:
                 continue
             e = per.setdefault(kind, {}).setdefault(r["Kernel_Name"], {"meta": r, "c": {}, "t": []})
             e["c"].setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
@@ -179,7 +179,9 @@ def summarize_pmc(dir_a, dir_b, cmd_a, cmd_b):
         xs = sorted(xs)
         return xs[len(xs) // 2]
 
-    out = ["# Occupancy, waits and instruction mix: x forward and z pass, RK4 + p=4, FP32, 256x256x16", "",
+    order = [k for k, _ in KIND_PATTERNS]
+    kinds = sorted(per, key=order.index)
+    out = ["# Occupancy, waits and instruction mix of the step's kernels: RK4 + p=4, FP32, 256x256x16", "",
            "Commands (from the repository root, R = its path; one counter pass each):", "", "```", cmd_a, cmd_b,
            "```", "",
            "Per kernel, the median over its dispatches.  SQ counters are summed over all CUs; the SQ cycle",
@@ -189,11 +191,12 @@ def summarize_pmc(dir_a, dir_b, cmd_a, cmd_b):
            "SQ_WAIT_INST_ANY (a wave waits at s_waitcnt for memory or LDS results), SQ_WAIT_INST_LDS (for",
            "LDS results), SQ_WAIT_ANY (any wait, barriers included).  LDS limit: waves/SIMD that the",
            "workgroups' LDS allows (160 KiB per CU; the hardware holds at most 8).", "",
-           "| | " + " | ".join(f"`{re.sub(r'[(].*', '', max(v, key=lambda n: len(v[n]['t'])).replace('void llgx::', ''))}`"
-                                for k, v in sorted(per.items())) + " |",
-           "|---|" + "---:|" * len(per)]
+           "| | " + " | ".join(f"`{re.sub(r'[(].*', '', max(per[k], key=lambda n: len(per[k][n]['t'])).replace('void llgx::', ''))}`"
+                                for k in kinds) + " |",
+           "|---|" + "---:|" * len(kinds)]
     rows = {}
-    for kind, v in sorted(per.items()):
+    for kind in kinds:
+        v = per[kind]
         name = max(v, key=lambda n: len(v[n]["t"]))
         e = v[name]
         c = {k: med(x) for k, x in e["c"].items()}
