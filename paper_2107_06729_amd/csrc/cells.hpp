@@ -139,7 +139,8 @@ __device__ __forceinline__ void epoly_blocks(long npack, const EPoly<T>& ep, int
             g[1][k] = nt_load<T>(ep.g[k], i1);
         }
         const int nd = ND > 0 ? ND : ep.nd;
-#pragma unroll(ND > 0 ? ND : 1)
+        constexpr int UNR = ND > 0 ? ND : 1;
+#pragma unroll UNR
         for (int j = 0; j < nd; ++j) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
@@ -165,7 +166,8 @@ __device__ __forceinline__ void epoly_scalar_blocks(long n, const EPoly<T>& ep, 
 #pragma unroll
         for (int k = 0; k < NG; ++k) g[k] = ep.g[k][i];
         const int nd = ND > 0 ? ND : ep.nd;
-#pragma unroll(ND > 0 ? ND : 1)
+        constexpr int UNR = ND > 0 ? ND : 1;
+#pragma unroll UNR
         for (int j = 0; j < nd; ++j) {
             T v = T(0);
 #pragma unroll
