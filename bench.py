@@ -647,7 +647,7 @@ def main():
         # ---- batched sweep: 64 samples over 4 meshes, RK4 h = 50 fs, FP32 ---
         log("batch of 64 samples ...")
         samples = workloads.batch_samples(64)
-        for tag, ex, launch in (("p4", p, "persistent"), ("p4", p, "streams"), ("full", None, "persistent"),
+        for tag, ex, launch in (("p4", p, "jobs"), ("p4", p, "streams"), ("full", None, "jobs"),
                                 ("full", None, "streams")):
             bt = llgx.Batch([q for q, _ in samples], "f32", stream=stream)
             bt.set_launch(launch)
@@ -672,8 +672,8 @@ def main():
             extras[f"{key}_sample_ns_per_h"] = 64 * 5e-14 * 1e9 * kb_ / wall * 3600.0
             extras[f"{key}_kernels_per_step"] = inf["kernels_per_step"]
             if ex is not None:
-                # the persistent launches run Eq. (6) as a pass of its own
-                alg = batch_step_bytes([q for q, _ in samples], 4, p, fused_ep=launch != "persistent")
+                # the job-table launches run Eq. (6) as a pass of its own
+                alg = batch_step_bytes([q for q, _ in samples], 4, p, fused_ep=launch != "jobs")
                 extras[f"{key}_alg_bytes"] = alg
                 extras[f"{key}_gbs"] = alg / (wall / kb_) / 1e9
                 extras[f"{key}_roofline_frac"] = extras[f"{key}_gbs"] / HBM_PEAK_GBS

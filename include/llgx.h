@@ -326,30 +326,33 @@ llgx_status llgx_batch_info(llgx_batch b, int32_t* ngroups, int64_t* total_cells
 
 /* How a captured batched step launches its work (the parametric sweeps of
  * Sec. IV: many small, uneven meshes at once).
- *   LLGX_BATCH_PERSISTENT: each pass of the step (Eq. (6) extrapolation,
- *     stage inputs of Eq. (4), Eq. (3) update; x forward, y forward, z pass,
+ *   LLGX_BATCH_JOBS: each pass of the step (Eq. (6) extrapolation, stage
+ *     inputs of Eq. (4), Eq. (3) update; x forward, y forward, z pass,
  *     y inverse, x inverse with the fused right-hand side once per FFT
- *     length among the groups) is one persistent launch whose workgroups
- *     loop over a job table of (mesh group, tile) entries of its groups (up
- *     to 4 groups a launch; more take one launch per 4).  The job tables
- *     live in device memory the batch allocates when it captures a step and
- *     frees in llgx_batch_destroy.  Steps that have no persistent form
- *     (16-bit spectra, padded lengths above 1024 along x, 512 along y or 64
- *     along z) are captured as with LLGX_BATCH_STREAMS.
+ *     length among the groups) is one launch over a job table of
+ *     (mesh group, tile) entries of its groups, one workgroup per job (up to
+ *     4 groups a launch; more take one launch per 4).  The launches of one
+ *     pass for different FFT lengths run side by side on forked streams.
+ *     The job tables live in device memory the batch allocates when it
+ *     captures a step and frees in llgx_batch_destroy.  Steps that have no
+ *     job-table form (16-bit spectra, padded lengths above 1024 along x,
+ *     512 along y or 64 along z) are captured as with LLGX_BATCH_STREAMS.
  *   LLGX_BATCH_STREAMS (default): each group's own launches, on streams
  *     forked from the batch stream inside the captured graph, so the
- *     kernels of different meshes overlap (the faster of the two on the
+ *     kernels of different meshes overlap, and a small mesh's step does not
+ *     wait at every pass for the large ones (the faster of the two on the
  *     64-sample sweep of four meshes).
  * Both give each sample the bits it gets when stepped alone.  Changing the
  * mode synchronises the batch stream and drops the captured graphs.
  * LLGX_E_ARG for an unknown mode.
- * llgx_batch_launch_info: whether the graph captured last is persistent (1)
- * or forked (0), and its persistent launches per step (-1 when forked);
- * when a step falls back to forked streams, llgx_batch_last_error says why. */
-#define LLGX_BATCH_PERSISTENT 0
+ * llgx_batch_launch_info: whether the graph captured last uses job tables
+ * (1) or forked streams (0), and its job-table launches per step (-1 when
+ * forked); when a step falls back to forked streams, llgx_batch_last_error
+ * says why. */
+#define LLGX_BATCH_JOBS 0
 #define LLGX_BATCH_STREAMS 1
 llgx_status llgx_batch_set_launch(llgx_batch b, int32_t mode);
-llgx_status llgx_batch_launch_info(llgx_batch b, int32_t* persistent, int32_t* kernels_per_step);
+llgx_status llgx_batch_launch_info(llgx_batch b, int32_t* job_table, int32_t* kernels_per_step);
 
 /* Time, proposed next step and counters of the handle. */
 llgx_status llgx_get_time(llgx_handle h, double* t, double* h_next);

@@ -28,7 +28,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK, E_ARG, E_STATE, E_HIP, E_NONFINITE, E_OOM, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 F64, F32 = 0, 1
 SPEC_NATIVE, SPEC_BF16, SPEC_F16 = 0, 1, 2
-BATCH_PERSISTENT, BATCH_STREAMS = 0, 1
+BATCH_JOBS, BATCH_STREAMS = 0, 1
 METHODS = {"RK4": 0, "RKF45": 1, "RKCK45": 2, "RKDP54": 3, "HEUN": 4, "RK23": 5, "RKF56": 6, "ABM2": 7}
 EXTRAP_FULL, EXTRAP_MATCHED = -1, -2
 
@@ -505,17 +505,17 @@ class Batch:
     def info(self):
         ng, nc, t = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_double()
         _bcheck(_lib.llgx_batch_info(self._h, ctypes.byref(ng), ctypes.byref(nc), ctypes.byref(t)), self._h)
-        pe, nk = ctypes.c_int32(), ctypes.c_int32()
-        _bcheck(_lib.llgx_batch_launch_info(self._h, ctypes.byref(pe), ctypes.byref(nk)), self._h)
-        return {"groups": ng.value, "cells": nc.value, "t": t.value, "persistent": bool(pe.value),
+        jt, nk = ctypes.c_int32(), ctypes.c_int32()
+        _bcheck(_lib.llgx_batch_launch_info(self._h, ctypes.byref(jt), ctypes.byref(nk)), self._h)
+        return {"groups": ng.value, "cells": nc.value, "t": t.value, "job_table": bool(jt.value),
                 "kernels_per_step": nk.value}
 
     def last_error(self):
-        """The batch's last error or note (why a captured step is not persistent)."""
+        """The batch's last error or note (why a captured step does not use job tables)."""
         return _lib.llgx_batch_last_error(self._h).decode()
 
     def set_launch(self, mode):
-        """'persistent' (one launch per pass over a job table of all mesh
-        groups) or 'streams' (each group's launches on forked streams)."""
-        m = {"persistent": BATCH_PERSISTENT, "streams": BATCH_STREAMS}[mode]
+        """'jobs' (one launch per pass and FFT length over a job table of the
+        mesh groups) or 'streams' (each group's launches on forked streams)."""
+        m = {"jobs": BATCH_JOBS, "streams": BATCH_STREAMS}[mode]
         _bcheck(_lib.llgx_batch_set_launch(self._h, m), self._h)

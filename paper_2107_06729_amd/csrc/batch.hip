@@ -1,18 +1,15 @@
-// Persistent kernels of batched steps: one launch per pass of a step covers
-// every mesh group of a batch.  The launch's job table lists each group's
-// (sample, tile) jobs; workgroup w of G takes jobs w, w + G, w + 2G, ...,
-// group by group: it reads a group's arguments once and runs that group's
-// pass instance (FFT lengths are template parameters, selected per group by
-// a switch) on each of its tiles there.  LDS is dynamic and sized for the
-// largest tile of the launch.  The per-tile work is the same function the
-// single-mesh kernels run, so a batched sample computes the same bits as the
-// sample stepped alone.
+// Job-table kernels of batched steps: one launch per pass of a step (and per
+// FFT length of the pass) covers every mesh group of a batch that shares the
+// length.  The launch's job table lists each group's (sample, tile) jobs;
+// workgroup w takes job w of the concatenated table: it finds its group,
+// reads that group's arguments and runs the group's tile.  The per-tile work
+// is the same function the single-mesh kernels run, so a batched sample
+// computes the same bits as the sample stepped alone.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstring>
-#include <map>
-#include <mutex>
 
 #include "batch.hpp"
 #include "cells.hpp"
@@ -41,19 +38,19 @@ __device__ __forceinline__ V sload(const V* p) {
 
 // The job table is read from device memory (as a kernel argument, indexed
 // by the job's group, the compiler would copy it into registers), through
-// the scalar cache: no launch writes a table.  Workgroup w takes the jobs
-// w, w + G, w + 2G, ... (G workgroups) of the concatenated table; it enters
-// each group once, at its first job there (loc0), and loops over the
-// group's jobs with stride G, so the group's arguments are read once per
-// workgroup and group, not per tile.
-#define BATCH_GROUPS(J)                                                 \
-    const int stride = (int)gridDim.x;                                  \
-    const int ngroups = sload(&J->ng);                                  \
-    for (int g = 0; g < ngroups; ++g) {                                 \
-        int loc0 = ((int)blockIdx.x - sload(&J->start[g])) % stride;   \
-        if (loc0 < 0) loc0 += stride;                                   \
-        if (loc0 >= sload(&J->g[g].jobs)) continue;
-#define BATCH_GROUPS_END }
+// the scalar cache: no launch writes a table.  Group g's jobs are the
+// workgroups start[g] .. start[g] + jobs - 1 (the offsets are padded to
+// multiples of 8, so every group starts on the same XCD; the workgroups of
+// the padding exit).  One job per workgroup: a workgroup that looped over
+// several jobs (grid = resident workgroups) kept more registers live across
+// the loop and ran slower.
+#define BATCH_JOB(J)                                                          \
+    const int ngroups = sload(&J->ng);                                        \
+    if (ngroups <= 0) return;                                                 \
+    int g = 0;                                                                \
+    while (g + 1 < ngroups && (int)blockIdx.x >= sload(&J->start[g + 1])) ++g; \
+    const int loc = (int)blockIdx.x - sload(&J->start[g]);                    \
+    if (loc >= sload(&J->g[g].jobs)) return;
 
 // Every field of a group's arguments is read by a scalar load into a local
 // struct (field by field, with its own type, so the struct lives in scalar
@@ -308,129 +305,94 @@ __device__ __forceinline__ BFinal<T> job_args(const BFinal<T>* p) {
 template <typename T, int LX, int R, bool HALF>
 __global__ __launch_bounds__(NT) void kb_xfwd(const BJobs<BXfwd<T>>* __restrict__ J) {
     __shared__ XfwdShared<T, LX, R> sh;
-    BATCH_GROUPS(J)
-        const BXfwd<T> a = job_args(&J->g[g]);
-        for (int loc = loc0; loc < a.jobs; loc += stride) {
-            xfwd_tile<T, T, LX, R, HALF, true>(a.in, a.mk_out, a.nin, a.nrows, a.spec, a.SX, a.twL, a.twP, T(1),
-                                         (long)loc * R, sh);
-            __syncthreads();  // the next tile reuses the LDS
-        }
-    BATCH_GROUPS_END
+    BATCH_JOB(J)
+    const BXfwd<T> a = job_args(&J->g[g]);
+    xfwd_tile<T, T, LX, R, HALF, true>(a.in, a.mk_out, a.nin, a.nrows, a.spec, a.SX, a.twL, a.twP, T(1),
+                                       (long)loc * R, sh);
 }
 
 template <typename T, int L, bool INV, int TK>
 __global__ __launch_bounds__(NT) void kb_col(const BJobs<BCol<T>>* __restrict__ J) {
     __shared__ ColShared<T, T, L, TK> sh;
-    BATCH_GROUPS(J)
-        const BCol<T> a = job_args(&J->g[g]);
-        for (int loc = loc0; loc < a.jobs; loc += stride) {
-            colfft_tile<T, T, L, INV, TK, true>(a.src, a.s_cs, a.s_os, a.s_is, a.n_in, a.dst, a.d_cs, a.d_os,
-                                                a.d_is, a.n_out, a.Kx, a.tw, T(1), loc, a.ntx, a.nouter, a.ncomp,
-                                                sh);
-            __syncthreads();
-        }
-    BATCH_GROUPS_END
+    BATCH_JOB(J)
+    const BCol<T> a = job_args(&J->g[g]);
+    colfft_tile<T, T, L, INV, TK, true>(a.src, a.s_cs, a.s_os, a.s_is, a.n_in, a.dst, a.d_cs, a.d_os, a.d_is,
+                                        a.n_out, a.Kx, a.tw, T(1), loc, a.ntx, a.nouter, a.ncomp, sh);
 }
 
 template <typename T, int LZ, int TK>
 __global__ __launch_bounds__(NT) void kb_zmul(const BJobs<BZmul<T>>* __restrict__ J) {
     __shared__ ZmulShared<T, LZ, TK> sh;
-    BATCH_GROUPS(J)
-        const BZmul<T> a = job_args(&J->g[g]);
-        for (int loc = loc0; loc < a.jobs; loc += stride) {
-            const int tile = loc % a.ntile, q = (loc / a.ntile) % a.nq, smp = loc / (a.ntile * a.nq);
-            zmul_tile<T, T, LZ, TK>(a.buf, a.SX, a.Kx, a.nz, a.nyrows, a.Py, a.kfold, a.tw, tile, q, smp, sh);
-            __syncthreads();
-        }
-    BATCH_GROUPS_END
+    BATCH_JOB(J)
+    const BZmul<T> a = job_args(&J->g[g]);
+    const int tile = loc % a.ntile, q = (loc / a.ntile) % a.nq, smp = loc / (a.ntile * a.nq);
+    zmul_tile<T, T, LZ, TK>(a.buf, a.SX, a.Kx, a.nz, a.nyrows, a.Py, a.kfold, a.tw, tile, q, smp, sh);
 }
 
 template <typename T, int LX, int R>
 __global__ __launch_bounds__(NT) void kb_xinv(const BJobs<BXinv<T>>* __restrict__ J) {
     __shared__ XinvShared<T, LX, R> sh;
-    BATCH_GROUPS(J)
-        const BXinv<T> a = job_args(&J->g[g]);
-        for (int loc = loc0; loc < a.jobs; loc += stride) {
-            xinv_tile<T, T, LX, R, XINV_RHS>(a.spec, a.SX, a.M, a.ph, a.out, a.twL, a.twP, T(1), loc % a.gx, a.gx,
-                                             loc / a.gx, sh);
-            __syncthreads();
-        }
-    BATCH_GROUPS_END
+    BATCH_JOB(J)
+    const BXinv<T> a = job_args(&J->g[g]);
+    xinv_tile<T, T, LX, R, XINV_RHS>(a.spec, a.SX, a.M, a.ph, a.out, a.twL, a.twP, T(1), loc % a.gx, a.gx,
+                                     loc / a.gx, sh);
 }
 
 template <typename T, int NG>
 __global__ __launch_bounds__(NT) void kb_epoly(const BJobs<BEpoly<T>>* __restrict__ J) {
-    BATCH_GROUPS(J)
-        const BEpoly<T> a = job_args(&J->g[g]);
-        // the arguments are a local copy: the sub-step times are unrolled
-        for (int loc = loc0; loc < a.jobs; loc += stride) {
-            switch (a.ep.nd) {
-#define ND_(K)                                                               \
-    case K:                                                                  \
-        if (a.vec)                                                           \
-            epoly_blocks<T, NG, K>(a.n / Vec<T>::N, a.ep, loc, a.nblk);      \
-        else                                                                 \
-            epoly_scalar_blocks<T, NG, K>(a.n, a.ep, loc, a.nblk);           \
+    BATCH_JOB(J)
+    const BEpoly<T> a = job_args(&J->g[g]);
+    // the arguments are a local copy: the sub-step times are unrolled
+    switch (a.ep.nd) {
+#define ND_(K)                                                       \
+    case K:                                                          \
+        if (a.vec)                                                   \
+            epoly_blocks<T, NG, K>(a.n / Vec<T>::N, a.ep, loc, a.nblk); \
+        else                                                         \
+            epoly_scalar_blocks<T, NG, K>(a.n, a.ep, loc, a.nblk);   \
         break;
-                ND_(1) ND_(2) ND_(3) ND_(4) ND_(5) ND_(6) ND_(7) ND_(8)
+        ND_(1) ND_(2) ND_(3) ND_(4) ND_(5) ND_(6) ND_(7) ND_(8)
 #undef ND_
-                default:
-                    break;
-            }
-        }
-    BATCH_GROUPS_END
+        default:
+            break;
+    }
 }
 
 template <typename T, int NF>
 __global__ __launch_bounds__(NT) void kb_combine(const BJobs<BCombine<T>>* __restrict__ J) {
-    BATCH_GROUPS(J)
-        const BCombine<T> a = job_args(&J->g[g]);
-        for (int loc = loc0; loc < a.jobs; loc += stride) {
-            if (a.vec)
-                combine_blocks<T, NF>(a.n / Vec<T>::N, a.c, a.out, loc, a.nblk);
-            else
-                combine_scalar_blocks<T, NF>(a.n, a.c, a.out, loc, a.nblk);
-        }
-    BATCH_GROUPS_END
+    BATCH_JOB(J)
+    const BCombine<T> a = job_args(&J->g[g]);
+    if (a.vec)
+        combine_blocks<T, NF>(a.n / Vec<T>::N, a.c, a.out, loc, a.nblk);
+    else
+        combine_scalar_blocks<T, NF>(a.n, a.c, a.out, loc, a.nblk);
 }
 
 template <typename T>
 __global__ __launch_bounds__(NT) void kb_stage(const BJobs<BStage<T>>* __restrict__ J) {
-    BATCH_GROUPS(J)
-        const BStage<T> a = job_args(&J->g[g]);
-        const int tid = threadIdx.x;
-        for (int loc = loc0; loc < a.jobs; loc += stride)
-            stage_block<T>(a.mk, a.ex, a.ph, a.F, a.nx,
-                           CellBlk{a.tx, a.ry, loc % a.gx, a.gx, loc / a.gx, tid % a.tx, tid / a.tx});
-    BATCH_GROUPS_END
+    BATCH_JOB(J)
+    const BStage<T> a = job_args(&J->g[g]);
+    const int tid = threadIdx.x;
+    stage_block<T>(a.mk, a.ex, a.ph, a.F, a.nx, CellBlk{a.tx, a.ry, loc % a.gx, a.gx, loc / a.gx, tid % a.tx, tid / a.tx});
 }
 
 template <typename T, int NF>
 __global__ __launch_bounds__(NT) void kb_stage_final(const BJobs<BStageFinal<T>>* __restrict__ J) {
-    BATCH_GROUPS(J)
-        const BStageFinal<T> a = job_args(&J->g[g]);
-        const int tid = threadIdx.x;
-        for (int loc = loc0; loc < a.jobs; loc += stride) {
-            stage_final_block<T, NF>(a.mk, a.ex, a.ph, a.M0, a.fs, a.inv_ms, a.mnew, a.parts,
-                                     CellBlk{a.tx, a.ry, loc % a.gx, a.gx, loc / a.gx, tid % a.tx, tid / a.tx});
-            __syncthreads();  // the block reduction's LDS is reused
-        }
-    BATCH_GROUPS_END
+    BATCH_JOB(J)
+    const BStageFinal<T> a = job_args(&J->g[g]);
+    const int tid = threadIdx.x;
+    stage_final_block<T, NF>(a.mk, a.ex, a.ph, a.M0, a.fs, a.inv_ms, a.mnew, a.parts,
+                             CellBlk{a.tx, a.ry, loc % a.gx, a.gx, loc / a.gx, tid % a.tx, tid / a.tx});
 }
 
 template <typename T, int NF>
 __global__ __launch_bounds__(NT) void kb_final(const BJobs<BFinal<T>>* __restrict__ J) {
-    BATCH_GROUPS(J)
-        const BFinal<T> a = job_args(&J->g[g]);
-        for (int loc = loc0; loc < a.jobs; loc += stride) {
-            final_blocks<T, NF>(a.ncell, a.nb, a.base, a.fs, a.inv_ms, a.mnew, a.parts, loc, a.nblk);
-            __syncthreads();
-        }
-    BATCH_GROUPS_END
+    BATCH_JOB(J)
+    const BFinal<T> a = job_args(&J->g[g]);
+    final_blocks<T, NF>(a.ncell, a.nb, a.base, a.fs, a.inv_ms, a.mnew, a.parts, loc, a.nblk);
 }
 
-#undef BATCH_GROUPS
-#undef BATCH_GROUPS_END
+#undef BATCH_JOB
 
 // ---------------------------------------------------------------------------
 // host side
@@ -486,38 +448,18 @@ static const void* xinv_fn(int LX) {
     return nullptr;
 }
 
-// workgroups resident at once on the device for kernel f with `lds` bytes of
-// dynamic LDS (cached per kernel and size)
-static int resident_blocks(const void* f, size_t lds) {
-    static std::mutex mu;
-    static std::map<std::pair<const void*, size_t>, int> cache;
-    std::lock_guard<std::mutex> lk(mu);
-    auto key = std::make_pair(f, lds);
-    auto it = cache.find(key);
-    if (it != cache.end()) return it->second;
-    int dev = 0, ncu = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, NT, lds) != hipSuccess || per < 1 || ncu < 1)
-        return 0;
-    const int n = per * ncu;
-    cache[key] = n;
-    return n;
-}
-
-// fill the job table's start offsets, size the grid for kernel f and append
-// the table to the blob
+// fill the job table's start offsets, size the grid for kernel f (one
+// workgroup per job and padding slot) and append the table to the blob
 template <typename A>
 static hipError_t finish(const void* f, BJobs<A>& J, size_t lds, std::vector<unsigned char>& blob, BatchLaunch& out) {
-    int at = 0;
+    long at = 0;
     for (int g = 0; g < J.ng; ++g) {
-        J.start[g] = at;
-        at += (J.g[g].jobs + 7) / 8 * 8;
+        J.start[g] = (int)at;
+        at += (J.g[g].jobs + 7L) / 8 * 8;
     }
-    J.start[J.ng] = at;
-    const int res = resident_blocks(f, lds);
-    if (res < 1) return hipErrorInvalidConfiguration;
-    out.grid = (unsigned)std::max(1, std::min(at, res >= 8 ? res / 8 * 8 : res));
+    if (at > INT_MAX) return hipErrorInvalidConfiguration;
+    J.start[J.ng] = (int)at;
+    out.grid = (unsigned)std::max(1L, at);
     out.lds = lds;
     out.offset = (blob.size() + 255) / 256 * 256;
     blob.resize(out.offset + sizeof(BJobs<A>));

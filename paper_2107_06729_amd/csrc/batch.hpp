@@ -1,6 +1,6 @@
-// Persistent launches of a batch of meshes: one kernel per pass of a step
+// Job-table launches of a batch of meshes: one kernel per pass of a step
 // (per FFT length for the FFT passes) covers the mesh groups of a batch,
-// its workgroups looping over a job table of (mesh group, tile) entries.
+// one workgroup per entry of a job table of (mesh group, tile) entries.
 // The arguments of each group are the ones the single-mesh launchers take
 // (kernels.hpp); batch.hip turns them into job ranges.
 #pragma once
@@ -12,7 +12,7 @@
 
 namespace llgx {
 
-constexpr int BMAX = 4;  // mesh groups per persistent launch (kernel-argument size)
+constexpr int BMAX = 4;  // mesh groups per job-table launch
 
 enum BatchKind { BK_XFWD, BK_COL, BK_ZMUL, BK_XINV, BK_EPOLY, BK_STAGE, BK_STAGE_FINAL, BK_COMBINE, BK_FINAL };
 
@@ -110,7 +110,7 @@ struct BFinal {
     int nblk, jobs;
 };
 
-// job table of one persistent launch: jobs start[g] .. start[g] + g[g].jobs - 1
+// job table of one launch: jobs start[g] .. start[g] + g[g].jobs - 1
 // belong to group g (start[g] is a multiple of 8, so a job's XCD is its
 // index within the group modulo 8, as in the single-mesh kernels)
 template <typename A>
@@ -120,13 +120,13 @@ struct BJobs {
     int ng;
 };
 
-// A prepared persistent launch: its job table is copied into device memory
+// A prepared job-table launch: its job table is copied into device memory
 // (at `offset` of a buffer the caller owns) before enqueue_batch launches
 // the kernel with a pointer to it, so the launch can be captured into a
 // graph.
 struct BatchLaunch {
     int kind, nf;
-    unsigned grid;   // workgroups (at most the device's resident count)
+    unsigned grid;   // workgroups: one per job and padding slot
     size_t lds;      // dynamic LDS per workgroup
     size_t offset;   // of the job table in the table buffer
     const void* fn;  // the kernel (its one argument: the job table)
@@ -149,7 +149,7 @@ int batch_instance(int kind, const void* arg);
 // derivatives; for BK_COL 0 forward, 1 inverse).  At most BMAX groups, all
 // of one batch_instance.  The job table is appended to `blob` (256-byte
 // aligned).  hipErrorInvalidValue when a group is outside what the
-// persistent kernels are built for.
+// job-table kernels are built for.
 template <typename T>
 hipError_t prepare_batch(int kind, int nf, const std::vector<const void*>& args, std::vector<unsigned char>& blob,
                          BatchLaunch& out);

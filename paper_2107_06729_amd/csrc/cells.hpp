@@ -1,7 +1,7 @@
 // Per-cell streaming and stencil work of one explicit step (Eq. (3)-(4))
 // and of the extrapolated sub-steps (Eq. (6)), as the work of one
 // workgroup: llg.hip wraps each part in a kernel over its own grid,
-// batch.hip in persistent kernels that loop over a job table of meshes.
+// batch.hip in kernels over a job table of meshes.
 //
 // * combine_*        : M_k = M0 + sum_l (h b_kl) F_l                    (Eq. 4)
 // * epoly_*          : E_j = sum_i L_i(t_j) G_i for every distinct sub-step
@@ -83,7 +83,7 @@ __device__ __forceinline__ typename Vec<T>::type nt_load(const T* p, long i) {
 
 // Work of workgroup blk of nblk (grid-stride over 16-byte packs or cells);
 // the kernels of llg.hip pass their block index and grid size, the batched
-// persistent kernels of batch.hip their job index and job count.
+// job-table kernels of batch.hip their job index and job count.
 template <typename T, int NF>
 __device__ __forceinline__ void combine_blocks(long npack, const Combo<T>& c, T* __restrict__ out, int blk, int nblk) {
     using V = typename Vec<T>::type;

@@ -1,6 +1,6 @@
 // Streaming kernels of one explicit step (Eq. (3)-(4)) and of the
 // extrapolated sub-steps (Eq. (6)), for gfx950.  The per-block work of the
-// first five is in cells.hpp (shared with the persistent batched kernels);
+// first five is in cells.hpp (shared with the job-table batched kernels);
 // here are the kernels over their own grids and the launchers.
 //
 // * k_combine    : M_k = M0 + sum_l (h b_kl) F_l                        (Eq. 4)

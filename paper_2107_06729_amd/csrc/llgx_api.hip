@@ -126,9 +126,9 @@ struct Ctx {
     std::map<GraphKey, hipGraphExec_t> graphs;
 
     // When set, the launches of one step attempt are recorded here (kind of
-    // the persistent batched kernel, its template count, its arguments)
+    // the job-table batched kernel, its template count, its arguments)
     // instead of made; rec_unsupported is set by a launch that has no
-    // persistent form (16-bit spectra, error-norm reduction, ...).
+    // job-table form (16-bit spectra, error-norm reduction, ...).
     struct Rec {
         int kind, nf;
         std::vector<unsigned char> arg;
@@ -308,7 +308,7 @@ static void record(Ctx* c, int kind, int nf, const A& a) {
     c->rec->push_back(std::move(r));
 }
 
-// the arguments of pass `kind` for the persistent batched kernels
+// the arguments of pass `kind` for the job-table batched kernels
 template <typename T>
 static void record_pass(Ctx* c, int kind, const EvalArgs<T>& a, void* A, void* B) {
     using C = cx<T>;
@@ -1525,14 +1525,35 @@ struct Batch {
     std::vector<hipEvent_t> joins;
     hipEvent_t fork = nullptr;
     // LLGX_BATCH_STREAMS (default): the groups' own launches on forked
-    // streams; LLGX_BATCH_PERSISTENT: each pass of a captured step is one
-    // persistent launch over a job table of the mesh groups (per FFT length
+    // streams; LLGX_BATCH_JOBS: each pass of a captured step is one
+    // launch over a job table of the mesh groups (per FFT length
     // for the FFT passes; up to BMAX groups a launch), where every launch of
     // the step has that form (else the forked-stream capture)
     int mode = LLGX_BATCH_STREAMS;
-    std::vector<void*> tables;  // device job tables of the captured persistent steps
-    int last_persistent = 0, last_kernels = 0;
+    std::vector<void*> tables;  // device job tables of the captured job-table steps
+    std::vector<hipEvent_t> cap_events;  // fork/join events of the captured job-table steps
+    int last_jobs = 0, last_kernels = 0;
 };
+
+// the streams and events of forked captures: ng - 1 side streams (default
+// priority) and their join events, and the fork event
+static llgx_status fork_streams(Batch* bt, size_t ng) {
+    if (ng < 2 || !bt->gstreams.empty()) return LLGX_OK;
+    hipError_t e = hipEventCreateWithFlags(&bt->fork, hipEventDisableTiming);
+    for (size_t g = 1; g < ng && e == hipSuccess; ++g) {
+        hipStream_t gs = nullptr;
+        hipEvent_t je = nullptr;
+        e = hipStreamCreateWithFlags(&gs, hipStreamNonBlocking);
+        if (e == hipSuccess) bt->gstreams.push_back(gs);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&je, hipEventDisableTiming);
+        if (e == hipSuccess) bt->joins.push_back(je);
+    }
+    if (e != hipSuccess) {
+        bt->err = "stream creation failed";
+        return LLGX_E_HIP;
+    }
+    return LLGX_OK;
+}
 
 static bool same_material(const llgx_problem& a, const llgx_problem& b) {
     return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.dx == b.dx && a.dy == b.dy && a.dz == b.dz &&
@@ -1540,17 +1561,17 @@ static bool same_material(const llgx_problem& a, const llgx_problem& b) {
            a.easy[2] == b.easy[2] && a.alpha == b.alpha && a.gamma == b.gamma;
 }
 
-// Capture one step of every group as persistent launches: each group's
+// Capture one step of every group as job-table launches: each group's
 // launches are recorded (enqueue_attempt with Ctx::rec), the i-th launches
 // of all groups are joined into one job table per FFT length and BMAX
 // groups (a group without the pass, a one-row mesh's y passes, takes no
-// part), the tables
-// are copied to device memory (kept for the graph's lifetime), and the
-// launches are captured on the batch stream.  LLGX_E_UNSUPPORTED (nothing
-// captured) when some launch has no persistent form or the groups' launch
+// part), the tables are copied to device memory (kept for the graph's
+// lifetime), and the launches are captured on the batch stream, those of
+// one pass side by side on forked streams.  LLGX_E_UNSUPPORTED (nothing
+// captured) when some launch has no job-table form or the groups' launch
 // sequences differ (then the forked-stream capture is used).
 template <typename T>
-static llgx_status capture_persistent(Batch* bt, const std::vector<Plan>& plans, hipGraphExec_t* out, int* nkern) {
+static llgx_status capture_jobs(Batch* bt, const std::vector<Plan>& plans, hipGraphExec_t* out, int* nkern) {
     const size_t ng = bt->groups.size();
     std::vector<std::vector<Ctx::Rec>> recs(ng);
     bool ok = true;
@@ -1569,11 +1590,14 @@ static llgx_status capture_persistent(Batch* bt, const std::vector<Plan>& plans,
             ok = recs[g][i].kind == recs[0][i].kind && recs[g][i].nf == recs[0][i].nf;
     }
     if (!ok) {
-        bt->err = "persistent launch not used: a launch without persistent form, or groups with different launches";
+        bt->err = "job-table launch not used: a launch without job-table form, or groups with different launches";
         return LLGX_E_UNSUPPORTED;
     }
     std::vector<unsigned char> blob;
-    std::vector<BatchLaunch> launches;
+    // launches of the i-th recorded launch: one per FFT length (and BMAX
+    // groups), independent of each other
+    std::vector<std::vector<BatchLaunch>> levels(recs[0].size());
+    size_t width = 1, nlaunch = 0;
     for (size_t i = 0; i < recs[0].size(); ++i) {
         // the groups of each FFT length (one key for the per-cell kinds)
         std::map<int, std::vector<const void*>> by_len;
@@ -1588,17 +1612,24 @@ static llgx_status capture_persistent(Batch* bt, const std::vector<Plan>& plans,
                 BatchLaunch bl{};
                 hipError_t e = prepare_batch<T>(recs[0][i].kind, recs[0][i].nf, args, blob, bl);
                 if (e == hipErrorInvalidValue) {
-                    bt->err = "persistent launch not used: launch " + std::to_string(i) + " (kind " +
-                              std::to_string(recs[0][i].kind) + ") outside the persistent kernels' lengths";
+                    bt->err = "job-table launch not used: launch " + std::to_string(i) + " (kind " +
+                              std::to_string(recs[0][i].kind) + ") outside the job-table kernels' lengths";
                     return LLGX_E_UNSUPPORTED;
                 }
                 if (e != hipSuccess) {
-                    bt->err = std::string("persistent launch setup failed: ") + hipGetErrorString(e);
+                    bt->err = std::string("job-table launch setup failed: ") + hipGetErrorString(e);
                     return LLGX_E_HIP;
                 }
-                launches.push_back(bl);
+                levels[i].push_back(bl);
             }
         }
+        width = std::max(width, levels[i].size());
+        nlaunch += levels[i].size();
+    }
+    if (llgx_status fs = fork_streams(bt, ng)) return fs;
+    if (bt->gstreams.size() + 1 < width) {
+        bt->err = "job-table launch not used: more launches of one pass than side streams";
+        return LLGX_E_UNSUPPORTED;
     }
     void* dev = nullptr;
     if (hipMalloc(&dev, std::max<size_t>(blob.size(), 256)) != hipSuccess) {
@@ -1615,13 +1646,38 @@ static llgx_status capture_persistent(Batch* bt, const std::vector<Plan>& plans,
         bt->err = "graph capture could not start";
         return LLGX_E_HIP;
     }
+    // the launches of one level run side by side: launch 0 on the batch
+    // stream, launch j on side stream j - 1, forked from and joined back into
+    // the batch stream (events of their own, kept until the batch is
+    // destroyed)
     hipError_t e = hipSuccess;
-    for (size_t i = 0; i < launches.size() && e == hipSuccess; ++i)
-        e = enqueue_batch(launches[i], (const char*)dev + launches[i].offset, bt->stream);
+    auto event = [&](hipEvent_t* ev) {
+        if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+        if (e == hipSuccess) bt->cap_events.push_back(*ev);
+    };
+    for (size_t i = 0; i < levels.size() && e == hipSuccess; ++i) {
+        const std::vector<BatchLaunch>& lv = levels[i];
+        if (lv.empty()) continue;
+        hipEvent_t fk = nullptr;
+        std::vector<hipEvent_t> jn(lv.size(), nullptr);
+        if (lv.size() > 1) {
+            event(&fk);
+            if (e == hipSuccess) e = hipEventRecord(fk, bt->stream);
+        }
+        for (size_t j = 1; j < lv.size() && e == hipSuccess; ++j) {
+            hipStream_t ss = bt->gstreams[j - 1];
+            e = hipStreamWaitEvent(ss, fk, 0);
+            if (e == hipSuccess) e = enqueue_batch(lv[j], (const char*)dev + lv[j].offset, ss);
+            event(&jn[j]);
+            if (e == hipSuccess) e = hipEventRecord(jn[j], ss);
+        }
+        if (e == hipSuccess) e = enqueue_batch(lv[0], (const char*)dev + lv[0].offset, bt->stream);
+        for (size_t j = 1; j < lv.size() && e == hipSuccess; ++j) e = hipStreamWaitEvent(bt->stream, jn[j], 0);
+    }
     hipError_t e2 = hipStreamEndCapture(bt->stream, &gr);
     if (e != hipSuccess || e2 != hipSuccess) {
         if (e2 == hipSuccess) (void)hipGraphDestroy(gr);
-        bt->err = std::string("persistent capture failed: ") + hipGetErrorString(e != hipSuccess ? e : e2);
+        bt->err = std::string("job-table capture failed: ") + hipGetErrorString(e != hipSuccess ? e : e2);
         return LLGX_E_HIP;
     }
     hipGraphExec_t ge;
@@ -1632,7 +1688,7 @@ static llgx_status capture_persistent(Batch* bt, const std::vector<Plan>& plans,
         return LLGX_E_HIP;
     }
     *out = ge;
-    *nkern = (int)launches.size();
+    *nkern = (int)nlaunch;
     return LLGX_OK;
 }
 
@@ -1814,13 +1870,13 @@ static llgx_status batch_run_fixed(Batch* bt, const llgx_stepper* s, int64_t nst
             continue;
         }
         auto it = bt->graphs.find(keys);
-        if (it == bt->graphs.end() && bt->mode == LLGX_BATCH_PERSISTENT) {
+        if (it == bt->graphs.end() && bt->mode == LLGX_BATCH_JOBS) {
             hipGraphExec_t ge;
             int nk = 0;
-            llgx_status st = capture_persistent<T>(bt, plans, &ge, &nk);
+            llgx_status st = capture_jobs<T>(bt, plans, &ge, &nk);
             if (st == LLGX_OK) {
                 it = bt->graphs.emplace(keys, ge).first;
-                bt->last_persistent = 1;
+                bt->last_jobs = 1;
                 bt->last_kernels = nk;
             } else if (st != LLGX_E_UNSUPPORTED) {
                 return st;
@@ -1832,20 +1888,8 @@ static llgx_status batch_run_fixed(Batch* bt, const llgx_stepper* s, int64_t nst
                 bt->err = "graph capture could not start";
                 return LLGX_E_HIP;
             }
-            llgx_status st = LLGX_OK;
             const size_t ng = bt->groups.size();
-            if (ng > 1 && bt->gstreams.empty()) {
-                hipError_t e = hipEventCreateWithFlags(&bt->fork, hipEventDisableTiming);
-                for (size_t g = 1; g < ng && e == hipSuccess; ++g) {
-                    hipStream_t gs = nullptr;
-                    hipEvent_t je = nullptr;
-                    e = hipStreamCreateWithFlags(&gs, hipStreamNonBlocking);
-                    if (e == hipSuccess) bt->gstreams.push_back(gs);
-                    if (e == hipSuccess) e = hipEventCreateWithFlags(&je, hipEventDisableTiming);
-                    if (e == hipSuccess) bt->joins.push_back(je);
-                }
-                if (e != hipSuccess) st = LLGX_E_HIP, bt->err = "stream creation failed";
-            }
+            llgx_status st = fork_streams(bt, ng);
             if (st == LLGX_OK && ng > 1 && hipEventRecord(bt->fork, bt->stream) != hipSuccess)
                 st = LLGX_E_HIP, bt->err = "event record failed";
             for (size_t g = 0; g < ng && st == LLGX_OK; ++g) {
@@ -1883,7 +1927,7 @@ static llgx_status batch_run_fixed(Batch* bt, const llgx_stepper* s, int64_t nst
             }
             (void)hipGraphDestroy(gr);
             it = bt->graphs.emplace(keys, ge).first;
-            bt->last_persistent = 0;
+            bt->last_jobs = 0;
             bt->last_kernels = -1;
         }
         if (hipGraphLaunch(it->second, bt->stream) != hipSuccess) {
@@ -1974,6 +2018,7 @@ void llgx_batch_destroy(llgx_batch b) {
     for (auto& kv : bt->graphs) (void)hipGraphExecDestroy(kv.second);
     for (void* p : bt->tables) (void)hipFree(p);
     for (auto e : bt->joins) (void)hipEventDestroy(e);
+    for (auto e : bt->cap_events) (void)hipEventDestroy(e);
     if (bt->fork) (void)hipEventDestroy(bt->fork);
     for (auto st : bt->gstreams) (void)hipStreamDestroy(st);
     for (Ctx* c : bt->groups) {
@@ -2072,13 +2117,15 @@ llgx_status llgx_batch_autotune(llgx_batch b, int32_t reps) {
     bt->graphs.clear();
     for (void* p : bt->tables) (void)hipFree(p);
     bt->tables.clear();
+    for (auto e : bt->cap_events) (void)hipEventDestroy(e);
+    bt->cap_events.clear();
     return LLGX_OK;
 }
 
 llgx_status llgx_batch_set_launch(llgx_batch b, int32_t mode) {
     if (!b) return LLGX_E_ARG;
     Batch* bt = (Batch*)b;
-    if (mode != LLGX_BATCH_PERSISTENT && mode != LLGX_BATCH_STREAMS) {
+    if (mode != LLGX_BATCH_JOBS && mode != LLGX_BATCH_STREAMS) {
         bt->err = "unknown batch launch mode";
         return LLGX_E_ARG;
     }
@@ -2088,15 +2135,17 @@ llgx_status llgx_batch_set_launch(llgx_batch b, int32_t mode) {
         bt->graphs.clear();
         for (void* p : bt->tables) (void)hipFree(p);
         bt->tables.clear();
+        for (auto e : bt->cap_events) (void)hipEventDestroy(e);
+        bt->cap_events.clear();
         bt->mode = mode;
     }
     return LLGX_OK;
 }
 
-llgx_status llgx_batch_launch_info(llgx_batch b, int32_t* persistent, int32_t* kernels_per_step) {
+llgx_status llgx_batch_launch_info(llgx_batch b, int32_t* job_table, int32_t* kernels_per_step) {
     if (!b) return LLGX_E_ARG;
     Batch* bt = (Batch*)b;
-    if (persistent) *persistent = bt->last_persistent;
+    if (job_table) *job_table = bt->last_jobs;
     if (kernels_per_step) *kernels_per_step = bt->last_kernels;
     return LLGX_OK;
 }

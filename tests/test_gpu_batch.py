@@ -1,6 +1,6 @@
 """GPU tests of batched samples: each sample of a batch (samples grouped by
 mesh, per-sample applied field, graph-replayed steps; each pass one
-persistent launch over a job table of all mesh groups, or each group's own
+launch over a job table of all mesh groups, or each group's own
 launches on forked streams) equals the same sample stepped alone (bitwise:
 the per-sample arithmetic is identical) and the CPU oracle (FP32: 1e-5 Ms)."""
 
@@ -25,7 +25,7 @@ def _samples():
     return out
 
 
-@pytest.mark.parametrize("launch", ["persistent", "streams"])
+@pytest.mark.parametrize("launch", ["jobs", "streams"])
 @pytest.mark.parametrize("extrap", [None, 4], ids=["full", "p4"])
 def test_batch_matches_single_samples_and_oracle(extrap, launch):
     import torch
@@ -47,8 +47,8 @@ def test_batch_matches_single_samples_and_oracle(extrap, launch):
     bt.run_fixed(st, nsteps, use_graph=True)
     torch.cuda.synchronize()
     info = bt.info()
-    assert info["persistent"] == (launch == "persistent"), bt.last_error()
-    if launch == "persistent":
+    assert info["job_table"] == (launch == "jobs"), bt.last_error()
+    if launch == "jobs":
         assert info["kernels_per_step"] > 0
     for i, (p, seed) in enumerate(samples):
         got = to_host(bt.get_m(i))
@@ -155,14 +155,14 @@ def _sweep_batch(launch):
                 bt.set_m(i, to_dev(M0, "f32"))
         bt.run_fixed(llgx.make_stepper("RK4", extrap=4, h=5e-14), 100, use_graph=True)
         torch.cuda.synchronize()
-        assert bt.info()["persistent"] == (launch == "persistent"), bt.last_error()
+        assert bt.info()["job_table"] == (launch == "jobs"), bt.last_error()
         _SWEEP12[launch] = dict(samples=samples, M0s=M0s,
                                 got=[to_host(bt.get_m(i)) for i in range(len(samples))])
         bt.close()
     return _SWEEP12[launch]
 
 
-@pytest.mark.parametrize("launch", ["streams", "persistent"])
+@pytest.mark.parametrize("launch", ["streams", "jobs"])
 @pytest.mark.parametrize("shape", workloads.BATCH_SHAPES, ids=["x".join(map(str, n)) for n in workloads.BATCH_SHAPES])
 def test_sweep_batch_against_oracle_100_steps(shape, launch):
     """Each mesh of the batched sweep: the first sample of that mesh after 100
@@ -171,7 +171,7 @@ def test_sweep_batch_against_oracle_100_steps(shape, launch):
     the same bits."""
     import bench
     c = _sweep_batch(launch)
-    if launch == "persistent":  # the same bits as the forked-stream steps, checked below against the oracle
+    if launch == "jobs":  # the same bits as the forked-stream steps, checked below against the oracle
         other = _sweep_batch("streams")
         i = next(k for k, (p, _) in enumerate(c["samples"]) if tuple(p["n"]) == tuple(shape))
         assert np.array_equal(c["got"][i], other["got"][i])
@@ -189,11 +189,11 @@ def test_sweep_batch_against_oracle_100_steps(shape, launch):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_persistent_launch_over_more_groups_than_one_table(prec):
+def test_job_table_launch_over_more_groups_than_one_table(prec):
     """Six mesh groups (more than one job table holds: the per-cell passes
     take two launches; the FFT passes one per length) of uneven sizes,
     including a single-layer and a single-row
-    mesh: the persistent steps equal the forked-stream steps bit for bit, for
+    mesh: the job-table steps equal the forked-stream steps bit for bit, for
     RK4 with and without extrapolation and Heun's method."""
     import torch
 
@@ -207,9 +207,9 @@ def test_persistent_launch_over_more_groups_than_one_table(prec):
     if prec == "f32":
         M0s = [f32_round(m) for m in M0s]
     for method, extrap in (("RK4", 4), ("RK4", None), ("HEUN", None)):
-        log(f"persistent vs streams {prec} {method} {extrap}")
+        log(f"jobs vs streams {prec} {method} {extrap}")
         got = {}
-        for launch in ("persistent", "streams"):
+        for launch in ("jobs", "streams"):
             stream = torch.cuda.Stream()
             bt = llgx.Batch(probs, prec, stream=stream)
             bt.set_launch(launch)
@@ -221,16 +221,16 @@ def test_persistent_launch_over_more_groups_than_one_table(prec):
             bt.run_fixed(llgx.make_stepper(method, extrap=extrap, h=3e-14), 9, use_graph=True)
             torch.cuda.synchronize()
             info = bt.info()
-            assert info["persistent"] == (launch == "persistent"), bt.last_error()
+            assert info["job_table"] == (launch == "jobs"), bt.last_error()
             got[launch] = [to_host(bt.get_m(i)) for i in range(len(probs))]
             bt.close()
         for i in range(len(probs)):
-            assert np.array_equal(got["persistent"][i], got["streams"][i]), (method, extrap, i)
-            assert np.all(np.isfinite(got["persistent"][i]))
+            assert np.array_equal(got["jobs"][i], got["streams"][i]), (method, extrap, i)
+            assert np.all(np.isfinite(got["jobs"][i]))
 
 
 def test_batch_with_16bit_spectra_matches_single_samples():
-    """A batch with BF16 spectra (the persistent form does not cover 16-bit
+    """A batch with BF16 spectra (the job-table form does not cover 16-bit
     storage: its steps are captured on forked streams, and the batch says
     why) gives each sample the bits it gets alone with BF16 spectra."""
     import torch
@@ -239,7 +239,7 @@ def test_batch_with_16bit_spectra_matches_single_samples():
     samples = _samples()[:4]
     stream = torch.cuda.Stream()
     bt = llgx.Batch([p for p, _ in samples], "f32", stream=stream, spectral=llgx.SPEC_BF16)
-    bt.set_launch("persistent")
+    bt.set_launch("jobs")
     bt.precompute_demag()
     M0s = [f32_round(workloads.random_m(p["n"], p["Ms"], seed)) for p, seed in samples]
     with torch.cuda.stream(stream):
@@ -248,8 +248,8 @@ def test_batch_with_16bit_spectra_matches_single_samples():
     st = llgx.make_stepper("RK4", extrap=4, h=2e-14)
     bt.run_fixed(st, 9, use_graph=True)
     torch.cuda.synchronize()
-    assert not bt.info()["persistent"]
-    assert "persistent launch not used" in bt.last_error()
+    assert not bt.info()["job_table"]
+    assert "job-table launch not used" in bt.last_error()
     for i, (p, _) in enumerate(samples):
         s = llgx.Sim(p, "f32", spectral=llgx.SPEC_BF16, stream=stream)
         s.precompute_demag()
