@@ -451,7 +451,7 @@ static const void* xinv_fn(int LX) {
 // fill the job table's start offsets, size the grid for kernel f (one
 // workgroup per job and padding slot) and append the table to the blob
 template <typename A>
-static hipError_t finish(const void* f, BJobs<A>& J, size_t lds, std::vector<unsigned char>& blob, BatchLaunch& out) {
+static hipError_t finish(const void* f, BJobs<A>& J, std::vector<unsigned char>& blob, BatchLaunch& out) {
     long at = 0;
     for (int g = 0; g < J.ng; ++g) {
         J.start[g] = (int)at;
@@ -460,7 +460,6 @@ static hipError_t finish(const void* f, BJobs<A>& J, size_t lds, std::vector<uns
     if (at > INT_MAX) return hipErrorInvalidConfiguration;
     J.start[J.ng] = (int)at;
     out.grid = (unsigned)std::max(1L, at);
-    out.lds = lds;
     out.offset = (blob.size() + 255) / 256 * 256;
     blob.resize(out.offset + sizeof(BJobs<A>));
     std::memcpy(blob.data() + out.offset, &J, sizeof(BJobs<A>));
@@ -470,7 +469,7 @@ static hipError_t finish(const void* f, BJobs<A>& J, size_t lds, std::vector<uns
 
 hipError_t enqueue_batch(const BatchLaunch& b, const void* table_dev, hipStream_t s) {
     void* args[] = {(void*)&table_dev};
-    return hipLaunchKernel(b.fn, dim3(b.grid), dim3(NT), args, b.lds, s);
+    return hipLaunchKernel(b.fn, dim3(b.grid), dim3(NT), args, 0, s);
 }
 
 template <typename T>
@@ -510,7 +509,7 @@ hipError_t prepare_batch(int kind, int nf, const std::vector<const void*>& args,
                 a.jobs = (int)((a.nrows + bx_rows<T>(a.LX) - 1) / bx_rows<T>(a.LX));
             }
             const void* f = xfwd_fn<T>(LX);
-            return f ? finish<BXfwd<T>>(f, J, 0, blob, out) : hipErrorInvalidValue;
+            return f ? finish<BXfwd<T>>(f, J, blob, out) : hipErrorInvalidValue;
         }
         case BK_COL: {
             BJobs<BCol<T>> J{};
@@ -526,7 +525,7 @@ hipError_t prepare_batch(int kind, int nf, const std::vector<const void*>& args,
                 a.jobs = a.ntx * a.nouter * a.ncomp;
             }
             const void* f = inv ? col_fn<T, true>(L) : col_fn<T, false>(L);
-            return f ? finish<BCol<T>>(f, J, 0, blob, out) : hipErrorInvalidValue;
+            return f ? finish<BCol<T>>(f, J, blob, out) : hipErrorInvalidValue;
         }
         case BK_ZMUL: {
             BJobs<BZmul<T>> J{};
@@ -542,7 +541,7 @@ hipError_t prepare_batch(int kind, int nf, const std::vector<const void*>& args,
                 a.jobs = a.ntile * a.nq * a.nb;
             }
             const void* f = zmul_fn<T>(LZ);
-            return f ? finish<BZmul<T>>(f, J, 0, blob, out) : hipErrorInvalidValue;
+            return f ? finish<BZmul<T>>(f, J, blob, out) : hipErrorInvalidValue;
         }
         case BK_XINV: {
             BJobs<BXinv<T>> J{};
@@ -556,7 +555,7 @@ hipError_t prepare_batch(int kind, int nf, const std::vector<const void*>& args,
                 a.jobs = a.gx * a.ph.nb;
             }
             const void* f = xinv_fn<T>(LX);
-            return f ? finish<BXinv<T>>(f, J, 0, blob, out) : hipErrorInvalidValue;
+            return f ? finish<BXinv<T>>(f, J, blob, out) : hipErrorInvalidValue;
         }
         case BK_EPOLY: {
             BJobs<BEpoly<T>> J{};
@@ -574,7 +573,7 @@ hipError_t prepare_batch(int kind, int nf, const std::vector<const void*>& args,
             switch (nf) {
 #define EP(K) \
     case K:                                                                                            \
-        return finish<BEpoly<T>>((const void*)kb_epoly<T, K>, J, 0, blob, out);
+        return finish<BEpoly<T>>((const void*)kb_epoly<T, K>, J, blob, out);
                 EP(1) EP(2) EP(3) EP(4) EP(5) EP(6)
 #undef EP
             }
@@ -595,7 +594,7 @@ hipError_t prepare_batch(int kind, int nf, const std::vector<const void*>& args,
             switch (nf) {
 #define CB(K) \
     case K:                                                                                            \
-        return finish<BCombine<T>>((const void*)kb_combine<T, K>, J, 0, blob, out);
+        return finish<BCombine<T>>((const void*)kb_combine<T, K>, J, blob, out);
                 CB(0) CB(1) CB(2) CB(3) CB(4) CB(5) CB(6) CB(7) CB(8)
 #undef CB
             }
@@ -614,7 +613,7 @@ hipError_t prepare_batch(int kind, int nf, const std::vector<const void*>& args,
                 a.gy = (int)cg.grid.y;
                 a.jobs = a.gx * a.gy;
             }
-            return finish<BStage<T>>((const void*)kb_stage<T>, J, 0, blob, out);
+            return finish<BStage<T>>((const void*)kb_stage<T>, J, blob, out);
         }
         case BK_STAGE_FINAL: {
             BJobs<BStageFinal<T>> J{};
@@ -632,7 +631,7 @@ hipError_t prepare_batch(int kind, int nf, const std::vector<const void*>& args,
             switch (nf) {
 #define SF(K) \
     case K:                                                                                            \
-        return finish<BStageFinal<T>>((const void*)kb_stage_final<T, K>, J, 0, blob, out);
+        return finish<BStageFinal<T>>((const void*)kb_stage_final<T, K>, J, blob, out);
                 SF(1) SF(2) SF(3) SF(4) SF(5) SF(6) SF(7) SF(8)
 #undef SF
             }
@@ -649,7 +648,7 @@ hipError_t prepare_batch(int kind, int nf, const std::vector<const void*>& args,
             switch (nf) {
 #define FN(K) \
     case K:                                                                                            \
-        return finish<BFinal<T>>((const void*)kb_final<T, K>, J, 0, blob, out);
+        return finish<BFinal<T>>((const void*)kb_final<T, K>, J, blob, out);
                 FN(1) FN(2) FN(3) FN(4) FN(5) FN(6) FN(7) FN(8)
 #undef FN
             }

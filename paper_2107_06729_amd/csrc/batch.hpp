@@ -127,7 +127,6 @@ struct BJobs {
 struct BatchLaunch {
     int kind, nf;
     unsigned grid;   // workgroups: one per job and padding slot
-    size_t lds;      // dynamic LDS per workgroup
     size_t offset;   // of the job table in the table buffer
     const void* fn;  // the kernel (its one argument: the job table)
 };
