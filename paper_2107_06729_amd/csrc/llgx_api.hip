@@ -40,7 +40,9 @@ static int next_pow2(long v) {
 // A captured step depends on everything its launches take by value or by
 // pointer: the state buffer, the history slots, h (Lagrange weights, stage
 // coefficients), the method and order (launch sequence) and the tensor
-// generation (N00 inside the per-cell constants, the folded kernel).
+// generation (N00 inside the per-cell constants, the folded kernel).  A
+// graph of nsteps consecutive steps is keyed by the state its first step
+// starts from (the others follow from it).
 struct GraphKey {
     const void* M;
     int slot0;
@@ -48,7 +50,9 @@ struct GraphKey {
     double h;
     int method, p;
     long gen;
+    int nsteps = 1;
     bool operator<(const GraphKey& o) const {
+        if (nsteps != o.nsteps) return nsteps < o.nsteps;
         if (M != o.M) return M < o.M;
         if (slot0 != o.slot0) return slot0 < o.slot0;
         if (hist_slots != o.hist_slots) return hist_slots < o.hist_slots;
@@ -1076,6 +1080,50 @@ static llgx_status do_step(Ctx* c, const llgx_stepper* s, llgx_step_info* info) 
     return LLGX_OK;
 }
 
+// Fixed steps replayed from graphs capture up to this many consecutive
+// steps in one graph: each graph launch costs the device several µs on its
+// own (measured about 7 µs per launch of a chain of small kernels), which
+// one step's graph would pay once per step.
+constexpr int GRAPH_BLOCK_STEPS = 8;
+
+// the plan of a graph-replayed fixed step from the handle's current state
+static Plan fixed_plan(const Ctx* c, const Tableau* tab, int p, double h) {
+    Plan pl{};
+    pl.tab = tab;
+    pl.p = p;
+    pl.extrap = p >= 0;
+    pl.stage1 = true;
+    pl.slot0 = free_slot(c);
+    pl.want_err = false;
+    pl.in_place = true;
+    pl.h = h;
+    return pl;
+}
+
+// the host-side stepping state a step's commit changes
+struct StepState {
+    std::vector<Ctx::Hist> hist;
+    void* M;
+    void* Mnew;
+    void* F[MAX_F];
+    bool fsal_valid;
+    double t;
+    long long n_acc;
+    explicit StepState(const Ctx* c)
+        : hist(c->hist), M(c->M), Mnew(c->Mnew), fsal_valid(c->fsal_valid), t(c->t), n_acc(c->n_acc) {
+        std::copy(c->F, c->F + MAX_F, F);
+    }
+    void restore(Ctx* c) const {
+        c->hist = hist;
+        c->M = M;
+        c->Mnew = Mnew;
+        std::copy(F, F + MAX_F, c->F);
+        c->fsal_valid = fsal_valid;
+        c->t = t;
+        c->n_acc = n_acc;
+    }
+};
+
 template <typename T>
 static llgx_status do_run_fixed(Ctx* c, const llgx_stepper* s, int64_t nsteps, int use_graph, llgx_step_info* info) {
     if (s && s->adaptive) return c->fail(LLGX_E_ARG, "llgx_run_fixed needs a fixed step (adaptive = 0)");
@@ -1086,60 +1134,71 @@ static llgx_status do_run_fixed(Ctx* c, const llgx_stepper* s, int64_t nsteps, i
         sf.report_dmdt = 0;
         s = &sf;
     }
-    for (int64_t i = 0; i < nsteps; ++i) {
+    int64_t i = 0;
+    while (i < nsteps) {
         const Tableau* tab;
         int p;
         llgx_status st = check_stepper(c, s, &tab, &p);
         if (st) return st;
         const bool steady = !tab->multistep && ((p < 0 && !tab->fsal) || (p >= 0 && (int)c->hist.size() == p) ||
                                                 (p < 0 && tab->fsal && s->renormalize));
-        // the legacy default stream cannot be captured: replay needs a created stream
-        if (!use_graph || !steady || c->stream == nullptr || c->prof) {
-            st = do_step<T>(c, s, info);
-            if (st) return st;
-            continue;
-        }
-        Plan pl{};
-        pl.tab = tab;
-        pl.p = p;
-        pl.extrap = p >= 0;
-        pl.stage1 = true;
-        pl.slot0 = free_slot(c);
-        pl.want_err = false;
-        pl.in_place = true;
-        pl.h = s->h;
-        GraphKey key{c->M, pl.slot0, {}, s->h, s->method, p, c->kernel_gen};
-        for (auto& hh : c->hist) key.hist_slots.push_back(hh.slot);
         // the Lagrange nodes are relative times: graphs are reused only while steps stay uniform
         bool uniform = true;
         for (size_t j = 0; j < c->hist.size(); ++j) {
             const double expect = -(double)(c->hist.size() - j) * s->h;
             if (std::fabs((c->hist[j].t - c->t) - expect) > 1e-9 * s->h) uniform = false;
         }
-        if (!uniform) {
+        // the legacy default stream cannot be captured: replay needs a created stream
+        if (!use_graph || !steady || !uniform || c->stream == nullptr || c->prof) {
             st = do_step<T>(c, s, info);
             if (st) return st;
+            ++i;
             continue;
         }
+        // a steady, uniform step is followed by steady, uniform steps: the
+        // next `nb` steps are one graph
+        const int nb = nsteps - i >= GRAPH_BLOCK_STEPS ? GRAPH_BLOCK_STEPS : 1;
+        GraphKey key{c->M, free_slot(c), {}, s->h, s->method, p, c->kernel_gen, nb};
+        for (auto& hh : c->hist) key.hist_slots.push_back(hh.slot);
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
+            // capture the steps' launches (Eq. (3)-(6) attempts, renormalisation)
+            // on a copy of the stepping state, restored afterwards
+            const StepState saved(c);
             hipGraph_t g;
             HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-            st = enqueue_attempt<T>(c, pl);
+            hipError_t e = hipSuccess;
+            for (int k = 0; k < nb && st == LLGX_OK && e == hipSuccess; ++k) {
+                const Plan pl = fixed_plan(c, tab, p, s->h);
+                st = enqueue_attempt<T>(c, pl);
+                if (st == LLGX_OK) st = commit<T>(c, pl, s->h);
+                if (st == LLGX_OK && s->renormalize) e = launch_renorm<T>(c->stream, c->ncell, c->nb, (T*)c->M, c->p.Ms);
+            }
             hipError_t e2 = hipStreamEndCapture(c->stream, &g);
-            if (st) return st;
-            if (e2 != hipSuccess) return c->fail(LLGX_E_HIP, "graph capture failed: %s", hipGetErrorString(e2));
+            saved.restore(c);
+            if (st) {
+                if (e2 == hipSuccess) (void)hipGraphDestroy(g);
+                return st;
+            }
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (e2 == hipSuccess) (void)hipGraphDestroy(g);
+                return c->fail(LLGX_E_HIP, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+            }
             hipGraphExec_t ge;
-            HIPCHK(c, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+            e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return c->fail(LLGX_E_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
             it = c->graphs.emplace(key, ge).first;
         }
         HIPCHK(c, hipGraphLaunch(it->second, c->stream));
-        c->n_exact += 1 + (pl.extrap ? 0 : tab->S - 1);
-        c->n_extrap += pl.extrap ? tab->S - 1 : 0;
-        st = commit<T>(c, pl, s->h);
-        if (st) return st;
-        if (s->renormalize) HIPCHK(c, launch_renorm<T>(c->stream, c->ncell, c->nb, (T*)c->M, c->p.Ms));
+        // the host side of the replayed steps
+        for (int k = 0; k < nb; ++k) {
+            const Plan pl = fixed_plan(c, tab, p, s->h);
+            c->n_exact += 1 + (pl.extrap ? 0 : tab->S - 1);
+            c->n_extrap += pl.extrap ? tab->S - 1 : 0;
+            st = commit<T>(c, pl, s->h);
+            if (st) return st;
+        }
         c->h_next = s->h;
         if (info) {
             info->t = c->t;
@@ -1147,11 +1206,12 @@ static llgx_status do_run_fixed(Ctx* c, const llgx_stepper* s, int64_t nsteps, i
             info->h_next = s->h;
             info->err = -1.0;
             info->rejected = 0;
-            info->exact_evals = 1 + (pl.extrap ? 0 : tab->S - 1);
-            info->extrap_evals = pl.extrap ? tab->S - 1 : 0;
+            info->exact_evals = 1 + (p >= 0 ? 0 : tab->S - 1);
+            info->extrap_evals = p >= 0 ? tab->S - 1 : 0;
             info->forced = 0;
             info->max_dmdt = -1.0;
         }
+        i += nb;
     }
     return LLGX_OK;
 }

@@ -172,12 +172,16 @@ def test_film_256x64x1_rk4_200_steps_fp64():
     assert np.max(np.abs(got2 - ora.M)) <= 1e-8 * p["Ms"]
 
 
-@pytest.mark.parametrize("extrap", [None, 4], ids=["full", "p4"])
-def test_graph_replay_matches_eager(extrap):
+@pytest.mark.parametrize("method,extrap,renorm", [("RK4", None, False), ("RK4", 4, False), ("RKDP54", None, True),
+                                                  ("RKF56", 5, False), ("HEUN", 2, True)],
+                         ids=["rk4-full", "rk4-p4", "rkdp54-full-renorm", "rkf56-p5", "heun-p2-renorm"])
+def test_graph_replay_matches_eager(method, extrap, renorm):
     """HIP-graph replay of fixed steps is bitwise identical to eager stepping,
-    over enough steps to replay every captured phase several times."""
+    over enough steps to replay every captured phase several times: runs of
+    5, 19 and 13 steps, so graphs of one step and of several consecutive
+    steps are captured from different history phases and replayed."""
     import torch
-    log(f"graph replay {extrap}")
+    log(f"graph replay {method} {extrap} renorm={renorm}")
     p = film((32, 24, 4), (5e-9, 5e-9, 5e-9))
     M0 = workloads.random_m(p["n"], p["Ms"], 34)
     stream = torch.cuda.Stream()
@@ -185,14 +189,16 @@ def test_graph_replay_matches_eager(extrap):
     b = sim(p, "f32", stream=stream)
     a.set_m(to_dev(M0, "f32"))
     b.set_m(to_dev(M0, "f32"))
-    st = _stepper("RK4", extrap, 2e-14)
+    st = _stepper(method, extrap, 2e-14, renormalize=renorm)
     for _ in range(37):
         a.step(st)
-    b.run_fixed(st, 37, use_graph=True)
+    for n in (5, 19, 13):
+        b.run_fixed(st, n, use_graph=True)
     torch.cuda.synchronize()
     ma, mb = to_host(a.get_m()), to_host(b.get_m())
     assert np.array_equal(ma, mb)
     assert a.counters() == b.counters()
+    assert a.time() == b.time()
 
 
 def test_renormalize_keeps_length():
