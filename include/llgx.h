@@ -205,8 +205,10 @@ llgx_status llgx_demag_noalloc(llgx_handle h, const void* M_dev, void* H_dev);
 llgx_status llgx_step(llgx_handle h, const llgx_stepper* s, llgx_step_info* info);
 
 /* nsteps fixed steps (s->adaptive must be 0) with no host synchronisation;
- * with use_graph the steady-state step is captured once per history phase
- * into HIP graphs and replayed.  info may be NULL; its max_dmdt is -1. */
+ * with use_graph the steady-state steps are captured into HIP graphs (per
+ * history phase; 8 consecutive steps per graph while at least 8 remain,
+ * else one) and replayed, bitwise the same as eager steps.  info (the last
+ * step's) may be NULL; its max_dmdt is -1. */
 llgx_status llgx_run_fixed(llgx_handle h, const llgx_stepper* s, int64_t nsteps, int32_t use_graph,
                            llgx_step_info* info);
 
