@@ -17,7 +17,10 @@ enumerated at the first two and last two values of every grid coordinate
 depend only on the ragged last kx tile and on the ky rows q = 0 and Py/2,
 which are all among those values).  Where a kernel permutes its workgroups
 (xcd_run, yslab: bijections, checked below) the coordinates enumerated are
-those the workgroup ends up with (plane, y group).  No GPU is used.
+those the workgroup ends up with (plane, y group).  The job tables of the
+batched launches (batch.hip: the start offsets and the search every batched
+kernel starts with) are restated too: every job runs exactly once.  No GPU
+is used.
 """
 
 import itertools
@@ -607,6 +610,47 @@ def test_grid_maps_are_bijections():
         for planes in (1, 2, 3, 7, 16):
             seen = sorted(yslab(p, gy, planes) for p in range(gy * planes))
             assert seen == sorted((pl_, yg) for pl_ in range(planes) for yg in range(gy))
+
+
+# ---- job tables of the batched launches (batch.hip finish, BATCH_JOB) -----
+def job_table(jobs):
+    """Start offsets and grid of one job-table launch over groups with the
+    given job counts (each group's first job on a multiple of 8)."""
+    start, at = [], 0
+    for n in jobs:
+        start.append(at)
+        at += (n + 7) // 8 * 8
+    return start + [at], max(1, at)
+
+
+def job_of(b, jobs, start):
+    """The (group, job) workgroup b runs, or None when it exits (a padding
+    slot): the scalar search of the start offsets that every batched kernel
+    begins with."""
+    if len(jobs) == 0:
+        return None
+    g = 0
+    while g + 1 < len(jobs) and b >= start[g + 1]:
+        g += 1
+    loc = b - start[g]
+    return None if loc >= jobs[g] else (g, loc)
+
+
+def test_job_tables_run_every_job_once():
+    """Every (group, job) of a batched launch is run by exactly one
+    workgroup, padding slots exit, and each group starts on a multiple of 8
+    (the XCD of a job is its index in the group modulo 8), for up to 4
+    groups of 0 to 1000 jobs, including groups without jobs."""
+    rng = np.random.default_rng(7)
+    cases = [[1], [8], [9], [0, 5], [5, 0], [0, 0, 3], [7, 1, 16, 3]]
+    cases += [list(rng.integers(0, 1000, size=rng.integers(1, 5))) for _ in range(200)]
+    for jobs in cases:
+        start, grid = job_table(jobs)
+        assert all(st % 8 == 0 for st in start)
+        ran = [job_of(b, jobs, start) for b in range(grid)]
+        got = sorted(r for r in ran if r is not None)
+        assert got == [(g, j) for g, n in enumerate(jobs) for j in range(n)], jobs
+        assert grid - len(got) == sum((n + 7) // 8 * 8 - n for n in jobs) + (1 if sum(jobs) == 0 else 0)
 
 
 def test_the_model_catches_a_planted_overrun():
