@@ -15,6 +15,8 @@ N, CELL = (40, 36, 6), (5e-9, 5e-9, 3e-9)
 # odd row length (no paired loads), 819 row groups in the x passes with a
 # ragged last one, and z length 128
 N_MANY = (7, 97, 45)
+# z length 1024
+N_LONGZ = (2, 3, 512)
 
 
 def nvar():
@@ -24,7 +26,8 @@ def nvar():
 
 @pytest.mark.parametrize("prec,spectral,n", [("f32", "native", N), ("f64", "native", N), ("f32", "bf16", N),
                                              ("f32", "f16", N), ("f32", "native", N_MANY),
-                                             ("f64", "native", N_MANY)])
+                                             ("f64", "native", N_MANY), ("f32", "bf16", N_MANY),
+                                             ("f32", "native", N_LONGZ), ("f64", "native", N_LONGZ)])
 def test_variants_bitwise(prec, spectral, n):
     import paper_2107_06729_amd as llgx
     log(f"variants {prec} {spectral} {n}")
